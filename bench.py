@@ -1,0 +1,149 @@
+"""Throughput of the all-pairs Oseen dumbbell step on one MI355X.
+
+A step is one RK4 step of the whole hot path: four stages of spring forces,
+the O(N^2) Oseen pair sum and the RK4 update, for S = 2048 dumbbells
+(N = 4096 spheres) in a cube of side 240 (seed 0, a = eta = k = 1, ell = 4,
+lambda = 1, T = 100, dt = 0.01), FP32 pair arithmetic with compensated
+accumulation and FP64 state. The inputs are resident on the device before
+the timed region starts. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+FLOPS_PER_PAIR = 28           # algorithmic flops of one ordered pair term
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(sim, steps, warmup):
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    sim.step(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / 1e3, wall
+
+
+def cpu_baseline(sus, budget_s):
+    """The oracle on the host cores: RK4 steps of the same suspension."""
+    from oracle import adref
+    adref.build(force=False)
+    p = sus.params
+    N = sus.N
+    t = time.perf_counter()
+    X, _, _, _ = adref.run(p, sus.X, sus.phi, 1)
+    one = time.perf_counter() - t
+    n = max(1, int(budget_s / max(one, 1e-6)) - 1)
+    t = time.perf_counter()
+    adref.run(p, X, sus.phi, n, step0=1)
+    dt = time.perf_counter() - t
+    pairs = 4.0 * N * (N - 1) * n
+    return {"value": pairs / dt, "unit": "pair interactions/s", "cores": adref.max_threads(),
+            "kind": "oracle",
+            "sample": f"{n} RK4 steps of the N={N} suspension ({dt:.1f} s), FP64, OpenMP over target spheres",
+            "sphere_steps_per_s": N * n / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--fp64-steps", type=int, default=200)
+    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_1004_1932_amd as P
+    from workload import make_preset
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    sus = make_preset("n4096")
+    N, S = sus.N, sus.S
+    pairs_per_step = 4.0 * N * (N - 1)
+
+    # FP32-compensated path, graph-replayed steps
+    sim = P.Simulator(sus.params, [S], precision="fp32c", graph=not args.no_graph)
+    sim.set_state(sus.X, sus.phi)
+    log(f"fp32c launch {sim.launch}")
+    secs, wall = time_steps(sim, args.steps, args.warmup)
+    assert sim.check() == 0
+    ms_per_step = secs / args.steps * 1e3
+    value = pairs_per_step * args.steps / secs
+    log(f"fp32c: {ms_per_step:.4f} ms/step, {value:.4e} pairs/s (wall {wall:.3f} s)")
+
+    # pair-kernel duration under HIP events on the launch stream
+    P.ad_profile_pairs(sim.ctx, True)
+    sim.step(args.profile_steps)
+    kern_ms, launches = P.ad_profile_read(sim.ctx)
+    P.ad_profile_pairs(sim.ctx, False)
+    avg_ms = kern_ms / launches
+    kernel_pairs = N * (N - 2)  # the dumbbell partner is summed in FP64 outside the kernel
+    achieved = FLOPS_PER_PAIR * kernel_pairs / (avg_ms * 1e-3) / 1e12
+    log(f"pair kernel: {avg_ms * 1e3:.2f} us avg over {launches} launches, {achieved:.2f} TFLOP/s")
+
+    # plain FP64 form (tiled) timed beside it
+    sim64 = P.Simulator(sus.params, [S], precision="fp64_tiled", graph=not args.no_graph)
+    sim64.set_state(sus.X, sus.phi)
+    secs64, _ = time_steps(sim64, args.fp64_steps, max(1, args.fp64_steps // 10))
+    v64 = pairs_per_step * args.fp64_steps / secs64
+    log(f"fp64_tiled: {secs64 / args.fp64_steps * 1e3:.4f} ms/step, {v64:.4e} pairs/s")
+
+    out = {
+        "metric": "Oseen pair interactions/s and sphere-steps/s at N=4096, FP32-comp vs FP64",
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "suspension of S=2048 active dumbbells (N=4096 spheres), cube side 240, "
+                               "RK4 dt=0.01, Oseen, FP32-compensated pair sum, FP64 state",
+                   "N": N, "S": S, "launch": sim.launch, "graph": not args.no_graph},
+        "sphere_steps_per_s": N * args.steps / secs,
+        "fp64_tiled": {"value": v64, "unit": "pair interactions/s", "ms_per_step": secs64 / args.fp64_steps * 1e3,
+                       "steps": args.fp64_steps},
+        "speedup_vs_fp64": value / v64,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_pairs_f32c", "avg_launch_us": avg_ms * 1e3,
+                     "flops_per_launch": FLOPS_PER_PAIR * kernel_pairs},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(sus, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * ad.h -- C ABI of the MI355X (gfx950) library for the all-pairs hydrodynamic
+ * step of active spring dumbbell suspensions.
+ *
+ * Model (Putz, Dunkel, Yeomans, "CUDA simulations of active dumbbell
+ * suspensions"):
+ *   dX_i/dt = u_i = F_i/(6 pi eta a)
+ *                 + 1/(8 pi eta) sum_{j != i} [F_j/r + r (r.F_j)/r^3],
+ *   r = X_i - X_j                       (Sec. II, Eq. e:langevin at zero
+ *                                        temperature; Eq. e:Mazur, Oseen part)
+ *   F = -grad U, U = sum_s k/2 (d_s - L_s(t))^2,
+ *   L_s(t) = ell + lambda sin(omega t + phi_s), omega = 2 pi / T
+ *                                       (Sec. II, Eq. e:swimmer_potential)
+ * Dumbbell s owns spheres 2s and 2s+1. Positions advance with classical RK4
+ * (default) or the paper's Heun predictor-corrector (Sec. V).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an int status: AD_OK (0) or a negative AD_E* code.
+ *     Nothing throws across the ABI. ad_last_error() gives the message of the
+ *     last failure on that context.
+ *   - Array pointers marked "device" are caller-owned device allocations;
+ *     pointers marked "host" are caller-owned host memory. The library never
+ *     frees caller memory and keeps no pointer to it after the call returns,
+ *     except the workspace bound with ad_bind_workspace.
+ *   - Positions, forces and velocities are row-major [N_total][3] float64
+ *     (a contiguous (N, 3) tensor). Systems of an ensemble are concatenated
+ *     in order; system b holds spheres [2*sum_{c<b} S_c, 2*sum_{c<=b} S_c).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work on it and return without waiting, unless stated.
+ *   - The context owns host-side objects only; all device memory it uses
+ *     lives in the caller's workspace.
+ *   - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef AD_H
+#define AD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define AD_OK 0
+#define AD_EINVAL (-1)     /* bad argument: null pointer, size, parameter */
+#define AD_ENOMEM (-2)     /* workspace too small or host allocation failed */
+#define AD_EDEVICE (-3)    /* HIP runtime error */
+#define AD_ESTATE (-4)     /* call out of order (no workspace or no state) */
+#define AD_ENONFINITE (-5) /* non-finite velocity or coincident spheres */
+
+/* arithmetic of the pair sum (ad_params.precision) */
+#define AD_FP64 0      /* FP64, ascending j, no FMA: bitwise equal to a plain
+                          sequential FP64 evaluation of the sum */
+#define AD_FP64_TILED 1 /* FP64 pair math, j split across work-groups */
+#define AD_FP32C 2     /* FP32 pair math on hi/lo-split positions with
+                          compensated (TwoSum) accumulation over j; self and
+                          dumbbell-partner terms, state and RK4 in FP64 */
+
+/* time integrator (ad_params.integrator) */
+#define AD_RK4 0
+#define AD_HEUN 1 /* Sec. V: x~ = x + dt u(x,t); x' = x + dt/2 (u(x,t) + u(x~,t+dt)) */
+
+/* pair tensor (ad_params.tensor) */
+#define AD_OSEEN 0
+
+typedef struct ad_params {
+    double a;        /* sphere radius, > 0 */
+    double eta;      /* viscosity, > 0 */
+    double k;        /* spring constant k_0 */
+    double ell;      /* mean dumbbell length */
+    double lambda;   /* stroke amplitude (0: passive dumbbells) */
+    double T;        /* stroke period, > 0 */
+    double dt;       /* time step, > 0 */
+    double steric_k; /* steric repulsion strength; 0 disables (not in the paper) */
+    double steric_r; /* steric contact distance, force steric_k (steric_r - r) for r < steric_r */
+    int32_t precision;  /* AD_FP64 | AD_FP64_TILED | AD_FP32C */
+    int32_t integrator; /* AD_RK4 | AD_HEUN */
+    int32_t tensor;     /* AD_OSEEN */
+    int32_t reserved;   /* must be 0 */
+} ad_params;
+
+/* Launch shape of the pair kernel: i-spheres per lane and j-chunk length.
+ * Zero fields mean "library default for this size". */
+typedef struct ad_launch {
+    int32_t ipl;      /* i-spheres per lane: 1, 2 or 4 (FP64 modes use at most 2) */
+    int32_t jchunk;   /* j-range of one work-group, >= 64 (AD_FP64: always the whole system) */
+    int32_t wg;       /* work-group size: 64 or 256 */
+    int32_t reserved; /* must be 0 */
+} ad_launch;
+
+typedef struct ad_ctx ad_ctx;
+
+/* Create a context for nsys independent systems, system b holding
+ * S_per_sys[b] >= 1 dumbbells (host array). Validates the parameters
+ * (a, eta, T, dt > 0; finite values; known enums). *out receives the
+ * context. No device memory is allocated. */
+int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx** out);
+
+/* Destroy a context (host objects and captured graphs only). NULL is a no-op. */
+int ad_destroy(ad_ctx* ctx);
+
+/* Bytes of device workspace the context needs with its current launch shape. */
+int ad_workspace_size(const ad_ctx* ctx, uint64_t* bytes);
+
+/* Bind a caller-owned device buffer of at least ad_workspace_size() bytes,
+ * 256-byte aligned. The caller keeps it alive until ad_destroy or the next
+ * bind. Rebinding drops the state (call ad_set_state again). */
+int ad_bind_workspace(ad_ctx* ctx, void* dev_ptr, uint64_t bytes);
+
+/* Choose the pair-kernel launch shape (autotuning). Fails with AD_ENOMEM if
+ * the bound workspace is too small for it; the state is kept. */
+int ad_set_launch(ad_ctx* ctx, const ad_launch* launch);
+int ad_get_launch(const ad_ctx* ctx, ad_launch* launch);
+
+/* Load a state: X (device, [N_total][3] f64), phases phi (HOST, [S_total]
+ * f64), and the clock: step n starts at time t0 + n*dt, the state is at step
+ * step0. Clears the non-finite flag. */
+int ad_set_state(ad_ctx* ctx, const double* X, const double* phi, double t0, int64_t step0,
+                 void* stream);
+
+/* Checkpoint: copy the positions to X (device, [N_total][3] f64) and return
+ * the clock (t0, current step) on the host. Synchronises the stream. */
+int ad_get_state(ad_ctx* ctx, double* X, double* t0, int64_t* step, void* stream);
+
+/* F = -grad U at positions X (device [N_total][3]) and time t, plus steric
+ * forces when enabled (Eq. e:swimmer_potential). Uses the phases of the
+ * loaded state. F: device [N_total][3]. */
+int ad_forces(ad_ctx* ctx, const double* X, double t, double* F, void* stream);
+
+/* u = M(X) F for an arbitrary force F (Eq. e:Mazur, Oseen part, self term
+ * included), per system. X, F, u: device [N_total][3]. Does not change the
+ * loaded state. */
+int ad_mobility_apply(ad_ctx* ctx, const double* X, const double* F, double* u, void* stream);
+
+/* Advance the loaded state by nsteps >= 0 steps. Asynchronous. */
+int ad_step(ad_ctx* ctx, int64_t nsteps, void* stream);
+
+/* ad_step plus records: after every record_every-th step, the dumbbell
+ * centres (X_2s + X_2s+1)/2 go to centres[r] (device [nrec][S_total][3]) and
+ * each system's mean sphere position to com[r] (device [nrec][nsys][3]),
+ * nrec = nsteps / record_every. Either pointer may be NULL. Synchronises the
+ * stream at the end and returns AD_ENONFINITE if a non-finite velocity or a
+ * coincident sphere pair was met since ad_set_state. */
+int ad_run(ad_ctx* ctx, int64_t nsteps, int32_t record_every, double* centres, double* com,
+           void* stream);
+
+/* Synchronise the stream and report the non-finite flag (AD_OK or AD_ENONFINITE). */
+int ad_check(ad_ctx* ctx, void* stream);
+
+/* Capture one step into a HIP graph and replay it for ad_step/ad_run
+ * (enable != 0), or launch kernels directly (enable == 0, the default). */
+int ad_use_graph(ad_ctx* ctx, int32_t enable);
+
+/* Measurement support. With enable != 0, ad_step/ad_run launch kernels
+ * directly (no graph) and bracket every launch of the pair-sum kernel with
+ * HIP events on the call's stream; ad_profile_read synchronises and returns
+ * the summed duration (ms) and number of those launches since enabling. */
+int ad_profile_pairs(ad_ctx* ctx, int32_t enable);
+int ad_profile_read(ad_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Message of the last failure on ctx (never NULL; "" if none). With ctx ==
+ * NULL: the last failure of ad_create on the calling thread. */
+const char* ad_last_error(const ad_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AD_H */

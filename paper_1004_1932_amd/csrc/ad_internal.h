@@ -1,0 +1,87 @@
+/*
+ * Internal types shared by the kernels (ad_kernels.hip) and the host runtime
+ * (ad_runtime.hip). Not part of the ABI.
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ad {
+
+/* One work-group's share of a pair sum: target spheres [i0, i0+ni) against
+ * source spheres [j0, j0+nj), both inside system `sys` whose spheres are
+ * [ioff, ioff+Nb). `c` numbers the j-chunk inside the system; the partial
+ * sum lands in partial slot c of the system. */
+struct Item {
+    int32_t sys, i0, ni, j0, nj, c, Nb, ioff;
+};
+
+/* Device control block at the start of the workspace. */
+struct Ctl {
+    long long step; /* index of the step in flight (bumped by stage 0) */
+    int flag;       /* non-zero once a non-finite velocity was met */
+    int pad[13];
+};
+
+/* Constants of the model, precomputed on the host. */
+struct Coef {
+    double cs;   /* 1/(6 pi eta a) */
+    double co;   /* 1/(8 pi eta) */
+    double k;    /* spring constant */
+    double ell;  /* mean length */
+    double lam;  /* stroke amplitude */
+    double dt;   /* step */
+    double h2;   /* 0.5*dt */
+    double dt6;  /* dt/6.0 */
+    double ks;   /* steric strength (0: off) */
+    double rc;   /* steric contact distance */
+};
+
+/* Device views into the workspace. */
+struct Dev {
+    Ctl* ctl;
+    double* X;          /* [3][Ntot] state, SoA */
+    double* R;          /* [3][Ntot] RK accumulator */
+    double* U0;         /* [3][Ntot] self (+partner) velocity of the stage */
+    double* Y;          /* [3][Ntot] stage positions (steric path only) */
+    double* Fs;         /* [3][Ntot] stage forces (steric path only) */
+    const double2* phitrig; /* [Stot] (sin phi, cos phi) */
+    const int* dsys;    /* [Stot] system of each dumbbell */
+    const int* sys_off; /* [nsys+1] sphere offsets */
+    const int* sys_P;   /* [nsys] number of j-chunks (partial slots) */
+    const long long* sys_pbase; /* [nsys] first partial of the system */
+    const Item* items;  /* [nitems] */
+    float4* pA;         /* FP32C pack: (hi.x, hi.y, hi.z, F.x) */
+    float4* pB;         /* FP32C pack: (lo.x, lo.y, lo.z, F.y) */
+    float* pC;          /* FP32C pack: F.z */
+    double2* pD;        /* FP64 pack: 3 double2 per sphere (x,y)(z,Fx)(Fy,Fz) */
+    double* part;       /* partial sums */
+    const double* tab;  /* [ring][8] (sin, cos) of omega*t per epilogue stage */
+    int ring;           /* entries in tab */
+    int Ntot, Stot, nsys, nitems;
+};
+
+enum { PREC_FP64 = 0, PREC_FP64_TILED = 1, PREC_FP32C = 2 };
+
+/* kernel launchers (ad_kernels.hip) */
+hipError_t launch_set_step(const Dev& d, long long value, hipStream_t s);
+hipError_t launch_clear_flag(const Dev& d, hipStream_t s);
+hipError_t launch_state_in(const Dev& d, const double* Xaos, hipStream_t s);
+hipError_t launch_state_out(const Dev& d, double* Xaos, hipStream_t s);
+/* pack from the state X at forces time (st, ct); prec selects the pack */
+hipError_t launch_pack_state(const Dev& d, const Coef& c, int prec, double st, double ct, hipStream_t s);
+/* pack from caller positions and forces (AoS) */
+hipError_t launch_pack_apply(const Dev& d, const Coef& c, int prec, const double* Xaos,
+                             const double* Faos, hipStream_t s);
+/* forces at caller positions (AoS) and time (st, ct), spring + steric */
+hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xaos, double st, double ct,
+                         double* Faos, hipStream_t s);
+hipError_t launch_pairs(const Dev& d, int prec, int wg, int ipl, int bump, hipStream_t s);
+/* epilogue of a step stage (integrator, stage) or of a mobility apply (u != NULL) */
+hipError_t launch_epilogue(const Dev& d, const Coef& c, int prec, int integrator, int stage,
+                           int pack_next, double* u_aos, hipStream_t s);
+/* steric forces at stage positions Y, then the pack (steric path) */
+hipError_t launch_steric_pack(const Dev& d, const Coef& c, int prec, int stage, hipStream_t s);
+hipError_t launch_record(const Dev& d, double* centres, double* com, hipStream_t s);
+
+}  // namespace ad

@@ -1,0 +1,673 @@
+/*
+ * HIP kernels for gfx950 (CDNA4): the all-pairs Oseen mobility step of
+ * active spring dumbbell suspensions (Putz, Dunkel, Yeomans, Sec. II and
+ * Sec. V).
+ *
+ * One RK4 stage is two launches:
+ *   k_pairs_*   the O(N^2) pair sum over a work list of (i-block, j-chunk)
+ *               items; each item stages its j-tile through LDS and every
+ *               lane holds IPL consecutive target spheres in registers.
+ *   k_epilogue  one thread per dumbbell: sums the j-chunk partials in a
+ *               fixed order, forms the stage velocity k = u0 + kappa*acc,
+ *               updates the RK accumulator and the state, and evaluates the
+ *               spring forces of the next stage (Eq. e:swimmer_potential)
+ *               straight into the pack the next pair kernel reads.
+ *
+ * All FP64 arithmetic is written in a fixed order and built without FMA
+ * contraction; FP32 FMAs are spelled out with __builtin_fmaf.
+ */
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "ad_internal.h"
+
+namespace ad {
+
+/* ------------------------------------------------------------ helpers */
+
+__device__ __forceinline__ void spring_forces(const Coef& c, const double y0[3], const double y1[3],
+                                              double sphi, double cphi, double st, double ct,
+                                              double f0[3], double f1[3]) {
+    /* F_{2s+1} = -k (d - L) n/d, F_{2s} = -F_{2s+1}, n = y1 - y0,
+     * L = ell + lam sin(omega t + phi) by the addition theorem. */
+    double nx = y1[0] - y0[0], ny = y1[1] - y0[1], nz = y1[2] - y0[2];
+    double d = sqrt((nx * nx + ny * ny) + nz * nz);
+    double L = c.ell + c.lam * (st * cphi + ct * sphi);
+    double cc = (-c.k * (d - L)) / d;
+    f1[0] = cc * nx;
+    f1[1] = cc * ny;
+    f1[2] = cc * nz;
+    f0[0] = -f1[0];
+    f0[1] = -f1[1];
+    f0[2] = -f1[2];
+}
+
+/* Oseen term of one source sphere in FP64, without the 1/(8 pi eta) factor:
+ * [F/r + r (r.F)/r^3]. */
+__device__ __forceinline__ void oseen_term64(const double r[3], const double F[3], double out[3]) {
+    double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+    double ir = 1.0 / sqrt(r2);
+    double fr = (r[0] * F[0] + r[1] * F[1]) + r[2] * F[2];
+    double t = fr / r2;
+    out[0] = ir * (F[0] + t * r[0]);
+    out[1] = ir * (F[1] + t * r[1]);
+    out[2] = ir * (F[2] + t * r[2]);
+}
+
+/* Steric sum for sphere i over the spheres [j0, j1) of its system: for
+ * 0 < r < rc, ks (rc - r) (X_i - X_j)/r, ascending j. Positions are read
+ * through `get`. Returns non-zero if a coincident sphere was met. */
+template <class Get>
+__device__ int steric_sum(const Coef& c, int i, int j0, int j1, Get get, double acc[3], int* any) {
+    double xi[3];
+    get(i, xi);
+    double rc2 = c.rc * c.rc;
+    int bad = 0;
+    acc[0] = acc[1] = acc[2] = 0.0;
+    *any = 0;
+    for (int j = j0; j < j1; ++j) {
+        if (j == i) continue;
+        double xj[3];
+        get(j, xj);
+        double rx = xi[0] - xj[0], ry = xi[1] - xj[1], rz = xi[2] - xj[2];
+        double r2 = (rx * rx + ry * ry) + rz * rz;
+        if (r2 >= rc2) continue;
+        if (r2 == 0.0) {
+            bad = 1;
+            continue;
+        }
+        double r = sqrt(r2);
+        double cc = c.ks * (c.rc - r) / r;
+        acc[0] = acc[0] + cc * rx;
+        acc[1] = acc[1] + cc * ry;
+        acc[2] = acc[2] + cc * rz;
+        *any = 1;
+    }
+    return bad;
+}
+
+__device__ __forceinline__ void split_f32(double v, float& hi, float& lo) {
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+/* Write the pair-kernel pack and the self (+partner) velocity u0 of the two
+ * spheres of one dumbbell at positions y0, y1 with forces f0, f1. */
+__device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const double y0[3],
+                           const double y1[3], const double f0[3], const double f1[3]) {
+    const int N = d.Ntot;
+    const int i1 = i0 + 1;
+    if (prec == PREC_FP32C) {
+        /* self term and dumbbell-partner term in FP64; the pair kernel skips
+         * the partner */
+        double r[3] = {y0[0] - y1[0], y0[1] - y1[1], y0[2] - y1[2]};
+        double t0[3], t1[3];
+        oseen_term64(r, f1, t0);
+        double rm[3] = {y1[0] - y0[0], y1[1] - y0[1], y1[2] - y0[2]};
+        oseen_term64(rm, f0, t1);
+        for (int a = 0; a < 3; ++a) {
+            d.U0[a * N + i0] = c.cs * f0[a] + c.co * t0[a];
+            d.U0[a * N + i1] = c.cs * f1[a] + c.co * t1[a];
+        }
+        float h[3], l[3];
+        for (int a = 0; a < 3; ++a) split_f32(y0[a], h[a], l[a]);
+        d.pA[i0] = make_float4(h[0], h[1], h[2], (float)f0[0]);
+        d.pB[i0] = make_float4(l[0], l[1], l[2], (float)f0[1]);
+        d.pC[i0] = (float)f0[2];
+        for (int a = 0; a < 3; ++a) split_f32(y1[a], h[a], l[a]);
+        d.pA[i1] = make_float4(h[0], h[1], h[2], (float)f1[0]);
+        d.pB[i1] = make_float4(l[0], l[1], l[2], (float)f1[1]);
+        d.pC[i1] = (float)f1[2];
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            d.U0[a * N + i0] = c.cs * f0[a];
+            d.U0[a * N + i1] = c.cs * f1[a];
+        }
+        d.pD[3 * i0 + 0] = make_double2(y0[0], y0[1]);
+        d.pD[3 * i0 + 1] = make_double2(y0[2], f0[0]);
+        d.pD[3 * i0 + 2] = make_double2(f0[1], f0[2]);
+        d.pD[3 * i1 + 0] = make_double2(y1[0], y1[1]);
+        d.pD[3 * i1 + 1] = make_double2(y1[2], f1[0]);
+        d.pD[3 * i1 + 2] = make_double2(f1[1], f1[2]);
+    }
+}
+
+/* ------------------------------------------------------------ small kernels */
+
+__global__ void k_set_step(Ctl* ctl, long long v) { ctl->step = v; }
+__global__ void k_clear_flag(Ctl* ctl) { ctl->flag = 0; }
+
+__global__ void k_state_in(Dev d, const double* __restrict__ Xa) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.Ntot) return;
+    for (int a = 0; a < 3; ++a) d.X[a * d.Ntot + i] = Xa[3 * i + a];
+}
+
+__global__ void k_state_out(Dev d, double* __restrict__ Xa) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.Ntot) return;
+    for (int a = 0; a < 3; ++a) Xa[3 * i + a] = d.X[a * d.Ntot + i];
+}
+
+/* pack from the state at time (st, ct); spring (+ steric) forces */
+__global__ void k_pack_state(Dev d, Coef c, int prec, double st, double ct) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.Stot) return;
+    const int N = d.Ntot;
+    const int i0 = 2 * s;
+    double y0[3], y1[3], f0[3], f1[3];
+    for (int a = 0; a < 3; ++a) {
+        y0[a] = d.X[a * N + i0];
+        y1[a] = d.X[a * N + i0 + 1];
+    }
+    double2 tp = d.phitrig[s];
+    spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+    if (c.ks != 0.0) {
+        int b = d.dsys[s];
+        int j0 = d.sys_off[b], j1 = d.sys_off[b + 1];
+        auto get = [&](int j, double x[3]) {
+            x[0] = d.X[j];
+            x[1] = d.X[N + j];
+            x[2] = d.X[2 * N + j];
+        };
+        double acc[3];
+        int any, bad = 0;
+        bad |= steric_sum(c, i0, j0, j1, get, acc, &any);
+        if (any)
+            for (int a = 0; a < 3; ++a) f0[a] = f0[a] + acc[a];
+        bad |= steric_sum(c, i0 + 1, j0, j1, get, acc, &any);
+        if (any)
+            for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
+        if (bad) d.ctl->flag = 1;
+    }
+    store_pack(d, c, prec, i0, y0, y1, f0, f1);
+}
+
+/* pack from caller positions and forces (row-major [N][3]) */
+__global__ void k_pack_apply(Dev d, Coef c, int prec, const double* __restrict__ Xa,
+                             const double* __restrict__ Fa) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.Stot) return;
+    const int i0 = 2 * s;
+    double y0[3], y1[3], f0[3], f1[3];
+    for (int a = 0; a < 3; ++a) {
+        y0[a] = Xa[3 * i0 + a];
+        y1[a] = Xa[3 * i0 + 3 + a];
+        f0[a] = Fa[3 * i0 + a];
+        f1[a] = Fa[3 * i0 + 3 + a];
+    }
+    store_pack(d, c, prec, i0, y0, y1, f0, f1);
+}
+
+/* spring + steric forces at caller positions, row-major output */
+__global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st, double ct,
+                         double* __restrict__ Fa) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.Stot) return;
+    const int i0 = 2 * s;
+    double y0[3], y1[3], f0[3], f1[3];
+    for (int a = 0; a < 3; ++a) {
+        y0[a] = Xa[3 * i0 + a];
+        y1[a] = Xa[3 * i0 + 3 + a];
+    }
+    double2 tp = d.phitrig[s];
+    spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+    if (c.ks != 0.0) {
+        int b = d.dsys[s];
+        int j0 = d.sys_off[b], j1 = d.sys_off[b + 1];
+        auto get = [&](int j, double x[3]) {
+            x[0] = Xa[3 * j];
+            x[1] = Xa[3 * j + 1];
+            x[2] = Xa[3 * j + 2];
+        };
+        double acc[3];
+        int any, bad = 0;
+        bad |= steric_sum(c, i0, j0, j1, get, acc, &any);
+        if (any)
+            for (int a = 0; a < 3; ++a) f0[a] = f0[a] + acc[a];
+        bad |= steric_sum(c, i0 + 1, j0, j1, get, acc, &any);
+        if (any)
+            for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
+        if (bad) d.ctl->flag = 1;
+    }
+    for (int a = 0; a < 3; ++a) {
+        Fa[3 * i0 + a] = f0[a];
+        Fa[3 * i0 + 3 + a] = f1[a];
+    }
+}
+
+/* ------------------------------------------------------------ pair sums */
+
+/* FP32C: positions as hi + lo floats, r = (hi_i - hi_j) + (lo_i - lo_j);
+ * pair math in FP32 with the hardware reciprocal square root; the terms of
+ * one LDS tile are summed in FP32 and the tile sum is added to a (hi, lo)
+ * accumulator with TwoSum. The dumbbell's own two spheres are skipped (their
+ * terms are in u0, in FP64). */
+template <int WG, int IPL>
+__global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
+    __shared__ float4 sA[WG];
+    __shared__ float4 sB[WG];
+    __shared__ float sC[WG];
+    const Item it = d.items[blockIdx.x];
+    if (bump && blockIdx.x == 0 && threadIdx.x == 0) d.ctl->step = d.ctl->step + 1;
+    const int t = threadIdx.x;
+    const int ib = it.i0 + t * IPL;
+    const int iend = it.i0 + it.ni;
+
+    float hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
+    float ax[IPL], ay[IPL], az[IPL];  /* running (hi) sums */
+    float bx[IPL], by[IPL], bz[IPL];  /* compensation (lo) */
+    float px[IPL], py[IPL], pz[IPL];  /* tile partial */
+    int dq[IPL];                      /* dumbbell of each target */
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        const int i = ib + q;
+        float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+        if (i < iend) {
+            A = d.pA[i];
+            B = d.pB[i];
+        }
+        hx[q] = A.x; hy[q] = A.y; hz[q] = A.z;
+        lx[q] = B.x; ly[q] = B.y; lz[q] = B.z;
+        ax[q] = ay[q] = az[q] = 0.f;
+        bx[q] = by[q] = bz[q] = 0.f;
+        px[q] = py[q] = pz[q] = 0.f;
+        dq[q] = i >> 1;
+    }
+    const int dlo = it.i0 & ~1;
+    const int dhi = (iend + 1) & ~1;
+    const int jend = it.j0 + it.nj;
+
+    for (int t0 = it.j0; t0 < jend; t0 += WG) {
+        const int n = min(WG, jend - t0);
+        float4 A, B;
+        float C;
+        if (t < n) {
+            A = d.pA[t0 + t];
+            B = d.pB[t0 + t];
+            C = d.pC[t0 + t];
+        } else {
+            /* padding: far away and force-free, contributes exactly zero */
+            A = make_float4(1.0e15f, 1.0e15f, 1.0e15f, 0.f);
+            B = make_float4(0.f, 0.f, 0.f, 0.f);
+            C = 0.f;
+        }
+        __syncthreads();
+        sA[t] = A;
+        sB[t] = B;
+        sC[t] = C;
+        __syncthreads();
+        const bool diag = (t0 < dhi) && (t0 + n > dlo);
+        if (!diag) {
+            const int n4 = (n + 3) & ~3;
+            for (int jj = 0; jj < n4; jj += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float4 Aj = sA[jj + u];
+                    const float4 Bj = sB[jj + u];
+                    const float Fz = sC[jj + u];
+#pragma unroll
+                    for (int q = 0; q < IPL; ++q) {
+                        float rx = (hx[q] - Aj.x) + (lx[q] - Bj.x);
+                        float ry = (hy[q] - Aj.y) + (ly[q] - Bj.y);
+                        float rz = (hz[q] - Aj.z) + (lz[q] - Bj.z);
+                        float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                        float ir = __builtin_amdgcn_rsqf(r2);
+                        float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Bj.w, rx * Aj.w));
+                        float tt = fr * (ir * ir);
+                        px[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, rx, Aj.w), px[q]);
+                        py[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, ry, Bj.w), py[q]);
+                        pz[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, rz, Fz), pz[q]);
+                    }
+                }
+            }
+        } else {
+            for (int jj = 0; jj < n; ++jj) {
+                const float4 Aj = sA[jj];
+                const float4 Bj = sB[jj];
+                const float Fz = sC[jj];
+                const int dj = (t0 + jj) >> 1;
+#pragma unroll
+                for (int q = 0; q < IPL; ++q) {
+                    float rx = (hx[q] - Aj.x) + (lx[q] - Bj.x);
+                    float ry = (hy[q] - Aj.y) + (ly[q] - Bj.y);
+                    float rz = (hz[q] - Aj.z) + (lz[q] - Bj.z);
+                    float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                    float ir = (dj == dq[q]) ? 0.f : __builtin_amdgcn_rsqf(r2);
+                    float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Bj.w, rx * Aj.w));
+                    float tt = fr * (ir * ir);
+                    px[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, rx, Aj.w), px[q]);
+                    py[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, ry, Bj.w), py[q]);
+                    pz[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, rz, Fz), pz[q]);
+                }
+            }
+        }
+        /* TwoSum of the tile partial into (hi, lo) */
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            float s, bb, e;
+            s = ax[q] + px[q]; bb = s - ax[q]; e = (ax[q] - (s - bb)) + (px[q] - bb); ax[q] = s; bx[q] = bx[q] + e;
+            s = ay[q] + py[q]; bb = s - ay[q]; e = (ay[q] - (s - bb)) + (py[q] - bb); ay[q] = s; by[q] = by[q] + e;
+            s = az[q] + pz[q]; bb = s - az[q]; e = (az[q] - (s - bb)) + (pz[q] - bb); az[q] = s; bz[q] = bz[q] + e;
+            px[q] = py[q] = pz[q] = 0.f;
+        }
+    }
+    const long long base = d.sys_pbase[it.sys] + (long long)it.c * 3 * it.Nb;
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        const int i = ib + q;
+        if (i < iend) {
+            const int li = i - it.ioff;
+            d.part[base + li] = (double)ax[q] + (double)bx[q];
+            d.part[base + it.Nb + li] = (double)ay[q] + (double)by[q];
+            d.part[base + 2 * it.Nb + li] = (double)az[q] + (double)bz[q];
+        }
+    }
+}
+
+/* FP64: the sum in ascending j with the plain operation order
+ *   r2 = (rx*rx + ry*ry) + rz*rz; ir = 1/sqrt(r2); fr = (rx*Fx + ry*Fy) + rz*Fz;
+ *   t = fr/r2; acc = acc + ir*(F + t*r)
+ * over every j != i of the chunk (partner included). A coincident pair is
+ * skipped and raises the flag. With one chunk per system this is the
+ * sequential FP64 sum exactly. */
+template <int WG, int IPL>
+__global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, int bump) {
+    __shared__ double2 sD[3][WG];
+    const Item it = d.items[blockIdx.x];
+    if (bump && blockIdx.x == 0 && threadIdx.x == 0) d.ctl->step = d.ctl->step + 1;
+    const int t = threadIdx.x;
+    const int ib = it.i0 + t * IPL;
+    const int iend = it.i0 + it.ni;
+    double xi[IPL], yi[IPL], zi[IPL], ax[IPL], ay[IPL], az[IPL];
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        const int i = ib + q;
+        double2 p0 = make_double2(0.0, 0.0), p1 = p0;
+        if (i < iend) {
+            p0 = d.pD[3 * i];
+            p1 = d.pD[3 * i + 1];
+        }
+        xi[q] = p0.x; yi[q] = p0.y; zi[q] = p1.x;
+        ax[q] = ay[q] = az[q] = 0.0;
+    }
+    int bad = 0;
+    const int jend = it.j0 + it.nj;
+    for (int t0 = it.j0; t0 < jend; t0 += WG) {
+        const int n = min(WG, jend - t0);
+        double2 a0, a1, a2;
+        if (t < n) {
+            a0 = d.pD[3 * (t0 + t)];
+            a1 = d.pD[3 * (t0 + t) + 1];
+            a2 = d.pD[3 * (t0 + t) + 2];
+        } else {
+            a0 = make_double2(1.0e300, 1.0e300);
+            a1 = make_double2(1.0e300, 0.0);
+            a2 = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        sD[0][t] = a0;
+        sD[1][t] = a1;
+        sD[2][t] = a2;
+        __syncthreads();
+        for (int jj = 0; jj < n; ++jj) {
+            const double2 b0 = sD[0][jj], b1 = sD[1][jj], b2 = sD[2][jj];
+            const double Fx = b1.y, Fy = b2.x, Fz = b2.y;
+            const int j = t0 + jj;
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) {
+                double rx = xi[q] - b0.x;
+                double ry = yi[q] - b0.y;
+                double rz = zi[q] - b1.x;
+                double r2 = (rx * rx + ry * ry) + rz * rz;
+                bool self = (j == ib + q);
+                bool skip = self || (r2 == 0.0);
+                bad |= (!self && r2 == 0.0);
+                double r2s = skip ? 1.0 : r2;
+                double ir = 1.0 / sqrt(r2s);
+                double fr = (rx * Fx + ry * Fy) + rz * Fz;
+                double tt = fr / r2s;
+                double gx = ir * (Fx + tt * rx);
+                double gy = ir * (Fy + tt * ry);
+                double gz = ir * (Fz + tt * rz);
+                ax[q] = skip ? ax[q] : ax[q] + gx;
+                ay[q] = skip ? ay[q] : ay[q] + gy;
+                az[q] = skip ? az[q] : az[q] + gz;
+            }
+        }
+    }
+    const long long base = d.sys_pbase[it.sys] + (long long)it.c * 3 * it.Nb;
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        const int i = ib + q;
+        if (i < iend) {
+            const int li = i - it.ioff;
+            d.part[base + li] = ax[q];
+            d.part[base + it.Nb + li] = ay[q];
+            d.part[base + 2 * it.Nb + li] = az[q];
+            if (bad) d.ctl->flag = 1;
+        }
+    }
+}
+
+/* ------------------------------------------------------------ epilogue */
+
+__global__ void k_epilogue(Dev d, Coef c, int prec, int integrator, int stage, int pack_next,
+                           double* __restrict__ u_aos) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.Stot) return;
+    const int N = d.Ntot;
+    const int b = d.dsys[s];
+    const int off = d.sys_off[b];
+    const int Nb = d.sys_off[b + 1] - off;
+    const int P = d.sys_P[b];
+    const long long pb = d.sys_pbase[b];
+    const int i0 = 2 * s;
+    double kv[2][3];
+    int bad = 0;
+    for (int h = 0; h < 2; ++h) {
+        const int li = i0 + h - off;
+        for (int a = 0; a < 3; ++a) {
+            const double* p = d.part + pb + (long long)a * Nb + li;
+            double acc = p[0];
+            for (int cc = 1; cc < P; ++cc) acc = acc + p[(long long)cc * 3 * Nb];
+            double v = d.U0[a * N + i0 + h] + c.co * acc;
+            kv[h][a] = v;
+            bad |= !isfinite(v);
+        }
+    }
+    if (bad) d.ctl->flag = 1;
+    if (u_aos) {
+        for (int h = 0; h < 2; ++h)
+            for (int a = 0; a < 3; ++a) u_aos[3 * (i0 + h) + a] = kv[h][a];
+        return;
+    }
+    double y[2][3];
+    for (int h = 0; h < 2; ++h) {
+        const int i = i0 + h;
+        for (int a = 0; a < 3; ++a) {
+            const int o = a * N + i;
+            const double k = kv[h][a];
+            const double x = d.X[o];
+            if (integrator == 0) { /* RK4 */
+                if (stage == 0) {
+                    d.R[o] = k;
+                    y[h][a] = x + c.h2 * k;
+                } else if (stage == 1) {
+                    d.R[o] = d.R[o] + 2.0 * k;
+                    y[h][a] = x + c.h2 * k;
+                } else if (stage == 2) {
+                    d.R[o] = d.R[o] + 2.0 * k;
+                    y[h][a] = x + c.dt * k;
+                } else {
+                    const double xn = x + c.dt6 * (d.R[o] + k);
+                    d.X[o] = xn;
+                    y[h][a] = xn;
+                }
+            } else { /* Heun */
+                if (stage == 0) {
+                    d.R[o] = k;
+                    y[h][a] = x + c.dt * k;
+                } else {
+                    const double xn = x + c.h2 * (d.R[o] + k);
+                    d.X[o] = xn;
+                    y[h][a] = xn;
+                }
+            }
+        }
+    }
+    /* forces of the next stage: (sin, cos) of omega t from the step table */
+    const long long e = d.ctl->step % d.ring;
+    const double st = d.tab[e * 8 + 2 * stage];
+    const double ct = d.tab[e * 8 + 2 * stage + 1];
+    double f0[3], f1[3];
+    const double2 tp = d.phitrig[s];
+    spring_forces(c, y[0], y[1], tp.x, tp.y, st, ct, f0, f1);
+    if (pack_next) {
+        store_pack(d, c, prec, i0, y[0], y[1], f0, f1);
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            d.Y[a * N + i0] = y[0][a];
+            d.Y[a * N + i0 + 1] = y[1][a];
+            d.Fs[a * N + i0] = f0[a];
+            d.Fs[a * N + i0 + 1] = f1[a];
+        }
+    }
+}
+
+/* steric forces at the stage positions Y, then the pack */
+__global__ void k_steric_pack(Dev d, Coef c, int prec) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.Stot) return;
+    const int N = d.Ntot;
+    const int i0 = 2 * s;
+    double y0[3], y1[3], f0[3], f1[3];
+    for (int a = 0; a < 3; ++a) {
+        y0[a] = d.Y[a * N + i0];
+        y1[a] = d.Y[a * N + i0 + 1];
+        f0[a] = d.Fs[a * N + i0];
+        f1[a] = d.Fs[a * N + i0 + 1];
+    }
+    const int b = d.dsys[s];
+    const int j0 = d.sys_off[b], j1 = d.sys_off[b + 1];
+    auto get = [&](int j, double x[3]) {
+        x[0] = d.Y[j];
+        x[1] = d.Y[N + j];
+        x[2] = d.Y[2 * N + j];
+    };
+    double acc[3];
+    int any, bad = 0;
+    bad |= steric_sum(c, i0, j0, j1, get, acc, &any);
+    if (any)
+        for (int a = 0; a < 3; ++a) f0[a] = f0[a] + acc[a];
+    bad |= steric_sum(c, i0 + 1, j0, j1, get, acc, &any);
+    if (any)
+        for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
+    if (bad) d.ctl->flag = 1;
+    store_pack(d, c, prec, i0, y0, y1, f0, f1);
+}
+
+/* records: dumbbell centres and per-system mean position */
+__global__ void k_record(Dev d, double* __restrict__ centres, double* __restrict__ com) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = d.Ntot;
+    if (centres && g < d.Stot) {
+        for (int a = 0; a < 3; ++a)
+            centres[3 * g + a] = 0.5 * (d.X[a * N + 2 * g] + d.X[a * N + 2 * g + 1]);
+    }
+    if (com && g < 3 * d.nsys) {
+        const int b = g / 3, a = g % 3;
+        const int j0 = d.sys_off[b], j1 = d.sys_off[b + 1];
+        double sum = 0.0;
+        for (int j = j0; j < j1; ++j) sum = sum + d.X[a * N + j];
+        com[3 * b + a] = sum / (double)(j1 - j0);
+    }
+}
+
+/* ------------------------------------------------------------ launchers */
+
+static inline dim3 blocks_for(int n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+hipError_t launch_set_step(const Dev& d, long long value, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, d.ctl, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flag(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, d.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_in(const Dev& d, const double* Xa, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_in, blocks_for(d.Ntot, 256), dim3(256), 0, s, d, Xa);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_out(const Dev& d, double* Xa, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_out, blocks_for(d.Ntot, 256), dim3(256), 0, s, d, Xa);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_state(const Dev& d, const Coef& c, int prec, double st, double ct, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_state, blocks_for(d.Stot, 128), dim3(128), 0, s, d, c, prec, st, ct);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_apply(const Dev& d, const Coef& c, int prec, const double* Xa, const double* Fa,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_apply, blocks_for(d.Stot, 128), dim3(128), 0, s, d, c, prec, Xa, Fa);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xa, double st, double ct, double* Fa,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_forces, blocks_for(d.Stot, 128), dim3(128), 0, s, d, c, Xa, st, ct, Fa);
+    return hipGetLastError();
+}
+
+template <int WG, int IPL>
+static hipError_t pairs_t(const Dev& d, int prec, int bump, hipStream_t s) {
+    if (prec == PREC_FP32C) {
+        hipLaunchKernelGGL((k_pairs_f32c<WG, IPL>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
+    } else {
+        /* the FP64 kernel exists for 1 and 2 targets per lane; the work list
+         * was built for this IPL, so a wider one is refused, not narrowed */
+        if constexpr (IPL > 2) return hipErrorInvalidValue;
+        else hipLaunchKernelGGL((k_pairs_f64<WG, IPL>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(const Dev& d, int prec, int wg, int ipl, int bump, hipStream_t s) {
+    if (d.nitems <= 0) return hipSuccess;
+    if (wg == 64) {
+        if (ipl == 1) return pairs_t<64, 1>(d, prec, bump, s);
+        if (ipl == 2) return pairs_t<64, 2>(d, prec, bump, s);
+        if (ipl == 4) return pairs_t<64, 4>(d, prec, bump, s);
+    } else if (wg == 256) {
+        if (ipl == 1) return pairs_t<256, 1>(d, prec, bump, s);
+        if (ipl == 2) return pairs_t<256, 2>(d, prec, bump, s);
+        if (ipl == 4) return pairs_t<256, 4>(d, prec, bump, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_epilogue(const Dev& d, const Coef& c, int prec, int integrator, int stage, int pack_next,
+                           double* u_aos, hipStream_t s) {
+    hipLaunchKernelGGL(k_epilogue, blocks_for(d.Stot, 128), dim3(128), 0, s, d, c, prec, integrator, stage,
+                       pack_next, u_aos);
+    return hipGetLastError();
+}
+
+hipError_t launch_steric_pack(const Dev& d, const Coef& c, int prec, int /*stage*/, hipStream_t s) {
+    hipLaunchKernelGGL(k_steric_pack, blocks_for(d.Stot, 128), dim3(128), 0, s, d, c, prec);
+    return hipGetLastError();
+}
+
+hipError_t launch_record(const Dev& d, double* centres, double* com, hipStream_t s) {
+    int n = d.Stot > 3 * d.nsys ? d.Stot : 3 * d.nsys;
+    hipLaunchKernelGGL(k_record, blocks_for(n, 128), dim3(128), 0, s, d, centres, com);
+    return hipGetLastError();
+}
+
+}  // namespace ad

@@ -1,0 +1,670 @@
+/*
+ * Host runtime behind the C ABI declared in include/ad.h: parameter
+ * validation, the work list of the pair kernel, the workspace layout, the
+ * step loop (direct launches or a captured HIP graph) and error reporting.
+ */
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/ad.h"
+#include "ad_internal.h"
+
+using ad::Coef;
+using ad::Ctl;
+using ad::Dev;
+using ad::Item;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kTabSteps = 4096;          /* steps per table chunk */
+constexpr int kRing = 2 * kTabSteps;     /* table entries (two chunks) */
+
+thread_local std::string g_create_error;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct ad_ctx {
+    ad_params p{};
+    Coef coef{};
+    double omega = 0.0;
+    int nsys = 0;
+    std::vector<int32_t> S;
+    std::vector<int32_t> off; /* sphere offsets, nsys+1 */
+    std::vector<int32_t> dsys;
+    int Ntot = 0, Stot = 0;
+    ad_launch launch{};
+    std::vector<Item> items;
+    std::vector<int32_t> sysP;
+    std::vector<long long> pbase;
+    long long npart = 0;
+
+    /* workspace */
+    void* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    Dev dev{};
+    bool state = false;
+    double t0 = 0.0;
+    long long step = 0;
+
+    /* pinned host staging */
+    double* h_tab = nullptr;    /* kRing*8 */
+    double2* h_phi = nullptr;   /* Stot */
+    int* h_flag = nullptr;
+    hipEvent_t tab_event = nullptr;
+    bool tab_event_live = false;
+
+    /* graph of one step */
+    bool use_graph = false;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t capture_stream = nullptr;
+
+    /* pair-kernel timing */
+    bool profile = false;
+    std::vector<hipEvent_t> ev;  /* start/stop pairs */
+    int ev_used = 0;
+    double prof_ms = 0.0;
+    long long prof_launches = 0;
+
+    std::string err;
+};
+
+static int fail(ad_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+#define HIPCHECK(ctx, expr)                                                                       \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, AD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+/* ------------------------------------------------------------ work list */
+
+static ad_launch default_launch(const ad_ctx* c) {
+    ad_launch L{};
+    int maxN = 0;
+    for (int b = 0; b < c->nsys; ++b) maxN = std::max(maxN, 2 * c->S[b]);
+    if (c->p.precision == AD_FP64) {
+        L.ipl = 1;
+        L.wg = 64;
+        L.jchunk = maxN;
+        return L;
+    }
+    if (c->nsys > 1 || maxN < 1024) {
+        L.wg = 64;
+        L.ipl = 1;
+        L.jchunk = 256;
+        return L;
+    }
+    L.wg = 256;
+    L.ipl = 1;
+    /* about 1024 work-groups of 4 waves, j-chunks of at least 64 */
+    int blocks = (maxN + L.wg * L.ipl - 1) / (L.wg * L.ipl);
+    int P = std::max(1, 1024 / blocks);
+    int jc = (maxN + P - 1) / P;
+    jc = std::max(64, (jc + 63) / 64 * 64);
+    L.jchunk = jc;
+    return L;
+}
+
+static int validate_launch(ad_ctx* c, const ad_launch& L) {
+    if (L.wg != 64 && L.wg != 256) return fail(c, AD_EINVAL, "launch.wg must be 64 or 256 (got %d)", L.wg);
+    if (L.ipl != 1 && L.ipl != 2 && L.ipl != 4) return fail(c, AD_EINVAL, "launch.ipl must be 1, 2 or 4");
+    if (c->p.precision != AD_FP32C && L.ipl > 2)
+        return fail(c, AD_EINVAL, "FP64 modes support ipl 1 or 2");
+    if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
+    if (L.reserved != 0) return fail(c, AD_EINVAL, "launch.reserved must be 0");
+    return AD_OK;
+}
+
+static void build_items(ad_ctx* c) {
+    const ad_launch& L = c->launch;
+    c->items.clear();
+    c->sysP.assign(c->nsys, 1);
+    c->pbase.assign(c->nsys, 0);
+    long long pb = 0;
+    const int IB = L.wg * L.ipl;
+    for (int b = 0; b < c->nsys; ++b) {
+        const int Nb = 2 * c->S[b];
+        const int jc = (c->p.precision == AD_FP64) ? Nb : std::min(L.jchunk, Nb);
+        const int P = (Nb + jc - 1) / jc;
+        c->sysP[b] = P;
+        c->pbase[b] = pb;
+        pb += (long long)P * 3 * Nb;
+        for (int ch = 0; ch < P; ++ch) {
+            const int j0 = c->off[b] + ch * jc;
+            const int nj = std::min(jc, Nb - ch * jc);
+            for (int i = 0; i < Nb; i += IB) {
+                Item it;
+                it.sys = b;
+                it.i0 = c->off[b] + i;
+                it.ni = std::min(IB, Nb - i);
+                it.j0 = j0;
+                it.nj = nj;
+                it.c = ch;
+                it.Nb = Nb;
+                it.ioff = c->off[b];
+                c->items.push_back(it);
+            }
+        }
+    }
+    c->npart = pb;
+    /* longest first: the hardware dispatcher then hands the cheap items to
+     * whichever compute units free up last */
+    std::stable_sort(c->items.begin(), c->items.end(), [](const Item& a, const Item& b) {
+        return (long long)a.ni * a.nj > (long long)b.ni * b.nj;
+    });
+}
+
+/* ------------------------------------------------------------ workspace */
+
+struct Layout {
+    size_t ctl, X, R, U0, Y, Fs, phitrig, dsys, sys_off, sys_P, sys_pbase, items, pA, pB, pC, pD, part, tab, total;
+};
+
+static Layout layout(const ad_ctx* c) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t N = c->Ntot, S = c->Stot;
+    L.ctl = take(sizeof(Ctl));
+    L.X = take(3 * N * 8);
+    L.R = take(3 * N * 8);
+    L.U0 = take(3 * N * 8);
+    const bool steric = c->p.steric_k != 0.0;
+    L.Y = take(steric ? 3 * N * 8 : 0);
+    L.Fs = take(steric ? 3 * N * 8 : 0);
+    L.phitrig = take(S * 16);
+    L.dsys = take(S * 4);
+    L.sys_off = take((c->nsys + 1) * 4);
+    L.sys_P = take(c->nsys * 4);
+    L.sys_pbase = take(c->nsys * 8);
+    L.items = take(std::max<size_t>(1, c->items.size()) * sizeof(Item));
+    const bool f32 = c->p.precision == AD_FP32C;
+    L.pA = take(f32 ? N * 16 : 0);
+    L.pB = take(f32 ? N * 16 : 0);
+    L.pC = take(f32 ? N * 4 : 0);
+    L.pD = take(f32 ? 0 : 3 * N * 16);
+    L.part = take((size_t)c->npart * 8);
+    L.tab = take((size_t)kRing * 8 * 8);
+    L.total = o;
+    return L;
+}
+
+static void make_dev(ad_ctx* c) {
+    Layout L = layout(c);
+    char* b = static_cast<char*>(c->ws);
+    Dev& d = c->dev;
+    d.ctl = reinterpret_cast<Ctl*>(b + L.ctl);
+    d.X = reinterpret_cast<double*>(b + L.X);
+    d.R = reinterpret_cast<double*>(b + L.R);
+    d.U0 = reinterpret_cast<double*>(b + L.U0);
+    d.Y = reinterpret_cast<double*>(b + L.Y);
+    d.Fs = reinterpret_cast<double*>(b + L.Fs);
+    d.phitrig = reinterpret_cast<const double2*>(b + L.phitrig);
+    d.dsys = reinterpret_cast<const int*>(b + L.dsys);
+    d.sys_off = reinterpret_cast<const int*>(b + L.sys_off);
+    d.sys_P = reinterpret_cast<const int*>(b + L.sys_P);
+    d.sys_pbase = reinterpret_cast<const long long*>(b + L.sys_pbase);
+    d.items = reinterpret_cast<const Item*>(b + L.items);
+    d.pA = reinterpret_cast<float4*>(b + L.pA);
+    d.pB = reinterpret_cast<float4*>(b + L.pB);
+    d.pC = reinterpret_cast<float*>(b + L.pC);
+    d.pD = reinterpret_cast<double2*>(b + L.pD);
+    d.part = reinterpret_cast<double*>(b + L.part);
+    d.tab = reinterpret_cast<const double*>(b + L.tab);
+    d.ring = kRing;
+    d.Ntot = c->Ntot;
+    d.Stot = c->Stot;
+    d.nsys = c->nsys;
+    d.nitems = (int)c->items.size();
+}
+
+static void drop_graph(ad_ctx* c) {
+    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+/* upload the work list and the per-system tables (synchronous) */
+static int upload_tables(ad_ctx* c) {
+    Layout L = layout(c);
+    char* b = static_cast<char*>(c->ws);
+    HIPCHECK(c, hipMemcpy(b + L.dsys, c->dsys.data(), c->Stot * 4, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(b + L.sys_off, c->off.data(), (c->nsys + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(b + L.sys_P, c->sysP.data(), c->nsys * 4, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(b + L.sys_pbase, c->pbase.data(), c->nsys * 8, hipMemcpyHostToDevice));
+    if (!c->items.empty())
+        HIPCHECK(c, hipMemcpy(b + L.items, c->items.data(), c->items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    return AD_OK;
+}
+
+/* ------------------------------------------------------------ step pieces */
+
+static int prec_of(const ad_ctx* c) {
+    return c->p.precision == AD_FP32C ? ad::PREC_FP32C
+                                      : (c->p.precision == AD_FP64_TILED ? ad::PREC_FP64_TILED : ad::PREC_FP64);
+}
+
+/* (sin, cos) of omega*t on the host (libm) */
+static void trig_at(const ad_ctx* c, double t, double* s, double* co) {
+    double wt = c->omega * t;
+    *s = sin(wt);
+    *co = cos(wt);
+}
+
+/* Fill the device table for steps [s0, s0 + count), count <= kTabSteps. */
+static int fill_table(ad_ctx* c, long long s0, int count, hipStream_t st) {
+    if (c->tab_event_live) HIPCHECK(c, hipEventSynchronize(c->tab_event));
+    const double dt = c->p.dt;
+    for (int q = 0; q < count; ++q) {
+        const long long n = s0 + q;
+        const long long e = n % kRing;
+        double* row = c->h_tab + e * 8;
+        const double tn = c->t0 + (double)n * dt;
+        const double tnext = c->t0 + (double)(n + 1) * dt;
+        if (c->p.integrator == AD_RK4) {
+            const double th = tn + 0.5 * dt, te = tn + dt;
+            trig_at(c, th, &row[0], &row[1]);
+            trig_at(c, th, &row[2], &row[3]);
+            trig_at(c, te, &row[4], &row[5]);
+            trig_at(c, tnext, &row[6], &row[7]);
+        } else {
+            const double te = tn + dt;
+            trig_at(c, te, &row[0], &row[1]);
+            trig_at(c, tnext, &row[2], &row[3]);
+            row[4] = row[5] = row[6] = row[7] = 0.0;
+        }
+    }
+    const long long e0 = s0 % kRing;
+    const long long first = std::min<long long>(count, kRing - e0);
+    double* dtab = const_cast<double*>(c->dev.tab);
+    HIPCHECK(c, hipMemcpyAsync(dtab + e0 * 8, c->h_tab + e0 * 8, first * 8 * sizeof(double),
+                               hipMemcpyHostToDevice, st));
+    if (first < count)
+        HIPCHECK(c, hipMemcpyAsync(dtab, c->h_tab, (count - first) * 8 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHECK(c, hipEventRecord(c->tab_event, st));
+    c->tab_event_live = true;
+    return AD_OK;
+}
+
+constexpr int kEventPairs = 512;
+
+/* sum the recorded pair-kernel intervals and recycle the events */
+static int profile_flush(ad_ctx* c) {
+    for (int q = 0; q < c->ev_used; ++q) {
+        float ms = 0.f;
+        HIPCHECK(c, hipEventSynchronize(c->ev[2 * q + 1]));
+        HIPCHECK(c, hipEventElapsedTime(&ms, c->ev[2 * q], c->ev[2 * q + 1]));
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+    }
+    c->ev_used = 0;
+    return AD_OK;
+}
+
+static int launch_pairs_timed(ad_ctx* c, int prec, int bump, hipStream_t st) {
+    if (!c->profile) {
+        HIPCHECK(c, ad::launch_pairs(c->dev, prec, c->launch.wg, c->launch.ipl, bump, st));
+        return AD_OK;
+    }
+    if (c->ev.empty()) {
+        c->ev.resize(2 * kEventPairs);
+        for (auto& e : c->ev) HIPCHECK(c, hipEventCreate(&e));
+    }
+    if (c->ev_used == kEventPairs) {
+        int rc = profile_flush(c);
+        if (rc != AD_OK) return rc;
+    }
+    HIPCHECK(c, hipEventRecord(c->ev[2 * c->ev_used], st));
+    HIPCHECK(c, ad::launch_pairs(c->dev, prec, c->launch.wg, c->launch.ipl, bump, st));
+    HIPCHECK(c, hipEventRecord(c->ev[2 * c->ev_used + 1], st));
+    c->ev_used += 1;
+    return AD_OK;
+}
+
+/* launches of one step (no table, no initial pack) */
+static int launch_step_kernels(ad_ctx* c, hipStream_t st) {
+    const int prec = prec_of(c);
+    const int nst = c->p.integrator == AD_RK4 ? 4 : 2;
+    const bool steric = c->p.steric_k != 0.0;
+    for (int s = 0; s < nst; ++s) {
+        int rc = launch_pairs_timed(c, prec, s == 0, st);
+        if (rc != AD_OK) return rc;
+        HIPCHECK(c, ad::launch_epilogue(c->dev, c->coef, prec, c->p.integrator, s, !steric, nullptr, st));
+        if (steric) HIPCHECK(c, ad::launch_steric_pack(c->dev, c->coef, prec, s, st));
+    }
+    return AD_OK;
+}
+
+static int ensure_graph(ad_ctx* c) {
+    if (c->graph_exec) return AD_OK;
+    if (!c->capture_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    HIPCHECK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_step_kernels(c, c->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+    if (rc != AD_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, AD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    c->graph = g;
+    HIPCHECK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    return AD_OK;
+}
+
+static int advance(ad_ctx* c, long long nsteps, int record_every, double* centres, double* com, hipStream_t st) {
+    if (!c->ws) return fail(c, AD_ESTATE, "no workspace bound");
+    if (!c->state) return fail(c, AD_ESTATE, "no state loaded (ad_set_state)");
+    if (nsteps < 0) return fail(c, AD_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return AD_OK;
+    const int prec = prec_of(c);
+    const bool graph = c->use_graph && !c->profile;
+    if (graph) {
+        int rc = ensure_graph(c);
+        if (rc != AD_OK) return rc;
+    }
+    HIPCHECK(c, ad::launch_set_step(c->dev, c->step - 1, st));
+    double s0, c0;
+    trig_at(c, c->t0 + (double)c->step * c->p.dt, &s0, &c0);
+    HIPCHECK(c, ad::launch_pack_state(c->dev, c->coef, prec, s0, c0, st));
+    long long done = 0, rec = 0;
+    while (done < nsteps) {
+        const int chunk = (int)std::min<long long>(nsteps - done, kTabSteps);
+        int rc = fill_table(c, c->step + done, chunk, st);
+        if (rc != AD_OK) return rc;
+        for (int q = 0; q < chunk; ++q) {
+            if (graph) {
+                HIPCHECK(c, hipGraphLaunch(c->graph_exec, st));
+            } else {
+                rc = launch_step_kernels(c, st);
+                if (rc != AD_OK) return rc;
+            }
+            const long long n = done + q + 1;
+            if (record_every > 0 && n % record_every == 0) {
+                double* cp = centres ? centres + rec * 3LL * c->Stot : nullptr;
+                double* mp = com ? com + rec * 3LL * c->nsys : nullptr;
+                HIPCHECK(c, ad::launch_record(c->dev, cp, mp, st));
+                ++rec;
+            }
+        }
+        done += chunk;
+    }
+    c->step += nsteps;
+    return AD_OK;
+}
+
+static int read_flag(ad_ctx* c, hipStream_t st) {
+    HIPCHECK(c, hipMemcpyAsync(c->h_flag, &c->dev.ctl->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(c, hipStreamSynchronize(st));
+    if (*c->h_flag) return fail(c, AD_ENONFINITE, "non-finite velocity or coincident spheres met");
+    return AD_OK;
+}
+
+/* ------------------------------------------------------------ ABI */
+
+extern "C" {
+
+int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx** out) {
+    g_create_error.clear();
+    if (!p || !S_per_sys || !out) return fail(nullptr, AD_EINVAL, "null argument");
+    *out = nullptr;
+    if (nsys <= 0) return fail(nullptr, AD_EINVAL, "nsys must be >= 1");
+    const double vals[] = {p->a, p->eta, p->k, p->ell, p->lambda, p->T, p->dt, p->steric_k, p->steric_r};
+    for (double v : vals)
+        if (!isfinite(v)) return fail(nullptr, AD_EINVAL, "parameters must be finite");
+    if (!(p->a > 0) || !(p->eta > 0) || !(p->T > 0) || !(p->dt > 0))
+        return fail(nullptr, AD_EINVAL, "a, eta, T and dt must be > 0");
+    if (p->steric_k != 0.0 && !(p->steric_r > 0)) return fail(nullptr, AD_EINVAL, "steric_r must be > 0");
+    if (p->precision != AD_FP64 && p->precision != AD_FP64_TILED && p->precision != AD_FP32C)
+        return fail(nullptr, AD_EINVAL, "unknown precision %d", p->precision);
+    if (p->integrator != AD_RK4 && p->integrator != AD_HEUN)
+        return fail(nullptr, AD_EINVAL, "unknown integrator %d", p->integrator);
+    if (p->tensor != AD_OSEEN) return fail(nullptr, AD_EINVAL, "unknown tensor %d", p->tensor);
+    if (p->reserved != 0) return fail(nullptr, AD_EINVAL, "reserved must be 0");
+    long long Stot = 0;
+    for (int b = 0; b < nsys; ++b) {
+        if (S_per_sys[b] < 1) return fail(nullptr, AD_EINVAL, "S_per_sys[%d] must be >= 1", b);
+        Stot += S_per_sys[b];
+    }
+    if (2 * Stot > (1LL << 30)) return fail(nullptr, AD_EINVAL, "too many spheres");
+    ad_ctx* c = new (std::nothrow) ad_ctx();
+    if (!c) return fail(nullptr, AD_ENOMEM, "out of host memory");
+    c->p = *p;
+    c->nsys = nsys;
+    c->S.assign(S_per_sys, S_per_sys + nsys);
+    c->off.assign(nsys + 1, 0);
+    for (int b = 0; b < nsys; ++b) c->off[b + 1] = c->off[b] + 2 * c->S[b];
+    c->Ntot = c->off[nsys];
+    c->Stot = (int)Stot;
+    c->dsys.resize(c->Stot);
+    for (int b = 0, s = 0; b < nsys; ++b)
+        for (int q = 0; q < c->S[b]; ++q) c->dsys[s++] = b;
+    Coef& k = c->coef;
+    k.cs = 1.0 / (6.0 * kPi * p->eta * p->a);
+    k.co = 1.0 / (8.0 * kPi * p->eta);
+    k.k = p->k;
+    k.ell = p->ell;
+    k.lam = p->lambda;
+    k.dt = p->dt;
+    k.h2 = 0.5 * p->dt;
+    k.dt6 = p->dt / 6.0;
+    k.ks = p->steric_k;
+    k.rc = p->steric_r;
+    c->omega = 2.0 * kPi / p->T;
+    c->launch = default_launch(c);
+    build_items(c);
+    *out = c;
+    return AD_OK;
+}
+
+int ad_destroy(ad_ctx* c) {
+    if (!c) return AD_OK;
+    drop_graph(c);
+    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+    if (c->tab_event) hipEventDestroy(c->tab_event);
+    for (auto& e : c->ev) hipEventDestroy(e);
+    if (c->h_tab) hipHostFree(c->h_tab);
+    if (c->h_phi) hipHostFree(c->h_phi);
+    if (c->h_flag) hipHostFree(c->h_flag);
+    delete c;
+    return AD_OK;
+}
+
+int ad_workspace_size(const ad_ctx* c, uint64_t* bytes) {
+    if (!c || !bytes) return AD_EINVAL;
+    *bytes = layout(c).total;
+    return AD_OK;
+}
+
+int ad_bind_workspace(ad_ctx* c, void* ptr, uint64_t bytes) {
+    if (!c) return AD_EINVAL;
+    if (!ptr) return fail(c, AD_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(ptr) % 256) return fail(c, AD_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < layout(c).total)
+        return fail(c, AD_ENOMEM, "workspace of %llu bytes, need %llu", (unsigned long long)bytes,
+                    (unsigned long long)layout(c).total);
+    if (!c->h_tab) {
+        HIPCHECK(c, hipHostMalloc((void**)&c->h_tab, (size_t)kRing * 8 * sizeof(double), hipHostMallocDefault));
+        HIPCHECK(c, hipHostMalloc((void**)&c->h_phi, (size_t)c->Stot * sizeof(double2), hipHostMallocDefault));
+        HIPCHECK(c, hipHostMalloc((void**)&c->h_flag, sizeof(int), hipHostMallocDefault));
+        HIPCHECK(c, hipEventCreateWithFlags(&c->tab_event, hipEventDisableTiming));
+    }
+    drop_graph(c);
+    c->ws = ptr;
+    c->ws_bytes = bytes;
+    c->state = false;
+    make_dev(c);
+    return upload_tables(c);
+}
+
+int ad_set_launch(ad_ctx* c, const ad_launch* L) {
+    if (!c || !L) return AD_EINVAL;
+    ad_launch want = *L;
+    ad_launch def = default_launch(c);
+    if (want.ipl == 0) want.ipl = def.ipl;
+    if (want.wg == 0) want.wg = def.wg;
+    if (want.jchunk == 0) want.jchunk = def.jchunk;
+    int rc = validate_launch(c, want);
+    if (rc != AD_OK) return rc;
+    ad_launch old = c->launch;
+    c->launch = want;
+    build_items(c);
+    if (c->ws) {
+        if (layout(c).total > c->ws_bytes) {
+            c->launch = old;
+            build_items(c);
+            return fail(c, AD_ENOMEM, "workspace too small for this launch shape");
+        }
+        /* regions ahead of the work list (state, phases, tables) keep their
+         * offsets; the packs, partials and step table are rebuilt per step */
+        drop_graph(c);
+        make_dev(c);
+        return upload_tables(c);
+    }
+    return AD_OK;
+}
+
+int ad_get_launch(const ad_ctx* c, ad_launch* L) {
+    if (!c || !L) return AD_EINVAL;
+    *L = c->launch;
+    return AD_OK;
+}
+
+int ad_set_state(ad_ctx* c, const double* X, const double* phi, double t0, int64_t step0, void* stream) {
+    if (!c) return AD_EINVAL;
+    if (!c->ws) return fail(c, AD_ESTATE, "no workspace bound");
+    if (!X || !phi) return fail(c, AD_EINVAL, "null X or phi");
+    if (!isfinite(t0) || step0 < 0) return fail(c, AD_EINVAL, "t0 must be finite and step0 >= 0");
+    hipStream_t st = as_stream(stream);
+    for (int s = 0; s < c->Stot; ++s) {
+        if (!isfinite(phi[s])) return fail(c, AD_EINVAL, "phi[%d] is not finite", s);
+        c->h_phi[s] = make_double2(sin(phi[s]), cos(phi[s]));
+    }
+    HIPCHECK(c, hipMemcpyAsync(const_cast<double2*>(c->dev.phitrig), c->h_phi, (size_t)c->Stot * sizeof(double2),
+                               hipMemcpyHostToDevice, st));
+    HIPCHECK(c, ad::launch_state_in(c->dev, X, st));
+    HIPCHECK(c, ad::launch_clear_flag(c->dev, st));
+    HIPCHECK(c, hipStreamSynchronize(st));
+    c->t0 = t0;
+    c->step = step0;
+    c->state = true;
+    return AD_OK;
+}
+
+int ad_get_state(ad_ctx* c, double* X, double* t0, int64_t* step, void* stream) {
+    if (!c) return AD_EINVAL;
+    if (!c->ws || !c->state) return fail(c, AD_ESTATE, "no state loaded");
+    hipStream_t st = as_stream(stream);
+    if (X) HIPCHECK(c, ad::launch_state_out(c->dev, X, st));
+    HIPCHECK(c, hipStreamSynchronize(st));
+    if (t0) *t0 = c->t0;
+    if (step) *step = c->step;
+    return AD_OK;
+}
+
+int ad_forces(ad_ctx* c, const double* X, double t, double* F, void* stream) {
+    if (!c) return AD_EINVAL;
+    if (!c->ws || !c->state) return fail(c, AD_ESTATE, "no state loaded (phases needed)");
+    if (!X || !F) return fail(c, AD_EINVAL, "null X or F");
+    if (!isfinite(t)) return fail(c, AD_EINVAL, "t must be finite");
+    double s0, c0;
+    trig_at(c, t, &s0, &c0);
+    HIPCHECK(c, ad::launch_forces(c->dev, c->coef, X, s0, c0, F, as_stream(stream)));
+    return AD_OK;
+}
+
+int ad_mobility_apply(ad_ctx* c, const double* X, const double* F, double* u, void* stream) {
+    if (!c) return AD_EINVAL;
+    if (!c->ws) return fail(c, AD_ESTATE, "no workspace bound");
+    if (!X || !F || !u) return fail(c, AD_EINVAL, "null X, F or u");
+    hipStream_t st = as_stream(stream);
+    const int prec = prec_of(c);
+    HIPCHECK(c, ad::launch_pack_apply(c->dev, c->coef, prec, X, F, st));
+    HIPCHECK(c, ad::launch_pairs(c->dev, prec, c->launch.wg, c->launch.ipl, 0, st));
+    HIPCHECK(c, ad::launch_epilogue(c->dev, c->coef, prec, c->p.integrator, 0, 0, u, st));
+    return AD_OK;
+}
+
+int ad_step(ad_ctx* c, int64_t nsteps, void* stream) {
+    if (!c) return AD_EINVAL;
+    return advance(c, nsteps, 0, nullptr, nullptr, as_stream(stream));
+}
+
+int ad_run(ad_ctx* c, int64_t nsteps, int32_t record_every, double* centres, double* com, void* stream) {
+    if (!c) return AD_EINVAL;
+    if (record_every < 0) return fail(c, AD_EINVAL, "record_every must be >= 0");
+    hipStream_t st = as_stream(stream);
+    int rc = advance(c, nsteps, record_every, centres, com, st);
+    if (rc != AD_OK) return rc;
+    return read_flag(c, st);
+}
+
+int ad_check(ad_ctx* c, void* stream) {
+    if (!c) return AD_EINVAL;
+    if (!c->ws) return fail(c, AD_ESTATE, "no workspace bound");
+    return read_flag(c, as_stream(stream));
+}
+
+int ad_use_graph(ad_ctx* c, int32_t enable) {
+    if (!c) return AD_EINVAL;
+    c->use_graph = enable != 0;
+    return AD_OK;
+}
+
+int ad_profile_pairs(ad_ctx* c, int32_t enable) {
+    if (!c) return AD_EINVAL;
+    if (c->profile && c->ev_used) {
+        int rc = profile_flush(c);
+        if (rc != AD_OK) return rc;
+    }
+    c->profile = enable != 0;
+    c->prof_ms = 0.0;
+    c->prof_launches = 0;
+    return AD_OK;
+}
+
+int ad_profile_read(ad_ctx* c, double* total_ms, int64_t* launches) {
+    if (!c || !total_ms || !launches) return AD_EINVAL;
+    int rc = profile_flush(c);
+    if (rc != AD_OK) return rc;
+    *total_ms = c->prof_ms;
+    *launches = c->prof_launches;
+    return AD_OK;
+}
+
+const char* ad_last_error(const ad_ctx* c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"

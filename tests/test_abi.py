@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports what include/ad.h declares, and rejects
+bad arguments before touching a device (no GPU needed)."""
+import ctypes as C
+import re
+from dataclasses import replace
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import paper_1004_1932_amd as P
+from paper_1004_1932_amd import binding as B
+from workload import Params
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def declared_symbols():
+    text = (ROOT / "include" / "ad.h").read_text()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(ad_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ("ad_create", "ad_set_state", "ad_forces", "ad_mobility_apply", "ad_step", "ad_run"):
+        assert required in names
+    assert sorted(B.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(str(P.LIB_PATH))
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    # 9 doubles + 4 int32 / 4 int32
+    assert C.sizeof(B.ad_params) == 9 * 8 + 4 * 4
+    assert C.sizeof(B.ad_launch) == 16
+
+
+@pytest.mark.parametrize("bad", [dict(a=0.0), dict(eta=-1.0), dict(T=0.0), dict(dt=float("nan")),
+                                 dict(k=float("inf"))])
+def test_create_rejects_bad_parameters(bad):
+    p = replace(Params(), **bad)
+    with pytest.raises(P.ADError) as e:
+        P.ad_create(P.make_params(p), [4])
+    assert e.value.code == B.AD_EINVAL
+    assert P.ad_last_error(None)
+
+
+def test_create_rejects_bad_sizes_and_enums():
+    with pytest.raises(P.ADError):
+        P.ad_create(P.make_params(Params()), [4, 0])
+    with pytest.raises(P.ADError):
+        P.ad_create(P.make_params(Params()), np.zeros(0, np.int32))
+    bad = P.make_params(Params())
+    bad.precision = 7
+    with pytest.raises(P.ADError):
+        P.ad_create(bad, [4])
+    bad = P.make_params(Params())
+    bad.integrator = 3
+    with pytest.raises(P.ADError):
+        P.ad_create(bad, [4])
+
+
+def test_calls_before_workspace_fail_cleanly():
+    ctx = P.ad_create(P.make_params(Params()), [8])
+    try:
+        lib = P.lib()
+        assert lib.ad_step(ctx, 1, None) == B.AD_ESTATE
+        assert "workspace" in P.ad_last_error(ctx)
+        assert lib.ad_check(ctx, None) == B.AD_ESTATE
+        assert lib.ad_mobility_apply(ctx, None, None, None, None) == B.AD_ESTATE
+        assert lib.ad_bind_workspace(ctx, None, 0) == B.AD_EINVAL
+        assert lib.ad_bind_workspace(ctx, C.c_void_p(256), 16) == B.AD_ENOMEM
+        assert lib.ad_bind_workspace(ctx, C.c_void_p(100), 1 << 30) == B.AD_EINVAL
+    finally:
+        P.ad_destroy(ctx)
+
+
+def test_launch_shapes_and_workspace_size():
+    ctx = P.ad_create(P.make_params(Params(), "fp32c"), [2048])
+    try:
+        L = P.ad_get_launch(ctx)
+        assert L["wg"] in (64, 256) and L["ipl"] in (1, 2, 4) and L["jchunk"] >= 64
+        P.ad_set_launch(ctx, ipl=4, jchunk=4096, wg=256)
+        one_chunk = P.ad_workspace_size(ctx)
+        P.ad_set_launch(ctx, ipl=4, jchunk=64, wg=256)
+        assert P.ad_get_launch(ctx) == {"ipl": 4, "jchunk": 64, "wg": 256}
+        # 64 j-chunks hold 64 partial sums per sphere instead of one
+        assert P.ad_workspace_size(ctx) - one_chunk >= 63 * 3 * 4096 * 8
+        for bad in (dict(ipl=3), dict(wg=128), dict(jchunk=32)):
+            with pytest.raises(P.ADError):
+                P.ad_set_launch(ctx, **bad)
+    finally:
+        P.ad_destroy(ctx)
+    ctx = P.ad_create(P.make_params(Params(), "fp64"), [2048])
+    try:
+        with pytest.raises(P.ADError):
+            P.ad_set_launch(ctx, ipl=4)
+    finally:
+        P.ad_destroy(ctx)
+
+
+def test_destroy_null_is_noop():
+    assert P.lib().ad_destroy(None) == 0

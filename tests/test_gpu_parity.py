@@ -1,0 +1,345 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Bars (written in each test):
+  * AD_FP64 (sequential j, fixed operation order, no FMA): bitwise equal.
+  * AD_FP64_TILED: relative velocity error <= 1e-13 (only the summation order
+    differs).
+  * AD_FP32C: relative velocity error <= 1e-6 per evaluation (the norm of the
+    error over one system's 3N components divided by the norm of the oracle
+    velocity), relative centre displacement drift <= 1e-4 over 1e4 steps.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import paper_1004_1932_amd as P
+from workload import Params, make_ensemble, make_single, make_preset
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def perturbed(sus, scale=0.05, seed=1):
+    return sus.X + np.random.default_rng(seed).normal(scale=scale, size=sus.X.shape)
+
+
+def sim(sus_or_S, params, precision, **kw):
+    S = [sus_or_S.S] if hasattr(sus_or_S, "S") else sus_or_S
+    return P.Simulator(params, S, precision=precision, **kw)
+
+
+# ---------------------------------------------------------------- forces
+
+def test_forces_bitwise(oracle):
+    _torch()
+    for name, sus in (("n16", make_preset("n16")), ("n512", make_preset("n512"))):
+        say(f"forces {name}")
+        s = sim(sus, sus.params, "fp64")
+        s.set_state(sus.X, sus.phi)
+        X = perturbed(sus, 0.1)
+        for t in (0.0, 13.37, 2500.25):
+            F = s.forces(X, t).cpu().numpy()
+            assert np.array_equal(F, oracle.forces(sus.params, X, sus.phi, t))
+
+
+def test_forces_steric_bitwise(oracle):
+    _torch()
+    p = Params(steric_k=100.0, steric_r=2.0)
+    sus = make_single(40, 14.0, 5, p, exclusion=False)
+    s = sim(sus, p, "fp64")
+    s.set_state(sus.X, sus.phi)
+    F = s.forces(sus.X, 1.0).cpu().numpy()
+    Fo = oracle.forces(p, sus.X, sus.phi, 1.0)
+    assert np.abs(Fo).max() > 1.0  # overlaps present
+    assert np.array_equal(F, Fo)
+
+
+# ---------------------------------------------------------------- mobility
+
+@pytest.mark.parametrize("S,side", [(1, 10.0), (3, 12.0), (8, 40.0), (37, 40.0), (256, 120.0)])
+def test_mobility_fp64_bitwise(oracle, S, side):
+    _torch()
+    say(f"mobility fp64 S={S}")
+    sus = make_single(S, side, 2)
+    F = np.random.default_rng(3).standard_normal(sus.X.shape)
+    s = sim(sus, sus.params, "fp64")
+    u = s.mobility(sus.X, F).cpu().numpy()
+    assert np.array_equal(u, oracle.mobility(sus.params, sus.X, F))
+
+
+@pytest.mark.parametrize("launch", [None, dict(ipl=1, jchunk=64, wg=64), dict(ipl=2, jchunk=192, wg=256),
+                                    dict(ipl=2, jchunk=100, wg=64)])
+def test_mobility_fp64_tiled(oracle, launch):
+    _torch()
+    say(f"mobility fp64_tiled {launch}")
+    sus = make_single(700, 150.0, 4)
+    F = np.random.default_rng(5).standard_normal(sus.X.shape)
+    s = sim(sus, sus.params, "fp64_tiled", launch=launch)
+    u = s.mobility(sus.X, F).cpu().numpy()
+    assert relerr(u, oracle.mobility(sus.params, sus.X, F)) <= 1e-13
+
+
+FP32C_LAUNCHES = [None, dict(ipl=1, jchunk=64, wg=64), dict(ipl=2, jchunk=320, wg=256),
+                  dict(ipl=4, jchunk=256, wg=256), dict(ipl=4, jchunk=1000, wg=64)]
+
+
+@pytest.mark.parametrize("launch", FP32C_LAUNCHES)
+@pytest.mark.parametrize("S,side", [(1, 10.0), (5, 20.0), (300, 120.0), (2048, 240.0)])
+def test_mobility_fp32c(oracle, S, side, launch):
+    """Spring-like forces (equal and opposite per dumbbell) at a perturbed
+    state, and arbitrary forces; relative velocity error <= 1e-6."""
+    _torch()
+    say(f"mobility fp32c S={S} {launch}")
+    sus = make_single(S, side, 6)
+    X = perturbed(sus, 0.2)
+    s = sim(sus, sus.params, "fp32c", launch=launch)
+    s.set_state(sus.X, sus.phi)
+    F = oracle.forces(sus.params, X, sus.phi, 7.0)
+    u = s.mobility(X, F).cpu().numpy()
+    e1 = relerr(u, oracle.mobility(sus.params, X, F))
+    G = np.random.default_rng(7).standard_normal(X.shape)
+    e2 = relerr(s.mobility(X, G).cpu().numpy(), oracle.mobility(sus.params, X, G))
+    say(f"  rel err spring-forces {e1:.3e} random-forces {e2:.3e}")
+    assert e1 <= 1e-6 and e2 <= 1e-6
+
+
+def test_mobility_fp32c_full_size_sampled(oracle):
+    """65536 spheres in the default launch: 64 sampled target spheres against
+    the oracle's rows, error relative to the sampled velocity norm."""
+    torch = _torch()
+    sus = make_preset("n65536")
+    say("mobility fp32c n65536 sampled")
+    X = perturbed(sus, 0.2)
+    F = oracle.forces(sus.params, X, sus.phi, 3.0)
+    s = sim(sus, sus.params, "fp32c")
+    u = s.mobility(X, F).cpu().numpy()
+    rows = np.random.default_rng(7).choice(sus.N, 64, replace=False)
+    uo = oracle.mobility_rows(sus.params, X, F, rows)
+    err = relerr(u[rows], uo)
+    say(f"  rel err {err:.3e}")
+    assert err <= 1e-6
+    del s
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- trajectories
+
+def _run_both(oracle, sus, precision, nsteps, rec, integrator="rk4", launch=None, graph=False, S_per_sys=None):
+    p = sus.params
+    S = S_per_sys if S_per_sys is not None else [sus.S]
+    s = P.Simulator(p, S, precision=precision, integrator=integrator, launch=launch, graph=graph)
+    s.set_state(sus.X, sus.phi)
+    cen, com, code = s.run(nsteps, rec)
+    assert code == 0
+    Xg = s.get_state()[0].cpu().numpy()
+    Xo, ceno, como, _ = oracle.run(p, sus.X, sus.phi, nsteps, record_every=rec,
+                                   S_per_sys=S, integrator=1 if integrator == "heun" else 0)
+    return Xg, cen.cpu().numpy(), com.cpu().numpy(), Xo, ceno, como
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "heun"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_trajectory_fp64_bitwise_small(oracle, integrator, graph):
+    """16 spheres, 2000 steps: state, centres and centre of mass bitwise."""
+    _torch()
+    say(f"trajectory fp64 n16 {integrator} graph={graph}")
+    sus = make_preset("n16")
+    Xg, cg, mg, Xo, co, mo = _run_both(oracle, sus, "fp64", 2000, 250, integrator, graph=graph)
+    assert np.array_equal(Xg, Xo)
+    assert np.array_equal(cg, co)
+    assert np.array_equal(mg, mo)
+
+
+def test_trajectory_fp64_bitwise_full_n16(oracle):
+    """The plain FP64 workload in full: 16 spheres, 1e4 RK4 steps."""
+    _torch()
+    sus = make_preset("n16")
+    Xg, cg, mg, Xo, co, mo = _run_both(oracle, sus, "fp64", 10_000, 1000, graph=True)
+    assert np.array_equal(Xg, Xo) and np.array_equal(cg, co) and np.array_equal(mg, mo)
+
+
+def test_trajectory_fp32c_drift_n512(oracle):
+    """512 spheres, 1e4 RK4 steps in FP32C: dumbbell-centre displacement
+    relative drift <= 1e-4 against the FP64 oracle; velocity error at the
+    final shared state <= 1e-6."""
+    _torch()
+    sus = make_preset("n512")
+    say("trajectory fp32c n512 1e4 steps")
+    nsteps, rec = 10_000, 1000
+    Xg, cg, mg, Xo, co, mo = _run_both(oracle, sus, "fp32c", nsteps, rec)
+    R0 = 0.5 * (sus.X[0::2] + sus.X[1::2])
+    dg, do = cg - R0, co - R0
+    drift = [relerr(dg[r], do[r]) for r in range(len(do))]
+    say(f"  drift per record {['%.2e' % x for x in drift]}")
+    assert max(drift) <= 1e-4
+    # velocity at the GPU's own final state, both sides on the same X
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c")
+    s.set_state(Xg, sus.phi)
+    t = nsteps * sus.params.dt
+    F = oracle.forces(sus.params, Xg, sus.phi, t)
+    assert relerr(s.mobility(Xg, F).cpu().numpy(), oracle.mobility(sus.params, Xg, F)) <= 1e-6
+
+
+def test_graph_equals_direct_launches(oracle):
+    _torch()
+    sus = make_single(300, 100.0, 9)
+    out = []
+    for graph in (False, True):
+        s = P.Simulator(sus.params, [sus.S], precision="fp32c", graph=graph)
+        s.set_state(sus.X, sus.phi)
+        for _ in range(3):  # several replays with eager work between them
+            s.step(40)
+            s.check()
+        out.append(s.get_state()[0].cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_deterministic_and_resumable(oracle):
+    _torch()
+    sus = make_single(200, 80.0, 10)
+    res = []
+    for _ in range(2):
+        s = P.Simulator(sus.params, [sus.S], precision="fp32c")
+        s.set_state(sus.X, sus.phi)
+        s.step(300)
+        res.append(s.get_state()[0].cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c")
+    s.set_state(sus.X, sus.phi)
+    s.step(150)
+    Xh, t0, step = s.get_state()
+    assert step == 150
+    s2 = P.Simulator(sus.params, [sus.S], precision="fp32c")
+    s2.set_state(Xh, sus.phi, t0, step)
+    s2.step(150)
+    assert np.array_equal(s2.get_state()[0].cpu().numpy(), res[0])
+
+
+# ---------------------------------------------------------------- ensembles
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_ensemble_matches_oracle(oracle, precision):
+    """A batch of uneven suspensions (sizes 1..120 dumbbells) in one launch
+    per stage: FP64 bitwise per system, FP32C within the bars."""
+    _torch()
+    sizes = np.array([1, 16, 120, 3, 57, 64, 33, 90], dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    say(f"ensemble {precision}")
+    s = P.Simulator(ens.params, sizes, precision=precision, graph=True)
+    s.set_state(ens.X, ens.phi)
+    nsteps, rec = 400, 100
+    cen, com, code = s.run(nsteps, rec)
+    assert code == 0
+    Xg = s.get_state()[0].cpu().numpy()
+    Xo, co, mo, _ = oracle.run(ens.params, ens.X, ens.phi, nsteps, record_every=rec, S_per_sys=sizes)
+    if precision == "fp64":
+        assert np.array_equal(Xg, Xo)
+        assert np.array_equal(com.cpu().numpy(), mo)
+    else:
+        off = ens.sphere_offsets
+        F = np.concatenate([oracle.forces(ens.params, Xg[off[b]:off[b + 1]], ens.phi[off[b] // 2:off[b + 1] // 2], 4.0)
+                            for b in range(len(sizes))])
+        u = s.mobility(Xg, F).cpu().numpy()
+        for b in range(len(sizes)):
+            sl = slice(off[b], off[b + 1])
+            uo = oracle.mobility(ens.params, Xg[sl], F[sl])
+            assert relerr(u[sl], uo) <= 1e-6, b
+        assert np.abs(Xg - Xo).max() < 1e-6
+
+
+def test_ensemble_full_size_sampled(oracle):
+    """The 512-suspension batch (16..400 dumbbells each) in the default
+    launch: mobility of 8 systems against the oracle; 20 steps run clean."""
+    _torch()
+    ens = make_preset("ens512")
+    say(f"ensemble 512 systems, {ens.X.shape[0]} spheres")
+    s = P.Simulator(ens.params, ens.S_per_sys, precision="fp32c", graph=True)
+    s.set_state(ens.X, ens.phi)
+    off = ens.sphere_offsets
+    F = np.random.default_rng(2).standard_normal(ens.X.shape)
+    u = s.mobility(ens.X, F).cpu().numpy()
+    for b in np.random.default_rng(3).choice(ens.nsys, 8, replace=False):
+        sl = slice(off[b], off[b + 1])
+        assert relerr(u[sl], oracle.mobility(ens.params, ens.X[sl], F[sl])) <= 1e-6, b
+    cen, com, code = s.run(20, 10)
+    assert code == 0 and np.isfinite(com.cpu().numpy()).all()
+
+
+# ---------------------------------------------------------------- failures
+
+def test_coincident_spheres_raise_flag(oracle):
+    _torch()
+    sus = make_single(8, 30.0, 3)
+    X = sus.X.copy()
+    X[5] = X[2]  # two spheres of different dumbbells on top of each other
+    for precision in ("fp64", "fp32c"):
+        s = P.Simulator(sus.params, [sus.S], precision=precision)
+        s.set_state(X, sus.phi)
+        _, _, code = s.run(2, 1)
+        assert code == P.binding.AD_ENONFINITE, precision
+
+
+def test_nan_state_raises_flag():
+    _torch()
+    sus = make_single(8, 30.0, 3)
+    X = sus.X.copy()
+    X[3, 1] = np.nan
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c")
+    s.set_state(X, sus.phi)
+    _, _, code = s.run(1, 1)
+    assert code == P.binding.AD_ENONFINITE
+    # a clean state clears it
+    s.set_state(sus.X, sus.phi)
+    _, _, code = s.run(1, 1)
+    assert code == 0
+
+
+def _steric_suspension():
+    """Dense draw with exclusion at 1.5 instead of 2a: steric repulsion is
+    active from the start while the Oseen tensor stays regular."""
+    p = Params(steric_k=100.0, steric_r=2.0)
+    return make_single(30, 16.0, 4, p, rmin=1.5)
+
+
+def test_steric_trajectory_fp64(oracle):
+    """Steric repulsion on (not in the paper): FP64 bitwise against the
+    oracle over 200 steps."""
+    _torch()
+    sus = _steric_suspension()
+    F = oracle.forces(sus.params, sus.X, sus.phi, 0.0)
+    assert np.abs(F).max() > 1.0  # overlaps present
+    Xg, cg, mg, Xo, co, mo = _run_both(oracle, sus, "fp64", 200, 50)
+    assert np.array_equal(Xg, Xo)
+
+
+def test_steric_fp32c(oracle):
+    """FP32C with steric forces: velocity error <= 1e-6 at the overlapping
+    start, and 200 steps within 1e-6 of the FP64 oracle's positions."""
+    _torch()
+    sus = _steric_suspension()
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c")
+    s.set_state(sus.X, sus.phi)
+    F = s.forces(sus.X, 0.0).cpu().numpy()
+    assert np.array_equal(F, oracle.forces(sus.params, sus.X, sus.phi, 0.0))
+    u = s.mobility(sus.X, F).cpu().numpy()
+    assert relerr(u, oracle.mobility(sus.params, sus.X, F)) <= 1e-6
+    Xg, cg, mg, Xo, co, mo = _run_both(oracle, sus, "fp32c", 200, 50)
+    err = np.abs(Xg - Xo).max()
+    say(f"  steric fp32c max position error after 200 steps {err:.2e}")
+    assert err < 1e-6

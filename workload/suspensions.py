@@ -137,9 +137,9 @@ class _Grid:
 
 
 def _draw_system(S: int, side: float, seed: int, params: Params,
-                 exclusion: bool, max_tries: int = 100000):
+                 exclusion: bool, max_tries: int = 100000, rmin: float | None = None):
     rng = np.random.default_rng(seed)
-    rmin = 2.0 * params.a
+    rmin = 2.0 * params.a if rmin is None else float(rmin)
     grid = _Grid(max(rmin, 1e-12))
     omega = 2.0 * math.pi / params.T
     X = np.empty((2 * S, 3), dtype=np.float64)
@@ -184,9 +184,11 @@ def min_pair_distance(X: np.ndarray, block: int = 2048) -> float:
 
 
 def make_single(S: int, side: float, seed: int = 0, params: Params | None = None,
-                exclusion: bool = True, with_min_distance: bool = False) -> Suspension:
+                exclusion: bool = True, with_min_distance: bool = False,
+                rmin: float | None = None) -> Suspension:
+    """One suspension; `rmin` overrides the exclusion distance 2a."""
     params = params or Params()
-    X, phi = _draw_system(S, side, seed, params, exclusion)
+    X, phi = _draw_system(S, side, seed, params, exclusion, rmin=rmin)
     sus = Suspension(X, phi, params, float(side), seed)
     if with_min_distance:
         sus.min_pair_distance = min_pair_distance(X)
