@@ -79,14 +79,20 @@ typedef struct ad_params {
     int32_t reserved;   /* must be 0 */
 } ad_params;
 
-/* Launch shape of the pair kernel: i-spheres per lane and j-chunk length.
- * Zero fields mean "library default for this size". */
+/* Launch shape of the pair kernel. Zero fields mean "library default for
+ * this size". A work-group of wg threads holds wg/64/wj waves on distinct
+ * target spheres (ipl per lane) and wj waves that split every j-tile. */
 typedef struct ad_launch {
-    int32_t ipl;      /* i-spheres per lane: 1, 2 or 4 (FP64 modes use at most 2) */
-    int32_t jchunk;   /* j-range of one work-group, >= 64 (AD_FP64: always the whole system) */
+    int32_t ipl;      /* target spheres per lane: 1, 2 or 4 (FP64 modes: 1 or 2) */
+    int32_t jchunk;   /* source spheres per work-group, >= 64 (AD_FP64: whole system) */
     int32_t wg;       /* work-group size: 64 or 256 */
+    int32_t wj;       /* waves splitting each j-tile: 1, or 4 with wg = 256 (AD_FP32C) */
+    int32_t posmode;  /* AD_FP32C positions: 1 = hi/lo float pair, 2 = single float */
     int32_t reserved; /* must be 0 */
 } ad_launch;
+
+#define AD_POS_HILO 1
+#define AD_POS_SINGLE 2
 
 typedef struct ad_ctx ad_ctx;
 

@@ -63,6 +63,14 @@ struct Dev {
 
 enum { PREC_FP64 = 0, PREC_FP64_TILED = 1, PREC_FP32C = 2 };
 
+/* Launch shape of the pair kernel: WG threads = (WG/64/wj) waves on distinct
+ * targets x wj waves splitting each j-tile; ipl targets per lane; split = 1
+ * for hi/lo positions (FP32C only). One work item covers 64*ipl*WG/64/wj
+ * target spheres. */
+struct Shape {
+    int wg, wj, ipl, split;
+};
+
 /* kernel launchers (ad_kernels.hip) */
 hipError_t launch_set_step(const Dev& d, long long value, hipStream_t s);
 hipError_t launch_clear_flag(const Dev& d, hipStream_t s);
@@ -76,7 +84,7 @@ hipError_t launch_pack_apply(const Dev& d, const Coef& c, int prec, const double
 /* forces at caller positions (AoS) and time (st, ct), spring + steric */
 hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xaos, double st, double ct,
                          double* Faos, hipStream_t s);
-hipError_t launch_pairs(const Dev& d, int prec, int wg, int ipl, int bump, hipStream_t s);
+hipError_t launch_pairs(const Dev& d, int prec, const Shape& sh, int bump, hipStream_t s);
 /* epilogue of a step stage (integrator, stage) or of a mobility apply (u != NULL) */
 hipError_t launch_epilogue(const Dev& d, const Coef& c, int prec, int integrator, int stage,
                            int pack_next, double* u_aos, hipStream_t s);

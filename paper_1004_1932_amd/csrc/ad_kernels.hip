@@ -91,6 +91,16 @@ __device__ __forceinline__ void split_f32(double v, float& hi, float& lo) {
     lo = (float)(v - (double)hi);
 }
 
+/* (hi, lo) += v with TwoSum: hi + lo keeps the exact sum up to the rounding
+ * of lo. */
+__device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float v) {
+    const float s = hi + v;
+    const float bb = s - hi;
+    const float e = (hi - (s - bb)) + (v - bb);
+    hi = s;
+    lo = lo + e;
+}
+
 /* Write the pair-kernel pack and the self (+partner) velocity u0 of the two
  * spheres of one dumbbell at positions y0, y1 with forces f0, f1. */
 __device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const double y0[3],
@@ -238,20 +248,37 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
 
 /* ------------------------------------------------------------ pair sums */
 
-/* FP32C: positions as hi + lo floats, r = (hi_i - hi_j) + (lo_i - lo_j);
- * pair math in FP32 with the hardware reciprocal square root; the terms of
- * one LDS tile are summed in FP32 and the tile sum is added to a (hi, lo)
- * accumulator with TwoSum. The dumbbell's own two spheres are skipped (their
- * terms are in u0, in FP64). */
-template <int WG, int IPL>
+/* FP32C pair sum. A work-group of WG threads is WI x WJ waves: WI waves own
+ * different target spheres (IPL consecutive spheres per lane), and the WJ
+ * waves that share the same targets take interleaved quarters of every
+ * j-tile. A tile of WG source spheres is staged through LDS once and read as
+ * broadcasts.
+ *   SPLIT = 1: positions are hi + lo floats, r = (hi_i - hi_j) + (lo_i - lo_j)
+ *              (r rounded relative to itself).
+ *   SPLIT = 0: positions are single floats, r = x_i - x_j (error ~ eps |x|).
+ * Pair math in FP32 with the hardware reciprocal square root. Each wave sums
+ * the terms of one tile in FP32 and adds that tile sum to a (hi, lo)
+ * accumulator with TwoSum; the WJ waves' accumulators are combined in LDS
+ * in a fixed order. The dumbbell's own two spheres are skipped (their terms
+ * are in u0, in FP64). */
+template <int WG, int IPL, int WJ, int SPLIT>
 __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
-    __shared__ float4 sA[WG];
-    __shared__ float4 sB[WG];
-    __shared__ float sC[WG];
+    constexpr int WI = WG / 64 / WJ;
+    constexpr int TJ = WG;          /* j per LDS tile */
+    constexpr int JW = TJ / WJ;     /* j per wave per tile */
+    __shared__ float4 sA[TJ];
+    __shared__ float4 sB[TJ];
+    __shared__ float sC[TJ];
+    __shared__ float red[WJ > 1 ? WJ : 1][WI * 64 * IPL][6];
     const Item it = d.items[blockIdx.x];
     if (bump && blockIdx.x == 0 && threadIdx.x == 0) d.ctl->step = d.ctl->step + 1;
     const int t = threadIdx.x;
-    const int ib = it.i0 + t * IPL;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int wi = wave % WI;
+    const int wj = wave / WI;
+    const int slot = wi * 64 + lane;          /* target slot inside the block */
+    const int ib = it.i0 + slot * IPL;
     const int iend = it.i0 + it.ni;
 
     float hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
@@ -268,7 +295,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
             B = d.pB[i];
         }
         hx[q] = A.x; hy[q] = A.y; hz[q] = A.z;
-        lx[q] = B.x; ly[q] = B.y; lz[q] = B.z;
+        lx[q] = SPLIT ? B.x : 0.f; ly[q] = SPLIT ? B.y : 0.f; lz[q] = SPLIT ? B.z : 0.f;
         ax[q] = ay[q] = az[q] = 0.f;
         bx[q] = by[q] = bz[q] = 0.f;
         px[q] = py[q] = pz[q] = 0.f;
@@ -278,8 +305,8 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
     const int dhi = (iend + 1) & ~1;
     const int jend = it.j0 + it.nj;
 
-    for (int t0 = it.j0; t0 < jend; t0 += WG) {
-        const int n = min(WG, jend - t0);
+    for (int t0 = it.j0; t0 < jend; t0 += TJ) {
+        const int n = min(TJ, jend - t0);
         float4 A, B;
         float C;
         if (t < n) {
@@ -298,9 +325,11 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
         sC[t] = C;
         __syncthreads();
         const bool diag = (t0 < dhi) && (t0 + n > dlo);
+        const int jb = wj * JW;                     /* this wave's part of the tile */
+        const int nw = max(0, min(JW, n - jb));
         if (!diag) {
-            const int n4 = (n + 3) & ~3;
-            for (int jj = 0; jj < n4; jj += 4) {
+            const int n4 = (nw + 3) & ~3;
+            for (int jj = jb; jj < jb + n4; jj += 4) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const float4 Aj = sA[jj + u];
@@ -308,9 +337,16 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
                     const float Fz = sC[jj + u];
 #pragma unroll
                     for (int q = 0; q < IPL; ++q) {
-                        float rx = (hx[q] - Aj.x) + (lx[q] - Bj.x);
-                        float ry = (hy[q] - Aj.y) + (ly[q] - Bj.y);
-                        float rz = (hz[q] - Aj.z) + (lz[q] - Bj.z);
+                        float rx, ry, rz;
+                        if (SPLIT) {
+                            rx = (hx[q] - Aj.x) + (lx[q] - Bj.x);
+                            ry = (hy[q] - Aj.y) + (ly[q] - Bj.y);
+                            rz = (hz[q] - Aj.z) + (lz[q] - Bj.z);
+                        } else {
+                            rx = hx[q] - Aj.x;
+                            ry = hy[q] - Aj.y;
+                            rz = hz[q] - Aj.z;
+                        }
                         float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                         float ir = __builtin_amdgcn_rsqf(r2);
                         float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Bj.w, rx * Aj.w));
@@ -322,16 +358,23 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
                 }
             }
         } else {
-            for (int jj = 0; jj < n; ++jj) {
+            for (int jj = jb; jj < jb + nw; ++jj) {
                 const float4 Aj = sA[jj];
                 const float4 Bj = sB[jj];
                 const float Fz = sC[jj];
                 const int dj = (t0 + jj) >> 1;
 #pragma unroll
                 for (int q = 0; q < IPL; ++q) {
-                    float rx = (hx[q] - Aj.x) + (lx[q] - Bj.x);
-                    float ry = (hy[q] - Aj.y) + (ly[q] - Bj.y);
-                    float rz = (hz[q] - Aj.z) + (lz[q] - Bj.z);
+                    float rx, ry, rz;
+                    if (SPLIT) {
+                        rx = (hx[q] - Aj.x) + (lx[q] - Bj.x);
+                        ry = (hy[q] - Aj.y) + (ly[q] - Bj.y);
+                        rz = (hz[q] - Aj.z) + (lz[q] - Bj.z);
+                    } else {
+                        rx = hx[q] - Aj.x;
+                        ry = hy[q] - Aj.y;
+                        rz = hz[q] - Aj.z;
+                    }
                     float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                     float ir = (dj == dq[q]) ? 0.f : __builtin_amdgcn_rsqf(r2);
                     float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Bj.w, rx * Aj.w));
@@ -345,11 +388,32 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
         /* TwoSum of the tile partial into (hi, lo) */
 #pragma unroll
         for (int q = 0; q < IPL; ++q) {
-            float s, bb, e;
-            s = ax[q] + px[q]; bb = s - ax[q]; e = (ax[q] - (s - bb)) + (px[q] - bb); ax[q] = s; bx[q] = bx[q] + e;
-            s = ay[q] + py[q]; bb = s - ay[q]; e = (ay[q] - (s - bb)) + (py[q] - bb); ay[q] = s; by[q] = by[q] + e;
-            s = az[q] + pz[q]; bb = s - az[q]; e = (az[q] - (s - bb)) + (pz[q] - bb); az[q] = s; bz[q] = bz[q] + e;
+            two_sum_acc(ax[q], bx[q], px[q]);
+            two_sum_acc(ay[q], by[q], py[q]);
+            two_sum_acc(az[q], bz[q], pz[q]);
             px[q] = py[q] = pz[q] = 0.f;
+        }
+    }
+    if (WJ > 1) {
+        /* combine the WJ waves that share these targets, in wave order */
+        if (wj > 0) {
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) {
+                float* r = red[wj][slot * IPL + q];
+                r[0] = ax[q]; r[1] = bx[q]; r[2] = ay[q]; r[3] = by[q]; r[4] = az[q]; r[5] = bz[q];
+            }
+        }
+        __syncthreads();
+        if (wj != 0) return;
+#pragma unroll
+        for (int w = 1; w < WJ; ++w) {
+#pragma unroll
+            for (int q = 0; q < IPL; ++q) {
+                const float* r = red[w][slot * IPL + q];
+                two_sum_acc(ax[q], bx[q], r[0]); bx[q] = bx[q] + r[1];
+                two_sum_acc(ay[q], by[q], r[2]); by[q] = by[q] + r[3];
+                two_sum_acc(az[q], bz[q], r[4]); bz[q] = bz[q] + r[5];
+            }
         }
     }
     const long long base = d.sys_pbase[it.sys] + (long long)it.c * 3 * it.Nb;
@@ -452,36 +516,54 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, int bump) {
 
 /* ------------------------------------------------------------ epilogue */
 
-__global__ void k_epilogue(Dev d, Coef c, int prec, int integrator, int stage, int pack_next,
-                           double* __restrict__ u_aos) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= d.Stot) return;
+/* Two phases in one block of 192 threads (32 dumbbells): first one thread
+ * per sphere component sums that component's j-chunk partials in chunk
+ * order (loads issued eight at a time) and forms k = u0 + kappa*acc; then one
+ * thread per dumbbell updates the RK state and evaluates the next forces. */
+__global__ __launch_bounds__(192) void k_epilogue(Dev d, Coef c, int prec, int integrator, int stage,
+                                                  int pack_next, double* __restrict__ u_aos) {
+    __shared__ double kvs[64][3];
+    __shared__ int badf;
     const int N = d.Ntot;
-    const int b = d.dsys[s];
-    const int off = d.sys_off[b];
-    const int Nb = d.sys_off[b + 1] - off;
-    const int P = d.sys_P[b];
-    const long long pb = d.sys_pbase[b];
-    const int i0 = 2 * s;
-    double kv[2][3];
-    int bad = 0;
-    for (int h = 0; h < 2; ++h) {
-        const int li = i0 + h - off;
-        for (int a = 0; a < 3; ++a) {
-            const double* p = d.part + pb + (long long)a * Nb + li;
+    const int t = threadIdx.x;
+    if (t == 0) badf = 0;
+    __syncthreads();
+    {
+        const int sl = t / 3, a = t - 3 * (t / 3);
+        const int i = blockIdx.x * 64 + sl;
+        if (i < N) {
+            const int b = d.dsys[i >> 1];
+            const int off = d.sys_off[b];
+            const int Nb = d.sys_off[b + 1] - off;
+            const int P = d.sys_P[b];
+            const long long stride = 3LL * Nb;
+            const double* p = d.part + d.sys_pbase[b] + (long long)a * Nb + (i - off);
             double acc = p[0];
-            for (int cc = 1; cc < P; ++cc) acc = acc + p[(long long)cc * 3 * Nb];
-            double v = d.U0[a * N + i0 + h] + c.co * acc;
-            kv[h][a] = v;
-            bad |= !isfinite(v);
+            for (int cc = 1; cc < P; cc += 8) {
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = (cc + q < P) ? p[(cc + q) * stride] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (cc + q < P) acc = acc + v[q];
+            }
+            const double v = d.U0[a * N + i] + c.co * acc;
+            if (!isfinite(v)) badf = 1;
+            if (u_aos)
+                u_aos[3 * i + a] = v;
+            else
+                kvs[sl][a] = v;
         }
     }
-    if (bad) d.ctl->flag = 1;
-    if (u_aos) {
-        for (int h = 0; h < 2; ++h)
-            for (int a = 0; a < 3; ++a) u_aos[3 * (i0 + h) + a] = kv[h][a];
-        return;
-    }
+    __syncthreads();
+    if (t == 0 && badf) d.ctl->flag = 1;
+    if (u_aos || t >= 32) return;
+    const int s = blockIdx.x * 32 + t;
+    if (s >= d.Stot) return;
+    const int i0 = 2 * s;
+    double kv[2][3];
+    for (int h = 0; h < 2; ++h)
+        for (int a = 0; a < 3; ++a) kv[h][a] = kvs[2 * t + h][a];
     double y[2][3];
     for (int h = 0; h < 2; ++h) {
         const int i = i0 + h;
@@ -625,36 +707,51 @@ hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xa, double s
     return hipGetLastError();
 }
 
-template <int WG, int IPL>
-static hipError_t pairs_t(const Dev& d, int prec, int bump, hipStream_t s) {
-    if (prec == PREC_FP32C) {
-        hipLaunchKernelGGL((k_pairs_f32c<WG, IPL>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
-    } else {
-        /* the FP64 kernel exists for 1 and 2 targets per lane; the work list
-         * was built for this IPL, so a wider one is refused, not narrowed */
-        if constexpr (IPL > 2) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((k_pairs_f64<WG, IPL>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
-    }
+template <int WG, int IPL, int WJ, int SPLIT>
+static hipError_t f32c_t(const Dev& d, int bump, hipStream_t s) {
+    hipLaunchKernelGGL((k_pairs_f32c<WG, IPL, WJ, SPLIT>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
     return hipGetLastError();
 }
 
-hipError_t launch_pairs(const Dev& d, int prec, int wg, int ipl, int bump, hipStream_t s) {
+template <int WG, int WJ, int SPLIT>
+static hipError_t f32c_ipl(const Dev& d, int ipl, int bump, hipStream_t s) {
+    if (ipl == 1) return f32c_t<WG, 1, WJ, SPLIT>(d, bump, s);
+    if (ipl == 2) return f32c_t<WG, 2, WJ, SPLIT>(d, bump, s);
+    if (ipl == 4) return f32c_t<WG, 4, WJ, SPLIT>(d, bump, s);
+    return hipErrorInvalidValue;
+}
+
+template <int WG, int IPL>
+static hipError_t f64_t(const Dev& d, int bump, hipStream_t s) {
+    hipLaunchKernelGGL((k_pairs_f64<WG, IPL>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(const Dev& d, int prec, const Shape& sh, int bump, hipStream_t s) {
     if (d.nitems <= 0) return hipSuccess;
-    if (wg == 64) {
-        if (ipl == 1) return pairs_t<64, 1>(d, prec, bump, s);
-        if (ipl == 2) return pairs_t<64, 2>(d, prec, bump, s);
-        if (ipl == 4) return pairs_t<64, 4>(d, prec, bump, s);
-    } else if (wg == 256) {
-        if (ipl == 1) return pairs_t<256, 1>(d, prec, bump, s);
-        if (ipl == 2) return pairs_t<256, 2>(d, prec, bump, s);
-        if (ipl == 4) return pairs_t<256, 4>(d, prec, bump, s);
+    if (prec == PREC_FP32C) {
+        const bool sp = sh.split != 0;
+        if (sh.wg == 64 && sh.wj == 1)
+            return sp ? f32c_ipl<64, 1, 1>(d, sh.ipl, bump, s) : f32c_ipl<64, 1, 0>(d, sh.ipl, bump, s);
+        if (sh.wg == 256 && sh.wj == 1)
+            return sp ? f32c_ipl<256, 1, 1>(d, sh.ipl, bump, s) : f32c_ipl<256, 1, 0>(d, sh.ipl, bump, s);
+        if (sh.wg == 256 && sh.wj == 4)
+            return sp ? f32c_ipl<256, 4, 1>(d, sh.ipl, bump, s) : f32c_ipl<256, 4, 0>(d, sh.ipl, bump, s);
+        return hipErrorInvalidValue;
     }
+    /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group; the
+     * work list was built for this shape, so anything else is refused */
+    if (sh.wj != 1) return hipErrorInvalidValue;
+    if (sh.wg == 64 && sh.ipl == 1) return f64_t<64, 1>(d, bump, s);
+    if (sh.wg == 64 && sh.ipl == 2) return f64_t<64, 2>(d, bump, s);
+    if (sh.wg == 256 && sh.ipl == 1) return f64_t<256, 1>(d, bump, s);
+    if (sh.wg == 256 && sh.ipl == 2) return f64_t<256, 2>(d, bump, s);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_epilogue(const Dev& d, const Coef& c, int prec, int integrator, int stage, int pack_next,
                            double* u_aos, hipStream_t s) {
-    hipLaunchKernelGGL(k_epilogue, blocks_for(d.Stot, 128), dim3(128), 0, s, d, c, prec, integrator, stage,
+    hipLaunchKernelGGL(k_epilogue, blocks_for(d.Ntot, 64), dim3(192), 0, s, d, c, prec, integrator, stage,
                        pack_next, u_aos);
     return hipGetLastError();
 }

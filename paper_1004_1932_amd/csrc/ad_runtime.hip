@@ -107,6 +107,8 @@ static ad_launch default_launch(const ad_ctx* c) {
     ad_launch L{};
     int maxN = 0;
     for (int b = 0; b < c->nsys; ++b) maxN = std::max(maxN, 2 * c->S[b]);
+    L.wj = 1;
+    L.posmode = c->p.precision == AD_FP32C ? AD_POS_HILO : 0;
     if (c->p.precision == AD_FP64) {
         L.ipl = 1;
         L.wg = 64;
@@ -121,11 +123,13 @@ static ad_launch default_launch(const ad_ctx* c) {
     }
     L.wg = 256;
     L.ipl = 1;
-    /* about 1024 work-groups of 4 waves, j-chunks of at least 64 */
-    int blocks = (maxN + L.wg * L.ipl - 1) / (L.wg * L.ipl);
-    int P = std::max(1, 1024 / blocks);
+    if (c->p.precision == AD_FP32C) L.wj = 4;
+    /* about 1024 work-groups of 4 waves; j-chunks a multiple of the tile */
+    const int IB = L.ipl * L.wg / L.wj;
+    const int blocks = (maxN + IB - 1) / IB;
+    const int P = std::max(1, 1024 / blocks);
     int jc = (maxN + P - 1) / P;
-    jc = std::max(64, (jc + 63) / 64 * 64);
+    jc = std::max(L.wg, (jc + L.wg - 1) / L.wg * L.wg);
     L.jchunk = jc;
     return L;
 }
@@ -133,11 +137,23 @@ static ad_launch default_launch(const ad_ctx* c) {
 static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (L.wg != 64 && L.wg != 256) return fail(c, AD_EINVAL, "launch.wg must be 64 or 256 (got %d)", L.wg);
     if (L.ipl != 1 && L.ipl != 2 && L.ipl != 4) return fail(c, AD_EINVAL, "launch.ipl must be 1, 2 or 4");
-    if (c->p.precision != AD_FP32C && L.ipl > 2)
-        return fail(c, AD_EINVAL, "FP64 modes support ipl 1 or 2");
+    if (L.wj != 1 && !(L.wj == 4 && L.wg == 256 && c->p.precision == AD_FP32C))
+        return fail(c, AD_EINVAL, "launch.wj must be 1, or 4 with wg 256 in AD_FP32C");
+    if (c->p.precision != AD_FP32C && L.ipl > 2) return fail(c, AD_EINVAL, "FP64 modes support ipl 1 or 2");
+    if (c->p.precision == AD_FP32C && L.posmode != AD_POS_HILO && L.posmode != AD_POS_SINGLE)
+        return fail(c, AD_EINVAL, "launch.posmode must be AD_POS_HILO or AD_POS_SINGLE");
     if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
     if (L.reserved != 0) return fail(c, AD_EINVAL, "launch.reserved must be 0");
     return AD_OK;
+}
+
+static ad::Shape shape_of(const ad_ctx* c) {
+    ad::Shape sh;
+    sh.wg = c->launch.wg;
+    sh.wj = c->launch.wj;
+    sh.ipl = c->launch.ipl;
+    sh.split = c->launch.posmode == AD_POS_HILO ? 1 : 0;
+    return sh;
 }
 
 static void build_items(ad_ctx* c) {
@@ -146,7 +162,7 @@ static void build_items(ad_ctx* c) {
     c->sysP.assign(c->nsys, 1);
     c->pbase.assign(c->nsys, 0);
     long long pb = 0;
-    const int IB = L.wg * L.ipl;
+    const int IB = L.ipl * L.wg / L.wj;
     for (int b = 0; b < c->nsys; ++b) {
         const int Nb = 2 * c->S[b];
         const int jc = (c->p.precision == AD_FP64) ? Nb : std::min(L.jchunk, Nb);
@@ -333,7 +349,7 @@ static int profile_flush(ad_ctx* c) {
 
 static int launch_pairs_timed(ad_ctx* c, int prec, int bump, hipStream_t st) {
     if (!c->profile) {
-        HIPCHECK(c, ad::launch_pairs(c->dev, prec, c->launch.wg, c->launch.ipl, bump, st));
+        HIPCHECK(c, ad::launch_pairs(c->dev, prec, shape_of(c), bump, st));
         return AD_OK;
     }
     if (c->ev.empty()) {
@@ -345,7 +361,7 @@ static int launch_pairs_timed(ad_ctx* c, int prec, int bump, hipStream_t st) {
         if (rc != AD_OK) return rc;
     }
     HIPCHECK(c, hipEventRecord(c->ev[2 * c->ev_used], st));
-    HIPCHECK(c, ad::launch_pairs(c->dev, prec, c->launch.wg, c->launch.ipl, bump, st));
+    HIPCHECK(c, ad::launch_pairs(c->dev, prec, shape_of(c), bump, st));
     HIPCHECK(c, hipEventRecord(c->ev[2 * c->ev_used + 1], st));
     c->ev_used += 1;
     return AD_OK;
@@ -534,6 +550,8 @@ int ad_set_launch(ad_ctx* c, const ad_launch* L) {
     if (want.ipl == 0) want.ipl = def.ipl;
     if (want.wg == 0) want.wg = def.wg;
     if (want.jchunk == 0) want.jchunk = def.jchunk;
+    if (want.wj == 0) want.wj = (want.wg == def.wg) ? def.wj : 1;
+    if (want.posmode == 0) want.posmode = def.posmode;
     int rc = validate_launch(c, want);
     if (rc != AD_OK) return rc;
     ad_launch old = c->launch;
@@ -610,7 +628,7 @@ int ad_mobility_apply(ad_ctx* c, const double* X, const double* F, double* u, vo
     hipStream_t st = as_stream(stream);
     const int prec = prec_of(c);
     HIPCHECK(c, ad::launch_pack_apply(c->dev, c->coef, prec, X, F, st));
-    HIPCHECK(c, ad::launch_pairs(c->dev, prec, c->launch.wg, c->launch.ipl, 0, st));
+    HIPCHECK(c, ad::launch_pairs(c->dev, prec, shape_of(c), 0, st));
     HIPCHECK(c, ad::launch_epilogue(c->dev, c->coef, prec, c->p.integrator, 0, 0, u, st));
     return AD_OK;
 }

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     # 9 doubles + 4 int32 / 4 int32
     assert C.sizeof(B.ad_params) == 9 * 8 + 4 * 4
-    assert C.sizeof(B.ad_launch) == 16
+    assert C.sizeof(B.ad_launch) == 24
 
 
 @pytest.mark.parametrize("bad", [dict(a=0.0), dict(eta=-1.0), dict(T=0.0), dict(dt=float("nan")),
@@ -87,10 +87,11 @@ def test_launch_shapes_and_workspace_size():
         P.ad_set_launch(ctx, ipl=4, jchunk=4096, wg=256)
         one_chunk = P.ad_workspace_size(ctx)
         P.ad_set_launch(ctx, ipl=4, jchunk=64, wg=256)
-        assert P.ad_get_launch(ctx) == {"ipl": 4, "jchunk": 64, "wg": 256}
+        assert P.ad_get_launch(ctx) == {"ipl": 4, "jchunk": 64, "wg": 256, "wj": 4, "posmode": 1}
         # 64 j-chunks hold 64 partial sums per sphere instead of one
         assert P.ad_workspace_size(ctx) - one_chunk >= 63 * 3 * 4096 * 8
-        for bad in (dict(ipl=3), dict(wg=128), dict(jchunk=32)):
+        for bad in (dict(ipl=3), dict(wg=128), dict(jchunk=32), dict(wg=256, wj=2), dict(wg=64, wj=4),
+                    dict(posmode=3)):
             with pytest.raises(P.ADError):
                 P.ad_set_launch(ctx, **bad)
     finally:
@@ -99,6 +100,8 @@ def test_launch_shapes_and_workspace_size():
     try:
         with pytest.raises(P.ADError):
             P.ad_set_launch(ctx, ipl=4)
+        with pytest.raises(P.ADError):
+            P.ad_set_launch(ctx, wg=256, wj=4)
     finally:
         P.ad_destroy(ctx)
 
