@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--counter-probe", action="store_true",
+                    help="for rocprofv3 --pmc runs: a few steps plus one plain 256 MiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -87,8 +89,22 @@ def main():
     N, S = sus.N, sus.S
     pairs_per_step = 4.0 * N * (N - 1)
 
+    if args.counter_probe:
+        # a known-size copy calibrates FETCH_SIZE / WRITE_SIZE against bytes
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        src.uniform_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        sim = P.Simulator(sus.params, [S], precision="fp32c", launch="tuned")
+        sim.set_state(sus.X, sus.phi)
+        sim.step(3)
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_probe": True, "copy_bytes": src.numel() * 8, "launch": sim.launch}), flush=True)
+        return
+
     # FP32-compensated path, graph-replayed steps
-    sim = P.Simulator(sus.params, [S], precision="fp32c", graph=not args.no_graph)
+    sim = P.Simulator(sus.params, [S], precision="fp32c", graph=not args.no_graph, launch="tuned")
     sim.set_state(sus.X, sus.phi)
     log(f"fp32c launch {sim.launch}")
     secs, wall = time_steps(sim, args.steps, args.warmup)

@@ -47,6 +47,9 @@ extern "C" {
 #define AD_EDEVICE (-3)    /* HIP runtime error */
 #define AD_ESTATE (-4)     /* call out of order (no workspace or no state) */
 #define AD_ENONFINITE (-5) /* non-finite velocity or coincident spheres */
+#define AD_ERANGE (-6)     /* AD_FP32C steric path: more than 16 spheres within 1.5 steric_r
+                              of one sphere, or a sphere moved more than steric_r/4 in one
+                              stage (the candidate lists would be incomplete) */
 
 /* arithmetic of the pair sum (ad_params.precision) */
 #define AD_FP64 0      /* FP64, ascending j, no FMA: bitwise equal to a plain
@@ -146,11 +149,12 @@ int ad_step(ad_ctx* ctx, int64_t nsteps, void* stream);
  * each system's mean sphere position to com[r] (device [nrec][nsys][3]),
  * nrec = nsteps / record_every. Either pointer may be NULL. Synchronises the
  * stream at the end and returns AD_ENONFINITE if a non-finite velocity or a
- * coincident sphere pair was met since ad_set_state. */
+ * coincident sphere pair was met since ad_set_state (AD_ERANGE for the
+ * steric candidate conditions above). */
 int ad_run(ad_ctx* ctx, int64_t nsteps, int32_t record_every, double* centres, double* com,
            void* stream);
 
-/* Synchronise the stream and report the non-finite flag (AD_OK or AD_ENONFINITE). */
+/* Synchronise the stream and report the flags (AD_OK, AD_ENONFINITE or AD_ERANGE). */
 int ad_check(ad_ctx* ctx, void* stream);
 
 /* Capture one step into a HIP graph and replay it for ad_step/ad_run

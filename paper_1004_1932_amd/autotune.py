@@ -1,0 +1,158 @@
+"""Autotuner for the pair-kernel launch shape.
+
+For a given set of system sizes it tries launch shapes (targets per lane,
+j-chunk, work-group size, waves per j-tile, position split), rejects every
+shape whose FP32C velocities differ from the library's own FP64 path by more
+than an error gate, and keeps the one with the shortest graph-replayed RK4
+step. Results are stored per size bucket in a JSON table that
+`Simulator(..., launch="tuned")` reads.
+"""
+from __future__ import annotations
+
+import json
+import math
+from pathlib import Path
+
+import numpy as np
+
+from . import binding as B
+
+TABLE = Path(__file__).resolve().parent / "tuning_gfx950.json"
+
+
+def bucket_key(S_per_sys) -> str:
+    """Size bucket of a workload: one system by N rounded to a power of two,
+    an ensemble by the power-of-two bucket of its largest system."""
+    S = np.asarray(S_per_sys).reshape(-1)
+    n = int(2 * S.max())
+    p2 = 1 << max(0, math.ceil(math.log2(max(n, 1))))
+    return f"{'single' if len(S) == 1 else 'ensemble'}:N<={p2}"
+
+
+def load_table(path: Path = TABLE) -> dict:
+    if path.exists():
+        return json.loads(path.read_text())
+    return {}
+
+
+def tuned_launch(S_per_sys, path: Path = TABLE):
+    return load_table(path).get(bucket_key(S_per_sys), {}).get("launch")
+
+
+def candidates(N: int, ensemble: bool):
+    out = []
+    for posmode in (B.AD_POS_HILO, B.AD_POS_SINGLE):
+        if ensemble or N < 1024:
+            for ipl in (1, 2):
+                for jc in (128, 256, 512):
+                    out.append(dict(wg=64, wj=1, ipl=ipl, jchunk=jc, posmode=posmode))
+            for jc in (256, 512):
+                out.append(dict(wg=256, wj=4, ipl=1, jchunk=jc, posmode=posmode))
+            continue
+        # j-chunks from 256 up to a size that leaves about 256 work-groups
+        top = max(256, min(N, 256 * (1 << max(0, math.ceil(math.log2(max(1.0, N * N / (64 * 256 * 256))))))))
+        for ipl in (1, 2, 4):
+            jc = 256
+            while jc <= top:
+                out.append(dict(wg=256, wj=4, ipl=ipl, jchunk=jc, posmode=posmode))
+                jc *= 2
+        for ipl in (1, 2):
+            out.append(dict(wg=256, wj=1, ipl=ipl, jchunk=256, posmode=posmode))
+    uniq = []
+    for c in out:
+        if c not in uniq:
+            uniq.append(c)
+    return uniq
+
+
+def _relerr(u, ref):
+    import torch
+    return float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref))
+
+
+def _step_time(sim, steps: int) -> float:
+    import torch
+    sim.step(max(2, steps // 10))
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    sim.step(steps)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def tune(params, S_per_sys, X, phi, gate: float = 5e-7, steps: int = 50, cands=None, verbose=False) -> dict:
+    """Tune on the state (X, phi). Returns {"launch", "ms_per_step", "err",
+    "tried"}. The reference velocities come from AD_FP64_TILED at the same
+    state, forces from ad_forces."""
+    import torch
+    S_per_sys = np.asarray(S_per_sys, dtype=np.int32).reshape(-1)
+    ref = B.Simulator(params, S_per_sys, precision="fp64_tiled")
+    ref.set_state(X, phi)
+    Xd = torch.as_tensor(X, dtype=torch.float64, device=ref.device).contiguous()
+    F = ref.forces(Xd, 0.37 * params.T)
+    u_ref = ref.mobility(Xd, F)
+    ref.close()
+    sim = B.Simulator(params, S_per_sys, precision="fp32c", graph=True)
+    sim.set_state(X, phi)
+    N = int(2 * S_per_sys.max())
+    tried = []
+    best = None
+    for c in (cands or candidates(N, len(S_per_sys) > 1)):
+        try:
+            sim.set_launch(**c)
+        except B.ADError as e:
+            tried.append({"launch": c, "error": str(e)})
+            continue
+        sim.set_state(X, phi)
+        err = _relerr(sim.mobility(Xd, F), u_ref)
+        rec = {"launch": sim.launch, "err": err}
+        if err <= gate:
+            rec["ms_per_step"] = _step_time(sim, steps)
+            if best is None or rec["ms_per_step"] < best["ms_per_step"]:
+                best = rec
+        tried.append(rec)
+        if verbose:
+            print(json.dumps(rec), flush=True)
+    sim.close()
+    if best is None:
+        raise RuntimeError("no launch shape met the error gate")
+    return {"launch": best["launch"], "ms_per_step": best["ms_per_step"], "err": best["err"],
+            "gate": gate, "tried": tried}
+
+
+def store(S_per_sys, result: dict, path: Path = TABLE) -> None:
+    table = load_table(path)
+    table[bucket_key(S_per_sys)] = {k: result[k] for k in ("launch", "ms_per_step", "err", "gate")}
+    path.write_text(json.dumps(table, indent=1, sort_keys=True) + "\n")
+
+
+def main(argv=None):
+    """Tune named synthetic workloads and write the table:
+    python -m paper_1004_1932_amd.autotune --workload n4096 --out table.json"""
+    import argparse
+    import sys
+
+    sys.path.insert(0, str(Path(__file__).resolve().parents[1]))
+    from workload import make_preset
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", action="append", required=True)
+    ap.add_argument("--out", default=str(TABLE))
+    ap.add_argument("--gate", type=float, default=5e-7)
+    ap.add_argument("--steps", type=int, default=50)
+    args = ap.parse_args(argv)
+    for name in args.workload:
+        w = make_preset(name)
+        sizes = getattr(w, "S_per_sys", None)
+        sizes = [w.S] if sizes is None else sizes
+        print(f"tuning {name}", flush=True)
+        res = tune(w.params, sizes, w.X, w.phi, gate=args.gate, steps=args.steps, verbose=True)
+        store(sizes, res, Path(args.out))
+        print(json.dumps({"workload": name, "launch": res["launch"], "ms_per_step": res["ms_per_step"],
+                          "err": res["err"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -13,7 +13,7 @@ import numpy as np
 
 LIB_PATH = Path(__file__).resolve().parent / "libad.so"
 
-AD_OK, AD_EINVAL, AD_ENOMEM, AD_EDEVICE, AD_ESTATE, AD_ENONFINITE = 0, -1, -2, -3, -4, -5
+AD_OK, AD_EINVAL, AD_ENOMEM, AD_EDEVICE, AD_ESTATE, AD_ENONFINITE, AD_ERANGE = 0, -1, -2, -3, -4, -5, -6
 AD_FP64, AD_FP64_TILED, AD_FP32C = 0, 1, 2
 AD_RK4, AD_HEUN = 0, 1
 AD_OSEEN = 0
@@ -184,18 +184,18 @@ def ad_step(ctx, nsteps, stream=None) -> None:
 
 
 def ad_run(ctx, nsteps, record_every, centres=None, com=None, stream=None) -> int:
-    """Returns AD_OK, or AD_ENONFINITE (not raised) when the flag was set."""
+    """Returns AD_OK, or AD_ENONFINITE / AD_ERANGE (not raised) when a flag was set."""
     cp = _dev(centres, "centres") if centres is not None else None
     mp = _dev(com, "com") if com is not None else None
     code = lib().ad_run(ctx, int(nsteps), int(record_every), cp, mp, _stream(stream))
-    if code == AD_ENONFINITE:
+    if code in (AD_ENONFINITE, AD_ERANGE):
         return code
     return _check(code, ctx)
 
 
 def ad_check(ctx, stream=None) -> int:
     code = lib().ad_check(ctx, _stream(stream))
-    if code == AD_ENONFINITE:
+    if code in (AD_ENONFINITE, AD_ERANGE):
         return code
     return _check(code, ctx)
 
@@ -223,11 +223,28 @@ def ad_last_error(ctx=None) -> str:
 
 # ---------------------------------------------------------------- owner of a context
 
+class torch_device:
+    """Make `device` current while a context binds its workspace."""
+
+    def __init__(self, device):
+        self.device = device
+
+    def __enter__(self):
+        import torch
+        self._ctx = torch.cuda.device(self.device)
+        return self._ctx.__enter__()
+
+    def __exit__(self, *a):
+        return self._ctx.__exit__(*a)
+
+
 class Simulator:
     """A context plus its workspace tensor on one device."""
 
     def __init__(self, params, S_per_sys, precision="fp32c", integrator="rk4", device="cuda:0",
                  launch=None, graph=False):
+        """launch: None (library default), a dict of ad_launch fields, or
+        "tuned" (the autotuned shape for this size bucket, if any)."""
         import torch
         self.device = torch.device(device)
         self.S_per_sys = np.asarray(S_per_sys, dtype=np.int32).reshape(-1)
@@ -235,13 +252,24 @@ class Simulator:
         self.Stot = int(self.S_per_sys.sum())
         self.N = 2 * self.Stot
         self._p = make_params(params, precision, integrator)
-        self.ctx = ad_create(self._p, self.S_per_sys)
+        self._graph = bool(graph)
+        if launch == "tuned":
+            from .autotune import tuned_launch
+            launch = tuned_launch(self.S_per_sys) if self._p.precision == AD_FP32C else None
+        self.ctx = None
         self.ws = None
-        if launch:
-            ad_set_launch(self.ctx, **launch)
-        self._bind()
-        if graph:
-            ad_use_graph(self.ctx, True)
+        self._create(launch)
+
+    def _create(self, launch):
+        if self.ctx is not None:
+            ad_destroy(self.ctx)
+        with torch_device(self.device):
+            self.ctx = ad_create(self._p, self.S_per_sys)
+            if launch:
+                ad_set_launch(self.ctx, **launch)
+            self._bind()
+            if self._graph:
+                ad_use_graph(self.ctx, True)
 
     def _bind(self):
         import torch
@@ -250,7 +278,15 @@ class Simulator:
         ad_bind_workspace(self.ctx, self.ws)
 
     def set_launch(self, **kw):
-        ad_set_launch(self.ctx, **kw)
+        """Change the launch shape. If the workspace is too small for it, the
+        context is recreated with a larger one and the state must be set
+        again."""
+        try:
+            ad_set_launch(self.ctx, **kw)
+        except ADError as e:
+            if e.code != AD_ENOMEM:
+                raise
+            self._create(kw)
 
     @property
     def launch(self):

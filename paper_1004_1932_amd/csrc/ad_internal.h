@@ -19,9 +19,19 @@ struct Item {
 /* Device control block at the start of the workspace. */
 struct Ctl {
     long long step; /* index of the step in flight (bumped by stage 0) */
-    int flag;       /* non-zero once a non-finite velocity was met */
+    int flag;       /* FLAG_* bits, sticky until cleared */
     int pad[13];
 };
+
+enum {
+    FLAG_NONFINITE = 1, /* non-finite velocity or coincident spheres */
+    FLAG_NBR_FULL = 2,  /* steric candidate list of a sphere overflowed */
+    FLAG_NBR_SKIN = 4,  /* a sphere moved more than half the skin in one stage */
+};
+
+/* steric candidate lists (FP32C): spheres closer than rc + skin at the
+ * previous stage positions, at most NBR_CAP per sphere */
+constexpr int NBR_CAP = 16;
 
 /* Constants of the model, precomputed on the host. */
 struct Coef {
@@ -45,6 +55,10 @@ struct Dev {
     double* U0;         /* [3][Ntot] self (+partner) velocity of the stage */
     double* Y;          /* [3][Ntot] stage positions (steric path only) */
     double* Fs;         /* [3][Ntot] stage forces (steric path only) */
+    int* nbr_cnt;       /* [Ntot] candidate count (FP32C steric path) */
+    int* nbr_idx;       /* [Ntot][NBR_CAP] candidate source spheres */
+    float list_r2;      /* (rc + skin)^2: pairs closer than this are listed */
+    double move2;       /* (skin/2)^2: largest allowed stage displacement squared */
     const double2* phitrig; /* [Stot] (sin phi, cos phi) */
     const int* dsys;    /* [Stot] system of each dumbbell */
     const int* sys_off; /* [nsys+1] sphere offsets */
@@ -69,6 +83,7 @@ enum { PREC_FP64 = 0, PREC_FP64_TILED = 1, PREC_FP32C = 2 };
  * target spheres. */
 struct Shape {
     int wg, wj, ipl, split;
+    int steric; /* FP32C: record steric candidates while summing */
 };
 
 /* kernel launchers (ad_kernels.hip) */

@@ -188,7 +188,17 @@ __global__ void k_pack_state(Dev d, Coef c, int prec, double st, double ct) {
         bad |= steric_sum(c, i0 + 1, j0, j1, get, acc, &any);
         if (any)
             for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
-        if (bad) d.ctl->flag = 1;
+        if (bad) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+        /* stage positions (for the displacement check) and empty candidate
+         * lists for the first pair sum */
+        for (int a = 0; a < 3; ++a) {
+            d.Y[a * N + i0] = y0[a];
+            d.Y[a * N + i0 + 1] = y1[a];
+        }
+        if (d.nbr_cnt) {
+            d.nbr_cnt[i0] = 0;
+            d.nbr_cnt[i0 + 1] = 0;
+        }
     }
     store_pack(d, c, prec, i0, y0, y1, f0, f1);
 }
@@ -238,7 +248,7 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
         bad |= steric_sum(c, i0 + 1, j0, j1, get, acc, &any);
         if (any)
             for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
-        if (bad) d.ctl->flag = 1;
+        if (bad) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
     }
     for (int a = 0; a < 3; ++a) {
         Fa[3 * i0 + a] = f0[a];
@@ -247,6 +257,16 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
 }
 
 /* ------------------------------------------------------------ pair sums */
+
+/* append source j to the steric candidate list of target i (i < iend) */
+__device__ __noinline__ void add_candidate(const Dev& d, int i, int iend, int j) {
+    if (i >= iend) return;
+    const int k = atomicAdd(&d.nbr_cnt[i], 1);
+    if (k < NBR_CAP)
+        d.nbr_idx[i * NBR_CAP + k] = j;
+    else
+        atomicOr(&d.ctl->flag, FLAG_NBR_FULL);
+}
 
 /* FP32C pair sum. A work-group of WG threads is WI x WJ waves: WI waves own
  * different target spheres (IPL consecutive spheres per lane), and the WJ
@@ -260,8 +280,11 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
  * the terms of one tile in FP32 and adds that tile sum to a (hi, lo)
  * accumulator with TwoSum; the WJ waves' accumulators are combined in LDS
  * in a fixed order. The dumbbell's own two spheres are skipped (their terms
- * are in u0, in FP64). */
-template <int WG, int IPL, int WJ, int SPLIT>
+ * are in u0, in FP64).
+ *   STERIC = 1: every pair closer than rc + skin (r^2 is at hand) is appended
+ *              to the target's candidate list for the next stage's steric
+ *              forces. */
+template <int WG, int IPL, int WJ, int SPLIT, int STERIC>
 __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
     constexpr int WI = WG / 64 / WJ;
     constexpr int TJ = WG;          /* j per LDS tile */
@@ -348,6 +371,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
                             rz = hz[q] - Aj.z;
                         }
                         float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                        if (STERIC && r2 < d.list_r2) add_candidate(d, ib + q, iend, t0 + jj + u);
                         float ir = __builtin_amdgcn_rsqf(r2);
                         float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Bj.w, rx * Aj.w));
                         float tt = fr * (ir * ir);
@@ -376,6 +400,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
                         rz = hz[q] - Aj.z;
                     }
                     float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                    if (STERIC && r2 < d.list_r2 && t0 + jj != ib + q) add_candidate(d, ib + q, iend, t0 + jj);
                     float ir = (dj == dq[q]) ? 0.f : __builtin_amdgcn_rsqf(r2);
                     float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Bj.w, rx * Aj.w));
                     float tt = fr * (ir * ir);
@@ -509,7 +534,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, int bump) {
             d.part[base + li] = ax[q];
             d.part[base + it.Nb + li] = ay[q];
             d.part[base + 2 * it.Nb + li] = az[q];
-            if (bad) d.ctl->flag = 1;
+            if (bad) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
         }
     }
 }
@@ -556,7 +581,7 @@ __global__ __launch_bounds__(192) void k_epilogue(Dev d, Coef c, int prec, int i
         }
     }
     __syncthreads();
-    if (t == 0 && badf) d.ctl->flag = 1;
+    if (t == 0 && badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
     if (u_aos || t >= 32) return;
     const int s = blockIdx.x * 32 + t;
     if (s >= d.Stot) return;
@@ -608,6 +633,20 @@ __global__ __launch_bounds__(192) void k_epilogue(Dev d, Coef c, int prec, int i
     if (pack_next) {
         store_pack(d, c, prec, i0, y[0], y[1], f0, f1);
     } else {
+        if (d.nbr_cnt) {
+            /* candidate lists are valid while no sphere moves more than half
+             * the skin between stage positions */
+            double m2 = 0.0;
+            for (int h = 0; h < 2; ++h) {
+                double e2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double dd = y[h][a] - d.Y[a * N + i0 + h];
+                    e2 = e2 + dd * dd;
+                }
+                m2 = e2 > m2 ? e2 : m2;
+            }
+            if (!(m2 <= d.move2)) atomicOr(&d.ctl->flag, FLAG_NBR_SKIN);
+        }
         for (int a = 0; a < 3; ++a) {
             d.Y[a * N + i0] = y[0][a];
             d.Y[a * N + i0 + 1] = y[1][a];
@@ -617,7 +656,52 @@ __global__ __launch_bounds__(192) void k_epilogue(Dev d, Coef c, int prec, int i
     }
 }
 
-/* steric forces at the stage positions Y, then the pack */
+/* Steric sum of sphere i over its candidate list (FP32C path). The list holds
+ * every source that was closer than rc + skin at the previous stage; it is
+ * sorted so that the terms are added in ascending j, exactly as the full
+ * sum would add them, and then emptied for the next pair sum. */
+__device__ int steric_list(const Dev& d, const Coef& c, int i, double acc[3], int* any) {
+    const int N = d.Ntot;
+    int n = d.nbr_cnt[i];
+    n = n < NBR_CAP ? n : NBR_CAP; /* an overflow was flagged when it happened */
+    int idx[NBR_CAP];
+    for (int k = 0; k < n; ++k) idx[k] = d.nbr_idx[i * NBR_CAP + k];
+    for (int k = 1; k < n; ++k) { /* insertion sort, n <= NBR_CAP */
+        const int v = idx[k];
+        int m = k - 1;
+        while (m >= 0 && idx[m] > v) {
+            idx[m + 1] = idx[m];
+            --m;
+        }
+        idx[m + 1] = v;
+    }
+    const double xi[3] = {d.Y[i], d.Y[N + i], d.Y[2 * N + i]};
+    const double rc2 = c.rc * c.rc;
+    int bad = 0;
+    acc[0] = acc[1] = acc[2] = 0.0;
+    *any = 0;
+    for (int k = 0; k < n; ++k) {
+        const int j = idx[k];
+        const double rx = xi[0] - d.Y[j], ry = xi[1] - d.Y[N + j], rz = xi[2] - d.Y[2 * N + j];
+        const double r2 = (rx * rx + ry * ry) + rz * rz;
+        if (r2 >= rc2) continue;
+        if (r2 == 0.0) {
+            bad = 1;
+            continue;
+        }
+        const double r = sqrt(r2);
+        const double cc = c.ks * (c.rc - r) / r;
+        acc[0] = acc[0] + cc * rx;
+        acc[1] = acc[1] + cc * ry;
+        acc[2] = acc[2] + cc * rz;
+        *any = 1;
+    }
+    d.nbr_cnt[i] = 0;
+    return bad;
+}
+
+/* steric forces at the stage positions Y, then the pack: from the candidate
+ * lists when the pair kernel records them, else by the full ascending sum */
 __global__ void k_steric_pack(Dev d, Coef c, int prec) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.Stot) return;
@@ -630,22 +714,31 @@ __global__ void k_steric_pack(Dev d, Coef c, int prec) {
         f0[a] = d.Fs[a * N + i0];
         f1[a] = d.Fs[a * N + i0 + 1];
     }
-    const int b = d.dsys[s];
-    const int j0 = d.sys_off[b], j1 = d.sys_off[b + 1];
-    auto get = [&](int j, double x[3]) {
-        x[0] = d.Y[j];
-        x[1] = d.Y[N + j];
-        x[2] = d.Y[2 * N + j];
-    };
     double acc[3];
     int any, bad = 0;
-    bad |= steric_sum(c, i0, j0, j1, get, acc, &any);
-    if (any)
-        for (int a = 0; a < 3; ++a) f0[a] = f0[a] + acc[a];
-    bad |= steric_sum(c, i0 + 1, j0, j1, get, acc, &any);
-    if (any)
-        for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
-    if (bad) d.ctl->flag = 1;
+    if (d.nbr_cnt) {
+        bad |= steric_list(d, c, i0, acc, &any);
+        if (any)
+            for (int a = 0; a < 3; ++a) f0[a] = f0[a] + acc[a];
+        bad |= steric_list(d, c, i0 + 1, acc, &any);
+        if (any)
+            for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
+    } else {
+        const int b = d.dsys[s];
+        const int j0 = d.sys_off[b], j1 = d.sys_off[b + 1];
+        auto get = [&](int j, double x[3]) {
+            x[0] = d.Y[j];
+            x[1] = d.Y[N + j];
+            x[2] = d.Y[2 * N + j];
+        };
+        bad |= steric_sum(c, i0, j0, j1, get, acc, &any);
+        if (any)
+            for (int a = 0; a < 3; ++a) f0[a] = f0[a] + acc[a];
+        bad |= steric_sum(c, i0 + 1, j0, j1, get, acc, &any);
+        if (any)
+            for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
+    }
+    if (bad) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
     store_pack(d, c, prec, i0, y0, y1, f0, f1);
 }
 
@@ -707,18 +800,25 @@ hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xa, double s
     return hipGetLastError();
 }
 
-template <int WG, int IPL, int WJ, int SPLIT>
+template <int WG, int IPL, int WJ, int SPLIT, int STERIC>
 static hipError_t f32c_t(const Dev& d, int bump, hipStream_t s) {
-    hipLaunchKernelGGL((k_pairs_f32c<WG, IPL, WJ, SPLIT>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
+    hipLaunchKernelGGL((k_pairs_f32c<WG, IPL, WJ, SPLIT, STERIC>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
     return hipGetLastError();
 }
 
-template <int WG, int WJ, int SPLIT>
+template <int WG, int WJ, int SPLIT, int STERIC>
 static hipError_t f32c_ipl(const Dev& d, int ipl, int bump, hipStream_t s) {
-    if (ipl == 1) return f32c_t<WG, 1, WJ, SPLIT>(d, bump, s);
-    if (ipl == 2) return f32c_t<WG, 2, WJ, SPLIT>(d, bump, s);
-    if (ipl == 4) return f32c_t<WG, 4, WJ, SPLIT>(d, bump, s);
+    if (ipl == 1) return f32c_t<WG, 1, WJ, SPLIT, STERIC>(d, bump, s);
+    if (ipl == 2) return f32c_t<WG, 2, WJ, SPLIT, STERIC>(d, bump, s);
+    if (ipl == 4) return f32c_t<WG, 4, WJ, SPLIT, STERIC>(d, bump, s);
     return hipErrorInvalidValue;
+}
+
+template <int WG, int WJ>
+static hipError_t f32c_var(const Dev& d, const Shape& sh, int bump, hipStream_t s) {
+    if (sh.steric)
+        return sh.split ? f32c_ipl<WG, WJ, 1, 1>(d, sh.ipl, bump, s) : f32c_ipl<WG, WJ, 0, 1>(d, sh.ipl, bump, s);
+    return sh.split ? f32c_ipl<WG, WJ, 1, 0>(d, sh.ipl, bump, s) : f32c_ipl<WG, WJ, 0, 0>(d, sh.ipl, bump, s);
 }
 
 template <int WG, int IPL>
@@ -730,13 +830,10 @@ static hipError_t f64_t(const Dev& d, int bump, hipStream_t s) {
 hipError_t launch_pairs(const Dev& d, int prec, const Shape& sh, int bump, hipStream_t s) {
     if (d.nitems <= 0) return hipSuccess;
     if (prec == PREC_FP32C) {
-        const bool sp = sh.split != 0;
-        if (sh.wg == 64 && sh.wj == 1)
-            return sp ? f32c_ipl<64, 1, 1>(d, sh.ipl, bump, s) : f32c_ipl<64, 1, 0>(d, sh.ipl, bump, s);
-        if (sh.wg == 256 && sh.wj == 1)
-            return sp ? f32c_ipl<256, 1, 1>(d, sh.ipl, bump, s) : f32c_ipl<256, 1, 0>(d, sh.ipl, bump, s);
-        if (sh.wg == 256 && sh.wj == 4)
-            return sp ? f32c_ipl<256, 4, 1>(d, sh.ipl, bump, s) : f32c_ipl<256, 4, 0>(d, sh.ipl, bump, s);
+        if (sh.steric && !d.nbr_cnt) return hipErrorInvalidValue;
+        if (sh.wg == 64 && sh.wj == 1) return f32c_var<64, 1>(d, sh, bump, s);
+        if (sh.wg == 256 && sh.wj == 1) return f32c_var<256, 1>(d, sh, bump, s);
+        if (sh.wg == 256 && sh.wj == 4) return f32c_var<256, 4>(d, sh, bump, s);
         return hipErrorInvalidValue;
     }
     /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group; the

@@ -147,12 +147,16 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
     return AD_OK;
 }
 
+/* FP32C with steric forces: the pair kernel records steric candidates */
+static bool uses_lists(const ad_ctx* c) { return c->p.steric_k != 0.0 && c->p.precision == AD_FP32C; }
+
 static ad::Shape shape_of(const ad_ctx* c) {
     ad::Shape sh;
     sh.wg = c->launch.wg;
     sh.wj = c->launch.wj;
     sh.ipl = c->launch.ipl;
     sh.split = c->launch.posmode == AD_POS_HILO ? 1 : 0;
+    sh.steric = uses_lists(c) ? 1 : 0;
     return sh;
 }
 
@@ -198,7 +202,8 @@ static void build_items(ad_ctx* c) {
 /* ------------------------------------------------------------ workspace */
 
 struct Layout {
-    size_t ctl, X, R, U0, Y, Fs, phitrig, dsys, sys_off, sys_P, sys_pbase, items, pA, pB, pC, pD, part, tab, total;
+    size_t ctl, X, R, U0, Y, Fs, nbr_cnt, nbr_idx, phitrig, dsys, sys_off, sys_P, sys_pbase, items, pA, pB, pC, pD,
+        part, tab, total;
 };
 
 static Layout layout(const ad_ctx* c) {
@@ -217,6 +222,8 @@ static Layout layout(const ad_ctx* c) {
     const bool steric = c->p.steric_k != 0.0;
     L.Y = take(steric ? 3 * N * 8 : 0);
     L.Fs = take(steric ? 3 * N * 8 : 0);
+    L.nbr_cnt = take(uses_lists(c) ? N * 4 : 0);
+    L.nbr_idx = take(uses_lists(c) ? N * 4 * ad::NBR_CAP : 0);
     L.phitrig = take(S * 16);
     L.dsys = take(S * 4);
     L.sys_off = take((c->nsys + 1) * 4);
@@ -244,6 +251,15 @@ static void make_dev(ad_ctx* c) {
     d.U0 = reinterpret_cast<double*>(b + L.U0);
     d.Y = reinterpret_cast<double*>(b + L.Y);
     d.Fs = reinterpret_cast<double*>(b + L.Fs);
+    d.nbr_cnt = uses_lists(c) ? reinterpret_cast<int*>(b + L.nbr_cnt) : nullptr;
+    d.nbr_idx = uses_lists(c) ? reinterpret_cast<int*>(b + L.nbr_idx) : nullptr;
+    {
+        /* skin of half the contact distance: listed below 1.5 rc, valid while
+         * no sphere moves more than rc/4 between stages */
+        const double skin = 0.5 * c->p.steric_r;
+        d.list_r2 = (float)((c->p.steric_r + skin) * (c->p.steric_r + skin));
+        d.move2 = 0.25 * skin * skin;
+    }
     d.phitrig = reinterpret_cast<const double2*>(b + L.phitrig);
     d.dsys = reinterpret_cast<const int*>(b + L.dsys);
     d.sys_off = reinterpret_cast<const int*>(b + L.sys_off);
@@ -264,8 +280,8 @@ static void make_dev(ad_ctx* c) {
 }
 
 static void drop_graph(ad_ctx* c) {
-    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) hipGraphDestroy(c->graph);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     c->graph_exec = nullptr;
     c->graph = nullptr;
 }
@@ -442,7 +458,11 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
 static int read_flag(ad_ctx* c, hipStream_t st) {
     HIPCHECK(c, hipMemcpyAsync(c->h_flag, &c->dev.ctl->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(c, hipStreamSynchronize(st));
-    if (*c->h_flag) return fail(c, AD_ENONFINITE, "non-finite velocity or coincident spheres met");
+    const int f = *c->h_flag;
+    if (f & ad::FLAG_NONFINITE) return fail(c, AD_ENONFINITE, "non-finite velocity or coincident spheres met");
+    if (f & ad::FLAG_NBR_FULL)
+        return fail(c, AD_ERANGE, "more than %d steric candidates for one sphere", ad::NBR_CAP);
+    if (f & ad::FLAG_NBR_SKIN) return fail(c, AD_ERANGE, "a sphere moved more than the steric skin allows in one stage");
     return AD_OK;
 }
 
@@ -506,12 +526,12 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
 int ad_destroy(ad_ctx* c) {
     if (!c) return AD_OK;
     drop_graph(c);
-    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
-    if (c->tab_event) hipEventDestroy(c->tab_event);
-    for (auto& e : c->ev) hipEventDestroy(e);
-    if (c->h_tab) hipHostFree(c->h_tab);
-    if (c->h_phi) hipHostFree(c->h_phi);
-    if (c->h_flag) hipHostFree(c->h_flag);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->tab_event) (void)hipEventDestroy(c->tab_event);
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
+    if (c->h_tab) (void)hipHostFree(c->h_tab);
+    if (c->h_phi) (void)hipHostFree(c->h_phi);
+    if (c->h_flag) (void)hipHostFree(c->h_flag);
     delete c;
     return AD_OK;
 }

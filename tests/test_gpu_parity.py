@@ -345,3 +345,35 @@ def test_steric_fp32c(oracle):
     err = np.abs(Xg - Xo).max()
     say(f"  steric fp32c max position error after 200 steps {err:.2e}")
     assert err < 1e-6
+
+
+def test_steric_candidate_overflow_is_reported():
+    """More than 16 spheres within 1.5 steric_r of one sphere: the FP32C
+    candidate list would be incomplete, and ad_run says so (AD_ERANGE)."""
+    _torch()
+    p = Params(steric_k=100.0, steric_r=2.0)
+    sus = make_single(40, 7.0, 8, p, rmin=1.0)  # up to 23 spheres within 3 of one
+    s = P.Simulator(p, [sus.S], precision="fp32c")
+    s.set_state(sus.X, sus.phi)
+    _, _, code = s.run(1, 1)
+    assert code == P.binding.AD_ERANGE
+
+
+def test_large_steric_workload_runs_clean(oracle):
+    """65536 spheres with steric repulsion, FP32C: a few steps with no flag,
+    forces bitwise equal to the oracle's at the start."""
+    torch = _torch()
+    sus = make_preset("n65536")
+    say("n65536 steric 4 steps")
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c", launch="tuned", graph=True)
+    s.set_state(sus.X, sus.phi)
+    rows = np.random.default_rng(11).choice(sus.N, 256, replace=False)
+    F = s.forces(sus.X, 0.0).cpu().numpy()
+    Fo = oracle.forces(sus.params, sus.X, sus.phi, 0.0)
+    assert np.array_equal(F[rows], Fo[rows])
+    _, _, code = s.run(4, 2)
+    assert code == 0
+    Xg = s.get_state()[0].cpu().numpy()
+    assert np.isfinite(Xg).all() and np.abs(Xg - sus.X).max() < 0.1
+    del s
+    torch.cuda.empty_cache()
