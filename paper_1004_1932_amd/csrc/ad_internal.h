@@ -89,6 +89,7 @@ struct Shape {
 /* kernel launchers (ad_kernels.hip) */
 hipError_t launch_set_step(const Dev& d, long long value, hipStream_t s);
 hipError_t launch_clear_flag(const Dev& d, hipStream_t s);
+hipError_t launch_clear_lists(const Dev& d, hipStream_t s);
 hipError_t launch_state_in(const Dev& d, const double* Xaos, hipStream_t s);
 hipError_t launch_state_out(const Dev& d, double* Xaos, hipStream_t s);
 /* pack from the state X at forces time (st, ct); prec selects the pack */

@@ -261,11 +261,18 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
 /* append source j to the steric candidate list of target i (i < iend) */
 __device__ __noinline__ void add_candidate(const Dev& d, int i, int iend, int j) {
     if (i >= iend) return;
-    const int k = atomicAdd(&d.nbr_cnt[i], 1);
-    if (k < NBR_CAP)
-        d.nbr_idx[i * NBR_CAP + k] = j;
+    /* unsigned test: a count outside [0, NBR_CAP) never becomes an index */
+    const unsigned k = (unsigned)atomicAdd(&d.nbr_cnt[i], 1);
+    if (k < (unsigned)NBR_CAP)
+        d.nbr_idx[i * NBR_CAP + (int)k] = j;
     else
         atomicOr(&d.ctl->flag, FLAG_NBR_FULL);
+}
+
+/* empty every candidate list */
+__global__ void k_clear_lists(Dev d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.Ntot) d.nbr_cnt[i] = 0;
 }
 
 /* FP32C pair sum. A work-group of WG threads is WI x WJ waves: WI waves own
@@ -664,8 +671,12 @@ __device__ int steric_list(const Dev& d, const Coef& c, int i, double acc[3], in
     const int N = d.Ntot;
     int n = d.nbr_cnt[i];
     n = n < NBR_CAP ? n : NBR_CAP; /* an overflow was flagged when it happened */
+    n = n > 0 ? n : 0;
     int idx[NBR_CAP];
-    for (int k = 0; k < n; ++k) idx[k] = d.nbr_idx[i * NBR_CAP + k];
+    for (int k = 0; k < n; ++k) {
+        const int j = d.nbr_idx[i * NBR_CAP + k];
+        idx[k] = (j >= 0 && j < N) ? j : i; /* entries come from the pair kernel; i itself is skipped */
+    }
     for (int k = 1; k < n; ++k) { /* insertion sort, n <= NBR_CAP */
         const int v = idx[k];
         int m = k - 1;
@@ -682,6 +693,7 @@ __device__ int steric_list(const Dev& d, const Coef& c, int i, double acc[3], in
     *any = 0;
     for (int k = 0; k < n; ++k) {
         const int j = idx[k];
+        if (j == i) continue;
         const double rx = xi[0] - d.Y[j], ry = xi[1] - d.Y[N + j], rz = xi[2] - d.Y[2 * N + j];
         const double r2 = (rx * rx + ry * ry) + rz * rz;
         if (r2 >= rc2) continue;
@@ -765,6 +777,12 @@ static inline dim3 blocks_for(int n, int bs) { return dim3((unsigned)((n + bs - 
 
 hipError_t launch_set_step(const Dev& d, long long value, hipStream_t s) {
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, d.ctl, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_lists(const Dev& d, hipStream_t s) {
+    if (!d.nbr_cnt) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_lists, blocks_for(d.Ntot, 256), dim3(256), 0, s, d);
     return hipGetLastError();
 }
 

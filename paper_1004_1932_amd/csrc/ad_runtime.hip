@@ -612,6 +612,7 @@ int ad_set_state(ad_ctx* c, const double* X, const double* phi, double t0, int64
                                hipMemcpyHostToDevice, st));
     HIPCHECK(c, ad::launch_state_in(c->dev, X, st));
     HIPCHECK(c, ad::launch_clear_flag(c->dev, st));
+    HIPCHECK(c, ad::launch_clear_lists(c->dev, st));
     HIPCHECK(c, hipStreamSynchronize(st));
     c->t0 = t0;
     c->step = step0;
@@ -648,7 +649,9 @@ int ad_mobility_apply(ad_ctx* c, const double* X, const double* F, double* u, vo
     hipStream_t st = as_stream(stream);
     const int prec = prec_of(c);
     HIPCHECK(c, ad::launch_pack_apply(c->dev, c->coef, prec, X, F, st));
-    HIPCHECK(c, ad::launch_pairs(c->dev, prec, shape_of(c), 0, st));
+    ad::Shape sh = shape_of(c);
+    sh.steric = 0; /* candidate lists belong to the step loop */
+    HIPCHECK(c, ad::launch_pairs(c->dev, prec, sh, 0, st));
     HIPCHECK(c, ad::launch_epilogue(c->dev, c->coef, prec, c->p.integrator, 0, 0, u, st));
     return AD_OK;
 }
