@@ -18,8 +18,8 @@ struct Item {
 
 /* Device control block at the start of the workspace. */
 struct Ctl {
-    long long step; /* index of the step in flight (bumped by stage 0) */
-    int flag;       /* FLAG_* bits, sticky until cleared */
+    unsigned long long ticket; /* pair-kernel work-group tickets taken so far */
+    int flag;                  /* FLAG_* bits, sticky until cleared */
     int pad[13];
 };
 
@@ -55,6 +55,7 @@ struct Dev {
     double* U0;         /* [3][Ntot] self (+partner) velocity of the stage */
     double* Y;          /* [3][Ntot] stage positions (steric path only) */
     double* Fs;         /* [3][Ntot] stage forces (steric path only) */
+    int* blk_cnt;       /* [Ntot] finished j-chunks of the target block starting at i */
     int* nbr_cnt;       /* [Ntot] candidate count (FP32C steric path) */
     int* nbr_idx;       /* [Ntot][NBR_CAP] candidate source spheres */
     float list_r2;      /* (rc + skin)^2: pairs closer than this are listed */
@@ -65,10 +66,14 @@ struct Dev {
     const int* sys_P;   /* [nsys] number of j-chunks (partial slots) */
     const long long* sys_pbase; /* [nsys] first partial of the system */
     const Item* items;  /* [nitems] */
-    float4* pA;         /* FP32C pack: (hi.x, hi.y, hi.z, F.x) */
+    float4* pA;         /* FP32C pack read by this stage: (hi.x, hi.y, hi.z, F.x) */
     float4* pB;         /* FP32C pack: (lo.x, lo.y, lo.z, F.y) */
     float* pC;          /* FP32C pack: F.z */
     double2* pD;        /* FP64 pack: 3 double2 per sphere (x,y)(z,Fx)(Fy,Fz) */
+    float4* pA2;        /* the packs the epilogue writes for the next stage */
+    float4* pB2;
+    float* pC2;
+    double2* pD2;
     double* part;       /* partial sums */
     const double* tab;  /* [ring][8] (sin, cos) of omega*t per epilogue stage */
     int ring;           /* entries in tab */
@@ -77,6 +82,17 @@ struct Dev {
 
 enum { PREC_FP64 = 0, PREC_FP64_TILED = 1, PREC_FP32C = 2 };
 
+/* What the epilogue of a stage does. */
+struct Epi {
+    Coef c;
+    int prec;       /* PREC_* */
+    int integ;      /* 0 = RK4, 1 = Heun */
+    int stage;      /* stage index inside the step */
+    int nst;        /* stages per step */
+    int pack_next;  /* 1: write the next pack; 0: stage positions and spring forces for the steric kernel */
+    double* u_aos;  /* mobility apply: velocities out, row-major [N][3]; else nullptr */
+};
+
 /* Launch shape of the pair kernel: WG threads = (WG/64/wj) waves on distinct
  * targets x wj waves splitting each j-tile; ipl targets per lane; split = 1
  * for hi/lo positions (FP32C only). One work item covers 64*ipl*WG/64/wj
@@ -84,28 +100,30 @@ enum { PREC_FP64 = 0, PREC_FP64_TILED = 1, PREC_FP32C = 2 };
 struct Shape {
     int wg, wj, ipl, split;
     int steric; /* FP32C: record steric candidates while summing */
+    int fuse;   /* FP32C: epilogue in the pair kernel's last work-group per block */
 };
 
 /* kernel launchers (ad_kernels.hip) */
-hipError_t launch_set_step(const Dev& d, long long value, hipStream_t s);
+hipError_t launch_set_ticket(const Dev& d, unsigned long long value, hipStream_t s);
 hipError_t launch_clear_flag(const Dev& d, hipStream_t s);
-hipError_t launch_clear_lists(const Dev& d, hipStream_t s);
+hipError_t launch_clear_counts(const Dev& d, hipStream_t s);
 hipError_t launch_state_in(const Dev& d, const double* Xaos, hipStream_t s);
 hipError_t launch_state_out(const Dev& d, double* Xaos, hipStream_t s);
-/* pack from the state X at forces time (st, ct); prec selects the pack */
+/* pack from the state X at forces time (st, ct), into the first pack */
 hipError_t launch_pack_state(const Dev& d, const Coef& c, int prec, double st, double ct, hipStream_t s);
-/* pack from caller positions and forces (AoS) */
+/* pack from caller positions and forces (row-major), into the first pack */
 hipError_t launch_pack_apply(const Dev& d, const Coef& c, int prec, const double* Xaos,
                              const double* Faos, hipStream_t s);
-/* forces at caller positions (AoS) and time (st, ct), spring + steric */
+/* forces at caller positions (row-major) and time (st, ct), spring + steric */
 hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xaos, double st, double ct,
                          double* Faos, hipStream_t s);
-hipError_t launch_pairs(const Dev& d, int prec, const Shape& sh, int bump, hipStream_t s);
-/* epilogue of a step stage (integrator, stage) or of a mobility apply (u != NULL) */
-hipError_t launch_epilogue(const Dev& d, const Coef& c, int prec, int integrator, int stage,
-                           int pack_next, double* u_aos, hipStream_t s);
-/* steric forces at stage positions Y, then the pack (steric path) */
-hipError_t launch_steric_pack(const Dev& d, const Coef& c, int prec, int stage, hipStream_t s);
+/* pair sum; mode 0 = mobility apply, 1 = step stage, 2 = step stage with the
+ * epilogue fused (FP32C). With events, they time the dispatch itself. */
+hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s,
+                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+hipError_t launch_epilogue(const Dev& d, const Epi& e, hipStream_t s);
+/* steric forces at stage positions Y, then the next pack (steric path) */
+hipError_t launch_steric_pack(const Dev& d, const Coef& c, int prec, hipStream_t s);
 hipError_t launch_record(const Dev& d, double* centres, double* com, hipStream_t s);
 
 }  // namespace ad

@@ -3,19 +3,24 @@
  * active spring dumbbell suspensions (Putz, Dunkel, Yeomans, Sec. II and
  * Sec. V).
  *
- * One RK4 stage is two launches:
+ * One RK4 stage is one or two launches:
  *   k_pairs_*   the O(N^2) pair sum over a work list of (i-block, j-chunk)
- *               items; each item stages its j-tile through LDS and every
+ *               items; each item stages its j-tiles through LDS and every
  *               lane holds IPL consecutive target spheres in registers.
- *   k_epilogue  one thread per dumbbell: sums the j-chunk partials in a
- *               fixed order, forms the stage velocity k = u0 + kappa*acc,
- *               updates the RK accumulator and the state, and evaluates the
- *               spring forces of the next stage (Eq. e:swimmer_potential)
- *               straight into the pack the next pair kernel reads.
+ *   epilogue    for each target block: sums the j-chunk partials in chunk
+ *               order, forms the stage velocity k = u0 + kappa*acc, updates
+ *               the RK accumulator and the state, and evaluates the spring
+ *               forces of the next stage (Eq. e:swimmer_potential) into the
+ *               pack the next pair sum reads. It runs either as its own
+ *               kernel (k_epilogue) or, fused, in the last work-group of the
+ *               pair kernel to finish each target block.
+ * Packs are double-buffered: stage s reads one and writes the other, so a
+ * fused epilogue never overwrites sources another work-group still reads.
  *
  * All FP64 arithmetic is written in a fixed order and built without FMA
  * contraction; FP32 FMAs are spelled out with __builtin_fmaf.
  */
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -101,10 +106,12 @@ __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float v) {
     lo = lo + e;
 }
 
+
 /* Write the pair-kernel pack and the self (+partner) velocity u0 of the two
- * spheres of one dumbbell at positions y0, y1 with forces f0, f1. */
+ * spheres of one dumbbell at positions y0, y1 with forces f0, f1; into the
+ * next-stage pack buffers when nxt != 0. */
 __device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const double y0[3],
-                           const double y1[3], const double f0[3], const double f1[3]) {
+                           const double y1[3], const double f0[3], const double f1[3], int nxt) {
     const int N = d.Ntot;
     const int i1 = i0 + 1;
     if (prec == PREC_FP32C) {
@@ -119,32 +126,36 @@ __device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const 
             d.U0[a * N + i0] = c.cs * f0[a] + c.co * t0[a];
             d.U0[a * N + i1] = c.cs * f1[a] + c.co * t1[a];
         }
+        float4* pA = nxt ? d.pA2 : d.pA;
+        float4* pB = nxt ? d.pB2 : d.pB;
+        float* pC = nxt ? d.pC2 : d.pC;
         float h[3], l[3];
         for (int a = 0; a < 3; ++a) split_f32(y0[a], h[a], l[a]);
-        d.pA[i0] = make_float4(h[0], h[1], h[2], (float)f0[0]);
-        d.pB[i0] = make_float4(l[0], l[1], l[2], (float)f0[1]);
-        d.pC[i0] = (float)f0[2];
+        pA[i0] = make_float4(h[0], h[1], h[2], (float)f0[0]);
+        pB[i0] = make_float4(l[0], l[1], l[2], (float)f0[1]);
+        pC[i0] = (float)f0[2];
         for (int a = 0; a < 3; ++a) split_f32(y1[a], h[a], l[a]);
-        d.pA[i1] = make_float4(h[0], h[1], h[2], (float)f1[0]);
-        d.pB[i1] = make_float4(l[0], l[1], l[2], (float)f1[1]);
-        d.pC[i1] = (float)f1[2];
+        pA[i1] = make_float4(h[0], h[1], h[2], (float)f1[0]);
+        pB[i1] = make_float4(l[0], l[1], l[2], (float)f1[1]);
+        pC[i1] = (float)f1[2];
     } else {
         for (int a = 0; a < 3; ++a) {
             d.U0[a * N + i0] = c.cs * f0[a];
             d.U0[a * N + i1] = c.cs * f1[a];
         }
-        d.pD[3 * i0 + 0] = make_double2(y0[0], y0[1]);
-        d.pD[3 * i0 + 1] = make_double2(y0[2], f0[0]);
-        d.pD[3 * i0 + 2] = make_double2(f0[1], f0[2]);
-        d.pD[3 * i1 + 0] = make_double2(y1[0], y1[1]);
-        d.pD[3 * i1 + 1] = make_double2(y1[2], f1[0]);
-        d.pD[3 * i1 + 2] = make_double2(f1[1], f1[2]);
+        double2* pD = nxt ? d.pD2 : d.pD;
+        pD[3 * i0 + 0] = make_double2(y0[0], y0[1]);
+        pD[3 * i0 + 1] = make_double2(y0[2], f0[0]);
+        pD[3 * i0 + 2] = make_double2(f0[1], f0[2]);
+        pD[3 * i1 + 0] = make_double2(y1[0], y1[1]);
+        pD[3 * i1 + 1] = make_double2(y1[2], f1[0]);
+        pD[3 * i1 + 2] = make_double2(f1[1], f1[2]);
     }
 }
 
 /* ------------------------------------------------------------ small kernels */
 
-__global__ void k_set_step(Ctl* ctl, long long v) { ctl->step = v; }
+__global__ void k_set_ticket(Ctl* ctl, unsigned long long v) { ctl->ticket = v; }
 __global__ void k_clear_flag(Ctl* ctl) { ctl->flag = 0; }
 
 __global__ void k_state_in(Dev d, const double* __restrict__ Xa) {
@@ -157,6 +168,14 @@ __global__ void k_state_out(Dev d, double* __restrict__ Xa) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.Ntot) return;
     for (int a = 0; a < 3; ++a) Xa[3 * i + a] = d.X[a * d.Ntot + i];
+}
+
+/* empty every steric candidate list and every block counter */
+__global__ void k_clear_counts(Dev d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.Ntot) return;
+    if (d.nbr_cnt) d.nbr_cnt[i] = 0;
+    d.blk_cnt[i] = 0;
 }
 
 /* pack from the state at time (st, ct); spring (+ steric) forces */
@@ -200,7 +219,7 @@ __global__ void k_pack_state(Dev d, Coef c, int prec, double st, double ct) {
             d.nbr_cnt[i0 + 1] = 0;
         }
     }
-    store_pack(d, c, prec, i0, y0, y1, f0, f1);
+    store_pack(d, c, prec, i0, y0, y1, f0, f1, 0);
 }
 
 /* pack from caller positions and forces (row-major [N][3]) */
@@ -216,7 +235,7 @@ __global__ void k_pack_apply(Dev d, Coef c, int prec, const double* __restrict__
         f0[a] = Fa[3 * i0 + a];
         f1[a] = Fa[3 * i0 + 3 + a];
     }
-    store_pack(d, c, prec, i0, y0, y1, f0, f1);
+    store_pack(d, c, prec, i0, y0, y1, f0, f1, 0);
 }
 
 /* spring + steric forces at caller positions, row-major output */
@@ -256,7 +275,162 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
     }
 }
 
+/* ------------------------------------------------------------ epilogue */
+
+/* Epilogue of one target block [i0, i0 + ni) (ni even), run by all
+ * blockDim.x threads of a work-group.
+ * Phase 1, one thread per sphere component: issue the loads of that
+ * component's j-chunk partials, u0, X and R together, sum the partials in
+ * chunk order, form k = u0 + kappa*acc and apply the (componentwise) RK
+ * update: R, X to global memory, the next stage position y to LDS.
+ * Phase 2, one thread per dumbbell: the next stage's spring forces at y and
+ * the next pack (or, with steric forces, y and the spring forces for the
+ * steric kernel). `step` selects the (sin, cos) row of the step table;
+ * ys and mv are LDS scratch of ni x 3 doubles. */
+constexpr int EPI_MAXP = 16; /* partials loaded per batch */
+
+__device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long step, double (*ys)[3],
+                          double (*mv)[3], int* badf) {
+    const int N = d.Ntot;
+    const int t = threadIdx.x;
+    const int nt = blockDim.x;
+    const Coef& c = e.c;
+    const int stage = e.stage;
+    const bool apply = (e.u_aos != nullptr);
+    if (t == 0) *badf = 0;
+    __syncthreads();
+    for (int idx = t; idx < 3 * ni; idx += nt) {
+        const int sl = idx / 3, a = idx - 3 * sl;
+        const int i = i0 + sl;
+        const int b = d.dsys[i >> 1];
+        const int off = d.sys_off[b];
+        const int Nb = d.sys_off[b + 1] - off;
+        const int P = d.sys_P[b];
+        const long long stride = 3LL * Nb;
+        const double* p = d.part + d.sys_pbase[b] + (long long)a * Nb + (i - off);
+        const int o = a * N + i;
+        /* independent loads first, so they are in flight together */
+        const double u0 = d.U0[o];
+        const double x = apply ? 0.0 : d.X[o];
+        const double r = (!apply && stage > 0) ? d.R[o] : 0.0;
+        const double yold = (!apply && !e.pack_next && d.nbr_cnt) ? d.Y[o] : 0.0;
+        double v[EPI_MAXP];
+#pragma unroll
+        for (int q = 0; q < EPI_MAXP; ++q) v[q] = (q < P) ? p[q * stride] : 0.0;
+        double acc = v[0];
+#pragma unroll
+        for (int q = 1; q < EPI_MAXP; ++q)
+            if (q < P) acc = acc + v[q];
+        for (int cc = EPI_MAXP; cc < P; cc += EPI_MAXP) {
+#pragma unroll
+            for (int q = 0; q < EPI_MAXP; ++q) v[q] = (cc + q < P) ? p[(cc + q) * stride] : 0.0;
+#pragma unroll
+            for (int q = 0; q < EPI_MAXP; ++q)
+                if (cc + q < P) acc = acc + v[q];
+        }
+        const double k = u0 + c.co * acc;
+        if (!isfinite(k)) *badf = 1;
+        if (apply) {
+            e.u_aos[3 * i + a] = k;
+            continue;
+        }
+        double y;
+        if (e.integ == 0) { /* RK4 */
+            if (stage == 0) {
+                d.R[o] = k;
+                y = x + c.h2 * k;
+            } else if (stage == 1) {
+                d.R[o] = r + 2.0 * k;
+                y = x + c.h2 * k;
+            } else if (stage == 2) {
+                d.R[o] = r + 2.0 * k;
+                y = x + c.dt * k;
+            } else {
+                y = x + c.dt6 * (r + k);
+                d.X[o] = y;
+            }
+        } else { /* Heun */
+            if (stage == 0) {
+                d.R[o] = k;
+                y = x + c.dt * k;
+            } else {
+                y = x + c.h2 * (r + k);
+                d.X[o] = y;
+            }
+        }
+        ys[sl][a] = y;
+        const double dd = y - yold;
+        mv[sl][a] = dd * dd;
+    }
+    __syncthreads();
+    if (t == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+    if (apply) return;
+    /* forces of the next stage: (sin, cos) of omega t from the step table */
+    const long long row = step % d.ring;
+    const double st = d.tab[row * 8 + 2 * stage];
+    const double ct = d.tab[row * 8 + 2 * stage + 1];
+    for (int q = t; q < ni / 2; q += nt) {
+        const int s = (i0 >> 1) + q;
+        const int ia = 2 * s;
+        double y[2][3];
+        for (int h = 0; h < 2; ++h)
+            for (int a = 0; a < 3; ++a) y[h][a] = ys[2 * q + h][a];
+        double f0[3], f1[3];
+        const double2 tp = d.phitrig[s];
+        spring_forces(c, y[0], y[1], tp.x, tp.y, st, ct, f0, f1);
+        if (e.pack_next) {
+            store_pack(d, c, e.prec, ia, y[0], y[1], f0, f1, 1);
+        } else {
+            if (d.nbr_cnt) {
+                /* candidate lists are valid while no sphere moves more than
+                 * half the skin between stage positions */
+                for (int h = 0; h < 2; ++h) {
+                    const double e2 = (mv[2 * q + h][0] + mv[2 * q + h][1]) + mv[2 * q + h][2];
+                    if (!(e2 <= d.move2)) atomicOr(&d.ctl->flag, FLAG_NBR_SKIN);
+                }
+            }
+            for (int a = 0; a < 3; ++a) {
+                d.Y[a * N + ia] = y[0][a];
+                d.Y[a * N + ia + 1] = y[1][a];
+                d.Fs[a * N + ia] = f0[a];
+                d.Fs[a * N + ia + 1] = f1[a];
+            }
+        }
+    }
+}
+
+/* the epilogue as its own kernel: EPI_S spheres per work-group of EPI_T
+ * threads; the step index follows from the tickets the pair kernel took */
+constexpr int EPI_S = 32;
+constexpr int EPI_T = 96;
+
+__global__ __launch_bounds__(EPI_T) void k_epilogue(Dev d, Epi e) {
+    __shared__ double ys[EPI_S][3];
+    __shared__ double mv[EPI_S][3];
+    __shared__ int badf;
+    const int i0 = blockIdx.x * EPI_S;
+    const int ni = min(EPI_S, d.Ntot - i0);
+    const long long step =
+        e.u_aos ? 0 : (long long)((d.ctl->ticket - 1ULL) / ((unsigned long long)e.nst * (unsigned long long)d.nitems));
+    epi_block(d, e, i0, ni, step, ys, mv, &badf);
+}
+
 /* ------------------------------------------------------------ pair sums */
+
+/* One thread's entry of a source tile: sphere t0 + t of the pack, or
+ * padding (far away and force-free, so it contributes exactly zero). */
+__device__ __forceinline__ void load_tile_entry(const Dev& d, int t0, int jend, int t, float4& A, float4& B,
+                                                float& C) {
+    if (t0 + t < jend) {
+        A = d.pA[t0 + t];
+        B = d.pB[t0 + t];
+        C = d.pC[t0 + t];
+    } else {
+        A = make_float4(1.0e15f, 1.0e15f, 1.0e15f, 0.f);
+        B = make_float4(0.f, 0.f, 0.f, 0.f);
+        C = 0.f;
+    }
+}
 
 /* append source j to the steric candidate list of target i (i < iend) */
 __device__ __noinline__ void add_candidate(const Dev& d, int i, int iend, int j) {
@@ -269,17 +443,39 @@ __device__ __noinline__ void add_candidate(const Dev& d, int i, int iend, int j)
         atomicOr(&d.ctl->flag, FLAG_NBR_FULL);
 }
 
-/* empty every candidate list */
-__global__ void k_clear_lists(Dev d) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < d.Ntot) d.nbr_cnt[i] = 0;
+/* Start of a pair kernel in a step: one ticket per work-group. Tickets of
+ * step n, stage s are [(n*nst + s)*nitems, (n*nst + s + 1)*nitems), so the
+ * step index needs no counter that the same kernel would both read and
+ * write. */
+__device__ __forceinline__ long long take_ticket(const Dev& d, const Epi& e, unsigned long long* s_tk) {
+    if (threadIdx.x == 0) *s_tk = atomicAdd(&d.ctl->ticket, 1ULL);
+    __syncthreads();
+    return (long long)(*s_tk / ((unsigned long long)e.nst * (unsigned long long)d.nitems));
+}
+
+/* End of a pair kernel with the fused epilogue: the work-group that
+ * completes a target block (the last of its P j-chunks) runs the epilogue
+ * of that block. Returns true in that work-group. */
+__device__ __forceinline__ bool last_of_block(const Dev& d, const Item& it, int* s_last) {
+    __threadfence(); /* this group's partial sums are visible device-wide */
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int old = atomicAdd(&d.blk_cnt[it.i0], 1);
+        *s_last = (old == d.sys_P[it.sys] - 1);
+        if (*s_last) d.blk_cnt[it.i0] = 0; /* ready for the next launch */
+    }
+    __syncthreads();
+    if (!*s_last) return false;
+    __threadfence(); /* and the other groups' are visible here */
+    return true;
 }
 
 /* FP32C pair sum. A work-group of WG threads is WI x WJ waves: WI waves own
  * different target spheres (IPL consecutive spheres per lane), and the WJ
- * waves that share the same targets take interleaved quarters of every
- * j-tile. A tile of WG source spheres is staged through LDS once and read as
- * broadcasts.
+ * waves that share the same targets take interleaved parts of every j-tile.
+ * A tile of WG source spheres is staged through LDS once and read as
+ * broadcasts; tiles are software pipelined (the next one is loaded into
+ * registers while the current one is summed).
  *   SPLIT = 1: positions are hi + lo floats, r = (hi_i - hi_j) + (lo_i - lo_j)
  *              (r rounded relative to itself).
  *   SPLIT = 0: positions are single floats, r = x_i - x_j (error ~ eps |x|).
@@ -290,18 +486,32 @@ __global__ void k_clear_lists(Dev d) {
  * are in u0, in FP64).
  *   STERIC = 1: every pair closer than rc + skin (r^2 is at hand) is appended
  *              to the target's candidate list for the next stage's steric
- *              forces. */
+ *              forces.
+ * mode: 0 = mobility apply, 1 = step stage, 2 = step stage with the fused
+ * epilogue. */
 template <int WG, int IPL, int WJ, int SPLIT, int STERIC>
-__global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
+__global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
     constexpr int WI = WG / 64 / WJ;
     constexpr int TJ = WG;          /* j per LDS tile */
     constexpr int JW = TJ / WJ;     /* j per wave per tile */
-    __shared__ float4 sA[TJ];
-    __shared__ float4 sB[TJ];
-    __shared__ float sC[TJ];
-    __shared__ float red[WJ > 1 ? WJ : 1][WI * 64 * IPL][6];
+    constexpr int IB = 64 * WI * IPL;
+    /* one LDS area, used in turn by the source tiles, the cross-wave
+     * combination and the fused epilogue (barriers separate the uses) */
+    constexpr int TILE_B = TJ * (16 + 16 + 4);
+    constexpr int RED_B = (WJ > 1 ? WJ : 1) * IB * 6 * 4;
+    constexpr int EPI_B = IB * 3 * 8 * 2;
+    constexpr int LDS_B = TILE_B > RED_B ? (TILE_B > EPI_B ? TILE_B : EPI_B) : (RED_B > EPI_B ? RED_B : EPI_B);
+    __shared__ __align__(16) unsigned char lds[LDS_B];
+    float4* sA = reinterpret_cast<float4*>(lds);
+    float4* sB = sA + TJ;
+    float* sC = reinterpret_cast<float*>(sB + TJ);
+    float* red = reinterpret_cast<float*>(lds); /* [WJ][IB][6] */
+    double(*ys)[3] = reinterpret_cast<double(*)[3]>(lds);
+    double(*mv)[3] = reinterpret_cast<double(*)[3]>(lds + IB * 3 * 8);
+    __shared__ unsigned long long s_tk;
+    __shared__ int s_last, s_bad;
     const Item it = d.items[blockIdx.x];
-    if (bump && blockIdx.x == 0 && threadIdx.x == 0) d.ctl->step = d.ctl->step + 1;
+    const long long step = mode ? take_ticket(d, e, &s_tk) : 0;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -335,25 +545,17 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
     const int dhi = (iend + 1) & ~1;
     const int jend = it.j0 + it.nj;
 
+    float4 A, B;
+    float C;
+    load_tile_entry(d, it.j0, jend, t, A, B, C);
     for (int t0 = it.j0; t0 < jend; t0 += TJ) {
         const int n = min(TJ, jend - t0);
-        float4 A, B;
-        float C;
-        if (t < n) {
-            A = d.pA[t0 + t];
-            B = d.pB[t0 + t];
-            C = d.pC[t0 + t];
-        } else {
-            /* padding: far away and force-free, contributes exactly zero */
-            A = make_float4(1.0e15f, 1.0e15f, 1.0e15f, 0.f);
-            B = make_float4(0.f, 0.f, 0.f, 0.f);
-            C = 0.f;
-        }
         __syncthreads();
         sA[t] = A;
         sB[t] = B;
         sC[t] = C;
         __syncthreads();
+        if (t0 + TJ < jend) load_tile_entry(d, t0 + TJ, jend, t, A, B, C);
         const bool diag = (t0 < dhi) && (t0 + n > dlo);
         const int jb = wj * JW;                     /* this wave's part of the tile */
         const int nw = max(0, min(JW, n - jb));
@@ -428,37 +630,42 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
     }
     if (WJ > 1) {
         /* combine the WJ waves that share these targets, in wave order */
+        __syncthreads(); /* the last tile is no longer read */
         if (wj > 0) {
 #pragma unroll
             for (int q = 0; q < IPL; ++q) {
-                float* r = red[wj][slot * IPL + q];
+                float* r = red + ((wj * IB) + slot * IPL + q) * 6;
                 r[0] = ax[q]; r[1] = bx[q]; r[2] = ay[q]; r[3] = by[q]; r[4] = az[q]; r[5] = bz[q];
             }
         }
         __syncthreads();
-        if (wj != 0) return;
+        if (wj == 0) {
 #pragma unroll
-        for (int w = 1; w < WJ; ++w) {
+            for (int w = 1; w < WJ; ++w) {
 #pragma unroll
-            for (int q = 0; q < IPL; ++q) {
-                const float* r = red[w][slot * IPL + q];
-                two_sum_acc(ax[q], bx[q], r[0]); bx[q] = bx[q] + r[1];
-                two_sum_acc(ay[q], by[q], r[2]); by[q] = by[q] + r[3];
-                two_sum_acc(az[q], bz[q], r[4]); bz[q] = bz[q] + r[5];
+                for (int q = 0; q < IPL; ++q) {
+                    const float* r = red + ((w * IB) + slot * IPL + q) * 6;
+                    two_sum_acc(ax[q], bx[q], r[0]); bx[q] = bx[q] + r[1];
+                    two_sum_acc(ay[q], by[q], r[2]); by[q] = by[q] + r[3];
+                    two_sum_acc(az[q], bz[q], r[4]); bz[q] = bz[q] + r[5];
+                }
             }
         }
     }
-    const long long base = d.sys_pbase[it.sys] + (long long)it.c * 3 * it.Nb;
+    if (wj == 0) {
+        const long long base = d.sys_pbase[it.sys] + (long long)it.c * 3 * it.Nb;
 #pragma unroll
-    for (int q = 0; q < IPL; ++q) {
-        const int i = ib + q;
-        if (i < iend) {
-            const int li = i - it.ioff;
-            d.part[base + li] = (double)ax[q] + (double)bx[q];
-            d.part[base + it.Nb + li] = (double)ay[q] + (double)by[q];
-            d.part[base + 2 * it.Nb + li] = (double)az[q] + (double)bz[q];
+        for (int q = 0; q < IPL; ++q) {
+            const int i = ib + q;
+            if (i < iend) {
+                const int li = i - it.ioff;
+                d.part[base + li] = (double)ax[q] + (double)bx[q];
+                d.part[base + it.Nb + li] = (double)ay[q] + (double)by[q];
+                d.part[base + 2 * it.Nb + li] = (double)az[q] + (double)bz[q];
+            }
         }
     }
+    if (mode == 2 && last_of_block(d, it, &s_last)) epi_block(d, e, it.i0, it.ni, step, ys, mv, &s_bad);
 }
 
 /* FP64: the sum in ascending j with the plain operation order
@@ -468,10 +675,11 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, int bump) {
  * skipped and raises the flag. With one chunk per system this is the
  * sequential FP64 sum exactly. */
 template <int WG, int IPL>
-__global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, int bump) {
+__global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
     __shared__ double2 sD[3][WG];
+    __shared__ unsigned long long s_tk;
     const Item it = d.items[blockIdx.x];
-    if (bump && blockIdx.x == 0 && threadIdx.x == 0) d.ctl->step = d.ctl->step + 1;
+    if (mode) take_ticket(d, e, &s_tk);
     const int t = threadIdx.x;
     const int ib = it.i0 + t * IPL;
     const int iend = it.i0 + it.ni;
@@ -542,123 +750,6 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, int bump) {
             d.part[base + it.Nb + li] = ay[q];
             d.part[base + 2 * it.Nb + li] = az[q];
             if (bad) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
-        }
-    }
-}
-
-/* ------------------------------------------------------------ epilogue */
-
-/* Two phases in one block of 192 threads (32 dumbbells): first one thread
- * per sphere component sums that component's j-chunk partials in chunk
- * order (loads issued eight at a time) and forms k = u0 + kappa*acc; then one
- * thread per dumbbell updates the RK state and evaluates the next forces. */
-__global__ __launch_bounds__(192) void k_epilogue(Dev d, Coef c, int prec, int integrator, int stage,
-                                                  int pack_next, double* __restrict__ u_aos) {
-    __shared__ double kvs[64][3];
-    __shared__ int badf;
-    const int N = d.Ntot;
-    const int t = threadIdx.x;
-    if (t == 0) badf = 0;
-    __syncthreads();
-    {
-        const int sl = t / 3, a = t - 3 * (t / 3);
-        const int i = blockIdx.x * 64 + sl;
-        if (i < N) {
-            const int b = d.dsys[i >> 1];
-            const int off = d.sys_off[b];
-            const int Nb = d.sys_off[b + 1] - off;
-            const int P = d.sys_P[b];
-            const long long stride = 3LL * Nb;
-            const double* p = d.part + d.sys_pbase[b] + (long long)a * Nb + (i - off);
-            double acc = p[0];
-            for (int cc = 1; cc < P; cc += 8) {
-                double v[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = (cc + q < P) ? p[(cc + q) * stride] : 0.0;
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (cc + q < P) acc = acc + v[q];
-            }
-            const double v = d.U0[a * N + i] + c.co * acc;
-            if (!isfinite(v)) badf = 1;
-            if (u_aos)
-                u_aos[3 * i + a] = v;
-            else
-                kvs[sl][a] = v;
-        }
-    }
-    __syncthreads();
-    if (t == 0 && badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
-    if (u_aos || t >= 32) return;
-    const int s = blockIdx.x * 32 + t;
-    if (s >= d.Stot) return;
-    const int i0 = 2 * s;
-    double kv[2][3];
-    for (int h = 0; h < 2; ++h)
-        for (int a = 0; a < 3; ++a) kv[h][a] = kvs[2 * t + h][a];
-    double y[2][3];
-    for (int h = 0; h < 2; ++h) {
-        const int i = i0 + h;
-        for (int a = 0; a < 3; ++a) {
-            const int o = a * N + i;
-            const double k = kv[h][a];
-            const double x = d.X[o];
-            if (integrator == 0) { /* RK4 */
-                if (stage == 0) {
-                    d.R[o] = k;
-                    y[h][a] = x + c.h2 * k;
-                } else if (stage == 1) {
-                    d.R[o] = d.R[o] + 2.0 * k;
-                    y[h][a] = x + c.h2 * k;
-                } else if (stage == 2) {
-                    d.R[o] = d.R[o] + 2.0 * k;
-                    y[h][a] = x + c.dt * k;
-                } else {
-                    const double xn = x + c.dt6 * (d.R[o] + k);
-                    d.X[o] = xn;
-                    y[h][a] = xn;
-                }
-            } else { /* Heun */
-                if (stage == 0) {
-                    d.R[o] = k;
-                    y[h][a] = x + c.dt * k;
-                } else {
-                    const double xn = x + c.h2 * (d.R[o] + k);
-                    d.X[o] = xn;
-                    y[h][a] = xn;
-                }
-            }
-        }
-    }
-    /* forces of the next stage: (sin, cos) of omega t from the step table */
-    const long long e = d.ctl->step % d.ring;
-    const double st = d.tab[e * 8 + 2 * stage];
-    const double ct = d.tab[e * 8 + 2 * stage + 1];
-    double f0[3], f1[3];
-    const double2 tp = d.phitrig[s];
-    spring_forces(c, y[0], y[1], tp.x, tp.y, st, ct, f0, f1);
-    if (pack_next) {
-        store_pack(d, c, prec, i0, y[0], y[1], f0, f1);
-    } else {
-        if (d.nbr_cnt) {
-            /* candidate lists are valid while no sphere moves more than half
-             * the skin between stage positions */
-            double m2 = 0.0;
-            for (int h = 0; h < 2; ++h) {
-                double e2 = 0.0;
-                for (int a = 0; a < 3; ++a) {
-                    const double dd = y[h][a] - d.Y[a * N + i0 + h];
-                    e2 = e2 + dd * dd;
-                }
-                m2 = e2 > m2 ? e2 : m2;
-            }
-            if (!(m2 <= d.move2)) atomicOr(&d.ctl->flag, FLAG_NBR_SKIN);
-        }
-        for (int a = 0; a < 3; ++a) {
-            d.Y[a * N + i0] = y[0][a];
-            d.Y[a * N + i0 + 1] = y[1][a];
-            d.Fs[a * N + i0] = f0[a];
-            d.Fs[a * N + i0 + 1] = f1[a];
         }
     }
 }
@@ -751,7 +842,7 @@ __global__ void k_steric_pack(Dev d, Coef c, int prec) {
             for (int a = 0; a < 3; ++a) f1[a] = f1[a] + acc[a];
     }
     if (bad) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
-    store_pack(d, c, prec, i0, y0, y1, f0, f1);
+    store_pack(d, c, prec, i0, y0, y1, f0, f1, 1);
 }
 
 /* records: dumbbell centres and per-system mean position */
@@ -775,19 +866,18 @@ __global__ void k_record(Dev d, double* __restrict__ centres, double* __restrict
 
 static inline dim3 blocks_for(int n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
-hipError_t launch_set_step(const Dev& d, long long value, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, d.ctl, value);
-    return hipGetLastError();
-}
-
-hipError_t launch_clear_lists(const Dev& d, hipStream_t s) {
-    if (!d.nbr_cnt) return hipSuccess;
-    hipLaunchKernelGGL(k_clear_lists, blocks_for(d.Ntot, 256), dim3(256), 0, s, d);
+hipError_t launch_set_ticket(const Dev& d, unsigned long long value, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_ticket, dim3(1), dim3(1), 0, s, d.ctl, value);
     return hipGetLastError();
 }
 
 hipError_t launch_clear_flag(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, d.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_counts(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_counts, blocks_for(d.Ntot, 256), dim3(256), 0, s, d);
     return hipGetLastError();
 }
 
@@ -818,60 +908,67 @@ hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xa, double s
     return hipGetLastError();
 }
 
-template <int WG, int IPL, int WJ, int SPLIT, int STERIC>
-static hipError_t f32c_t(const Dev& d, int bump, hipStream_t s) {
-    hipLaunchKernelGGL((k_pairs_f32c<WG, IPL, WJ, SPLIT, STERIC>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
+/* Launch a pair kernel; with timing events the launch goes through
+ * hipExtLaunchKernelGGL, whose events carry the dispatch's own start and end
+ * times. */
+struct Timing {
+    hipEvent_t start, stop;
+};
+
+template <class K>
+static hipError_t go(K kern, int wg, const Dev& d, const Epi& e, int mode, hipStream_t s, const Timing& tm) {
+    if (tm.start)
+        hipExtLaunchKernelGGL(kern, dim3(d.nitems), dim3(wg), 0, s, tm.start, tm.stop, 0, d, e, mode);
+    else
+        hipLaunchKernelGGL(kern, dim3(d.nitems), dim3(wg), 0, s, d, e, mode);
     return hipGetLastError();
 }
 
 template <int WG, int WJ, int SPLIT, int STERIC>
-static hipError_t f32c_ipl(const Dev& d, int ipl, int bump, hipStream_t s) {
-    if (ipl == 1) return f32c_t<WG, 1, WJ, SPLIT, STERIC>(d, bump, s);
-    if (ipl == 2) return f32c_t<WG, 2, WJ, SPLIT, STERIC>(d, bump, s);
-    if (ipl == 4) return f32c_t<WG, 4, WJ, SPLIT, STERIC>(d, bump, s);
+static hipError_t f32c_ipl(const Dev& d, const Epi& e, int ipl, int mode, hipStream_t s, const Timing& tm) {
+    if (ipl == 1) return go(k_pairs_f32c<WG, 1, WJ, SPLIT, STERIC>, WG, d, e, mode, s, tm);
+    if (ipl == 2) return go(k_pairs_f32c<WG, 2, WJ, SPLIT, STERIC>, WG, d, e, mode, s, tm);
+    if (ipl == 4) return go(k_pairs_f32c<WG, 4, WJ, SPLIT, STERIC>, WG, d, e, mode, s, tm);
     return hipErrorInvalidValue;
 }
 
 template <int WG, int WJ>
-static hipError_t f32c_var(const Dev& d, const Shape& sh, int bump, hipStream_t s) {
+static hipError_t f32c_var(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, const Timing& tm) {
     if (sh.steric)
-        return sh.split ? f32c_ipl<WG, WJ, 1, 1>(d, sh.ipl, bump, s) : f32c_ipl<WG, WJ, 0, 1>(d, sh.ipl, bump, s);
-    return sh.split ? f32c_ipl<WG, WJ, 1, 0>(d, sh.ipl, bump, s) : f32c_ipl<WG, WJ, 0, 0>(d, sh.ipl, bump, s);
+        return sh.split ? f32c_ipl<WG, WJ, 1, 1>(d, e, sh.ipl, mode, s, tm)
+                        : f32c_ipl<WG, WJ, 0, 1>(d, e, sh.ipl, mode, s, tm);
+    return sh.split ? f32c_ipl<WG, WJ, 1, 0>(d, e, sh.ipl, mode, s, tm)
+                    : f32c_ipl<WG, WJ, 0, 0>(d, e, sh.ipl, mode, s, tm);
 }
 
-template <int WG, int IPL>
-static hipError_t f64_t(const Dev& d, int bump, hipStream_t s) {
-    hipLaunchKernelGGL((k_pairs_f64<WG, IPL>), dim3(d.nitems), dim3(WG), 0, s, d, bump);
-    return hipGetLastError();
-}
-
-hipError_t launch_pairs(const Dev& d, int prec, const Shape& sh, int bump, hipStream_t s) {
+hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, hipEvent_t ev_start,
+                        hipEvent_t ev_stop) {
     if (d.nitems <= 0) return hipSuccess;
-    if (prec == PREC_FP32C) {
+    const Timing tm{ev_start, ev_stop};
+    if (e.prec == PREC_FP32C) {
         if (sh.steric && !d.nbr_cnt) return hipErrorInvalidValue;
-        if (sh.wg == 64 && sh.wj == 1) return f32c_var<64, 1>(d, sh, bump, s);
-        if (sh.wg == 256 && sh.wj == 1) return f32c_var<256, 1>(d, sh, bump, s);
-        if (sh.wg == 256 && sh.wj == 4) return f32c_var<256, 4>(d, sh, bump, s);
+        if (sh.wg == 64 && sh.wj == 1) return f32c_var<64, 1>(d, e, sh, mode, s, tm);
+        if (sh.wg == 256 && sh.wj == 1) return f32c_var<256, 1>(d, e, sh, mode, s, tm);
+        if (sh.wg == 256 && sh.wj == 4) return f32c_var<256, 4>(d, e, sh, mode, s, tm);
         return hipErrorInvalidValue;
     }
-    /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group; the
-     * work list was built for this shape, so anything else is refused */
-    if (sh.wj != 1) return hipErrorInvalidValue;
-    if (sh.wg == 64 && sh.ipl == 1) return f64_t<64, 1>(d, bump, s);
-    if (sh.wg == 64 && sh.ipl == 2) return f64_t<64, 2>(d, bump, s);
-    if (sh.wg == 256 && sh.ipl == 1) return f64_t<256, 1>(d, bump, s);
-    if (sh.wg == 256 && sh.ipl == 2) return f64_t<256, 2>(d, bump, s);
+    /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group and
+     * no fused epilogue; the work list was built for this shape, so anything
+     * else is refused */
+    if (sh.wj != 1 || mode == 2) return hipErrorInvalidValue;
+    if (sh.wg == 64 && sh.ipl == 1) return go(k_pairs_f64<64, 1>, 64, d, e, mode, s, tm);
+    if (sh.wg == 64 && sh.ipl == 2) return go(k_pairs_f64<64, 2>, 64, d, e, mode, s, tm);
+    if (sh.wg == 256 && sh.ipl == 1) return go(k_pairs_f64<256, 1>, 256, d, e, mode, s, tm);
+    if (sh.wg == 256 && sh.ipl == 2) return go(k_pairs_f64<256, 2>, 256, d, e, mode, s, tm);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_epilogue(const Dev& d, const Coef& c, int prec, int integrator, int stage, int pack_next,
-                           double* u_aos, hipStream_t s) {
-    hipLaunchKernelGGL(k_epilogue, blocks_for(d.Ntot, 64), dim3(192), 0, s, d, c, prec, integrator, stage,
-                       pack_next, u_aos);
+hipError_t launch_epilogue(const Dev& d, const Epi& e, hipStream_t s) {
+    hipLaunchKernelGGL(k_epilogue, blocks_for(d.Ntot, EPI_S), dim3(EPI_T), 0, s, d, e);
     return hipGetLastError();
 }
 
-hipError_t launch_steric_pack(const Dev& d, const Coef& c, int prec, int /*stage*/, hipStream_t s) {
+hipError_t launch_steric_pack(const Dev& d, const Coef& c, int prec, hipStream_t s) {
     hipLaunchKernelGGL(k_steric_pack, blocks_for(d.Stot, 128), dim3(128), 0, s, d, c, prec);
     return hipGetLastError();
 }

@@ -51,7 +51,8 @@ struct ad_ctx {
     /* workspace */
     void* ws = nullptr;
     uint64_t ws_bytes = 0;
-    Dev dev{};
+    Dev dev{};     /* even stages: read pack 0, write pack 1 */
+    Dev dev_odd{}; /* odd stages: read pack 1, write pack 0 */
     bool state = false;
     double t0 = 0.0;
     long long step = 0;
@@ -109,6 +110,7 @@ static ad_launch default_launch(const ad_ctx* c) {
     for (int b = 0; b < c->nsys; ++b) maxN = std::max(maxN, 2 * c->S[b]);
     L.wj = 1;
     L.posmode = c->p.precision == AD_FP32C ? AD_POS_HILO : 0;
+    L.fuse = AD_FUSE_OFF;
     if (c->p.precision == AD_FP64) {
         L.ipl = 1;
         L.wg = 64;
@@ -143,7 +145,8 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (c->p.precision == AD_FP32C && L.posmode != AD_POS_HILO && L.posmode != AD_POS_SINGLE)
         return fail(c, AD_EINVAL, "launch.posmode must be AD_POS_HILO or AD_POS_SINGLE");
     if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
-    if (L.reserved != 0) return fail(c, AD_EINVAL, "launch.reserved must be 0");
+    if (L.fuse != AD_FUSE_OFF && !(L.fuse == AD_FUSE_ON && c->p.precision == AD_FP32C))
+        return fail(c, AD_EINVAL, "launch.fuse must be AD_FUSE_OFF, or AD_FUSE_ON in AD_FP32C");
     return AD_OK;
 }
 
@@ -157,6 +160,7 @@ static ad::Shape shape_of(const ad_ctx* c) {
     sh.ipl = c->launch.ipl;
     sh.split = c->launch.posmode == AD_POS_HILO ? 1 : 0;
     sh.steric = uses_lists(c) ? 1 : 0;
+    sh.fuse = c->launch.fuse == AD_FUSE_ON ? 1 : 0;
     return sh;
 }
 
@@ -202,8 +206,8 @@ static void build_items(ad_ctx* c) {
 /* ------------------------------------------------------------ workspace */
 
 struct Layout {
-    size_t ctl, X, R, U0, Y, Fs, nbr_cnt, nbr_idx, phitrig, dsys, sys_off, sys_P, sys_pbase, items, pA, pB, pC, pD,
-        part, tab, total;
+    size_t ctl, X, R, U0, Y, Fs, blk_cnt, nbr_cnt, nbr_idx, phitrig, dsys, sys_off, sys_P, sys_pbase, items, pA,
+        pB, pC, pD, pA2, pB2, pC2, pD2, part, tab, total;
 };
 
 static Layout layout(const ad_ctx* c) {
@@ -222,6 +226,7 @@ static Layout layout(const ad_ctx* c) {
     const bool steric = c->p.steric_k != 0.0;
     L.Y = take(steric ? 3 * N * 8 : 0);
     L.Fs = take(steric ? 3 * N * 8 : 0);
+    L.blk_cnt = take(N * 4);
     L.nbr_cnt = take(uses_lists(c) ? N * 4 : 0);
     L.nbr_idx = take(uses_lists(c) ? N * 4 * ad::NBR_CAP : 0);
     L.phitrig = take(S * 16);
@@ -235,6 +240,10 @@ static Layout layout(const ad_ctx* c) {
     L.pB = take(f32 ? N * 16 : 0);
     L.pC = take(f32 ? N * 4 : 0);
     L.pD = take(f32 ? 0 : 3 * N * 16);
+    L.pA2 = take(f32 ? N * 16 : 0);
+    L.pB2 = take(f32 ? N * 16 : 0);
+    L.pC2 = take(f32 ? N * 4 : 0);
+    L.pD2 = take(f32 ? 0 : 3 * N * 16);
     L.part = take((size_t)c->npart * 8);
     L.tab = take((size_t)kRing * 8 * 8);
     L.total = o;
@@ -251,6 +260,7 @@ static void make_dev(ad_ctx* c) {
     d.U0 = reinterpret_cast<double*>(b + L.U0);
     d.Y = reinterpret_cast<double*>(b + L.Y);
     d.Fs = reinterpret_cast<double*>(b + L.Fs);
+    d.blk_cnt = reinterpret_cast<int*>(b + L.blk_cnt);
     d.nbr_cnt = uses_lists(c) ? reinterpret_cast<int*>(b + L.nbr_cnt) : nullptr;
     d.nbr_idx = uses_lists(c) ? reinterpret_cast<int*>(b + L.nbr_idx) : nullptr;
     {
@@ -270,6 +280,10 @@ static void make_dev(ad_ctx* c) {
     d.pB = reinterpret_cast<float4*>(b + L.pB);
     d.pC = reinterpret_cast<float*>(b + L.pC);
     d.pD = reinterpret_cast<double2*>(b + L.pD);
+    d.pA2 = reinterpret_cast<float4*>(b + L.pA2);
+    d.pB2 = reinterpret_cast<float4*>(b + L.pB2);
+    d.pC2 = reinterpret_cast<float*>(b + L.pC2);
+    d.pD2 = reinterpret_cast<double2*>(b + L.pD2);
     d.part = reinterpret_cast<double*>(b + L.part);
     d.tab = reinterpret_cast<const double*>(b + L.tab);
     d.ring = kRing;
@@ -277,6 +291,16 @@ static void make_dev(ad_ctx* c) {
     d.Stot = c->Stot;
     d.nsys = c->nsys;
     d.nitems = (int)c->items.size();
+    Dev& o = c->dev_odd;
+    o = d;
+    o.pA = d.pA2;
+    o.pB = d.pB2;
+    o.pC = d.pC2;
+    o.pD = d.pD2;
+    o.pA2 = d.pA;
+    o.pB2 = d.pB;
+    o.pC2 = d.pC;
+    o.pD2 = d.pD;
 }
 
 static void drop_graph(ad_ctx* c) {
@@ -363,36 +387,49 @@ static int profile_flush(ad_ctx* c) {
     return AD_OK;
 }
 
-static int launch_pairs_timed(ad_ctx* c, int prec, int bump, hipStream_t st) {
+static ad::Epi epi_of(const ad_ctx* c, int stage, double* u_aos) {
+    ad::Epi e;
+    e.c = c->coef;
+    e.prec = prec_of(c);
+    e.integ = c->p.integrator;
+    e.stage = stage;
+    e.nst = c->p.integrator == AD_RK4 ? 4 : 2;
+    e.pack_next = c->p.steric_k == 0.0 ? 1 : 0;
+    e.u_aos = u_aos;
+    return e;
+}
+
+static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mode, hipStream_t st) {
+    const ad::Shape sh = shape_of(c);
     if (!c->profile) {
-        HIPCHECK(c, ad::launch_pairs(c->dev, prec, shape_of(c), bump, st));
+        HIPCHECK(c, ad::launch_pairs(d, e, sh, mode, st));
         return AD_OK;
     }
     if (c->ev.empty()) {
         c->ev.resize(2 * kEventPairs);
-        for (auto& e : c->ev) HIPCHECK(c, hipEventCreate(&e));
+        for (auto& ev : c->ev) HIPCHECK(c, hipEventCreate(&ev));
     }
     if (c->ev_used == kEventPairs) {
         int rc = profile_flush(c);
         if (rc != AD_OK) return rc;
     }
-    HIPCHECK(c, hipEventRecord(c->ev[2 * c->ev_used], st));
-    HIPCHECK(c, ad::launch_pairs(c->dev, prec, shape_of(c), bump, st));
-    HIPCHECK(c, hipEventRecord(c->ev[2 * c->ev_used + 1], st));
+    HIPCHECK(c, ad::launch_pairs(d, e, sh, mode, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
     c->ev_used += 1;
     return AD_OK;
 }
 
 /* launches of one step (no table, no initial pack) */
 static int launch_step_kernels(ad_ctx* c, hipStream_t st) {
-    const int prec = prec_of(c);
     const int nst = c->p.integrator == AD_RK4 ? 4 : 2;
     const bool steric = c->p.steric_k != 0.0;
+    const bool fuse = shape_of(c).fuse != 0;
     for (int s = 0; s < nst; ++s) {
-        int rc = launch_pairs_timed(c, prec, s == 0, st);
+        const Dev& d = (s & 1) ? c->dev_odd : c->dev;
+        const ad::Epi e = epi_of(c, s, nullptr);
+        int rc = launch_pairs_timed(c, d, e, fuse ? 2 : 1, st);
         if (rc != AD_OK) return rc;
-        HIPCHECK(c, ad::launch_epilogue(c->dev, c->coef, prec, c->p.integrator, s, !steric, nullptr, st));
-        if (steric) HIPCHECK(c, ad::launch_steric_pack(c->dev, c->coef, prec, s, st));
+        if (!fuse) HIPCHECK(c, ad::launch_epilogue(d, e, st));
+        if (steric) HIPCHECK(c, ad::launch_steric_pack(d, c->coef, e.prec, st));
     }
     return AD_OK;
 }
@@ -425,7 +462,8 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
         int rc = ensure_graph(c);
         if (rc != AD_OK) return rc;
     }
-    HIPCHECK(c, ad::launch_set_step(c->dev, c->step - 1, st));
+    const unsigned long long nst = c->p.integrator == AD_RK4 ? 4 : 2;
+    HIPCHECK(c, ad::launch_set_ticket(c->dev, (unsigned long long)c->step * nst * c->items.size(), st));
     double s0, c0;
     trig_at(c, c->t0 + (double)c->step * c->p.dt, &s0, &c0);
     HIPCHECK(c, ad::launch_pack_state(c->dev, c->coef, prec, s0, c0, st));
@@ -572,6 +610,7 @@ int ad_set_launch(ad_ctx* c, const ad_launch* L) {
     if (want.jchunk == 0) want.jchunk = def.jchunk;
     if (want.wj == 0) want.wj = (want.wg == def.wg) ? def.wj : 1;
     if (want.posmode == 0) want.posmode = def.posmode;
+    if (want.fuse == 0) want.fuse = def.fuse;
     int rc = validate_launch(c, want);
     if (rc != AD_OK) return rc;
     ad_launch old = c->launch;
@@ -612,7 +651,7 @@ int ad_set_state(ad_ctx* c, const double* X, const double* phi, double t0, int64
                                hipMemcpyHostToDevice, st));
     HIPCHECK(c, ad::launch_state_in(c->dev, X, st));
     HIPCHECK(c, ad::launch_clear_flag(c->dev, st));
-    HIPCHECK(c, ad::launch_clear_lists(c->dev, st));
+    HIPCHECK(c, ad::launch_clear_counts(c->dev, st));
     HIPCHECK(c, hipStreamSynchronize(st));
     c->t0 = t0;
     c->step = step0;
@@ -651,8 +690,9 @@ int ad_mobility_apply(ad_ctx* c, const double* X, const double* F, double* u, vo
     HIPCHECK(c, ad::launch_pack_apply(c->dev, c->coef, prec, X, F, st));
     ad::Shape sh = shape_of(c);
     sh.steric = 0; /* candidate lists belong to the step loop */
-    HIPCHECK(c, ad::launch_pairs(c->dev, prec, sh, 0, st));
-    HIPCHECK(c, ad::launch_epilogue(c->dev, c->coef, prec, c->p.integrator, 0, 0, u, st));
+    const ad::Epi e = epi_of(c, 0, u);
+    HIPCHECK(c, ad::launch_pairs(c->dev, e, sh, 0, st));
+    HIPCHECK(c, ad::launch_epilogue(c->dev, e, st));
     return AD_OK;
 }
 
