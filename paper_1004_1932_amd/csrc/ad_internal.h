@@ -18,9 +18,12 @@ struct Item {
 
 /* Device control block at the start of the workspace. */
 struct Ctl {
-    unsigned long long ticket; /* pair-kernel work-group tickets taken so far */
-    int flag;                  /* FLAG_* bits, sticky until cleared */
-    int pad[13];
+    /* step index as seen by even (slot 0) and odd (slot 1) stages: stage 0
+     * copies slot 0 into slot 1, the last stage stores slot 1 + 1 into slot
+     * 0, so no kernel reads a slot that it writes */
+    long long slot[2];
+    int flag; /* FLAG_* bits, sticky until cleared */
+    int pad[11];
 };
 
 enum {
@@ -104,7 +107,7 @@ struct Shape {
 };
 
 /* kernel launchers (ad_kernels.hip) */
-hipError_t launch_set_ticket(const Dev& d, unsigned long long value, hipStream_t s);
+hipError_t launch_set_step(const Dev& d, long long step, hipStream_t s);
 hipError_t launch_clear_flag(const Dev& d, hipStream_t s);
 hipError_t launch_clear_counts(const Dev& d, hipStream_t s);
 hipError_t launch_state_in(const Dev& d, const double* Xaos, hipStream_t s);

@@ -155,7 +155,7 @@ __device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const 
 
 /* ------------------------------------------------------------ small kernels */
 
-__global__ void k_set_ticket(Ctl* ctl, unsigned long long v) { ctl->ticket = v; }
+__global__ void k_set_step(Ctl* ctl, long long v) { ctl->slot[0] = v; }
 __global__ void k_clear_flag(Ctl* ctl) { ctl->flag = 0; }
 
 __global__ void k_state_in(Dev d, const double* __restrict__ Xa) {
@@ -400,7 +400,8 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
 }
 
 /* the epilogue as its own kernel: EPI_S spheres per work-group of EPI_T
- * threads; the step index follows from the tickets the pair kernel took */
+ * threads; the step index comes from the slot the pair kernel left for this
+ * stage */
 constexpr int EPI_S = 32;
 constexpr int EPI_T = 96;
 
@@ -410,8 +411,7 @@ __global__ __launch_bounds__(EPI_T) void k_epilogue(Dev d, Epi e) {
     __shared__ int badf;
     const int i0 = blockIdx.x * EPI_S;
     const int ni = min(EPI_S, d.Ntot - i0);
-    const long long step =
-        e.u_aos ? 0 : (long long)((d.ctl->ticket - 1ULL) / ((unsigned long long)e.nst * (unsigned long long)d.nitems));
+    const long long step = e.u_aos ? 0 : d.ctl->slot[e.stage & 1];
     epi_block(d, e, i0, ni, step, ys, mv, &badf);
 }
 
@@ -443,14 +443,13 @@ __device__ __noinline__ void add_candidate(const Dev& d, int i, int iend, int j)
         atomicOr(&d.ctl->flag, FLAG_NBR_FULL);
 }
 
-/* Start of a pair kernel in a step: one ticket per work-group. Tickets of
- * step n, stage s are [(n*nst + s)*nitems, (n*nst + s + 1)*nitems), so the
- * step index needs no counter that the same kernel would both read and
- * write. */
-__device__ __forceinline__ long long take_ticket(const Dev& d, const Epi& e, unsigned long long* s_tk) {
-    if (threadIdx.x == 0) *s_tk = atomicAdd(&d.ctl->ticket, 1ULL);
-    __syncthreads();
-    return (long long)(*s_tk / ((unsigned long long)e.nst * (unsigned long long)d.nitems));
+/* Step bookkeeping of a pair kernel in a step (one thread): stage 0 copies
+ * slot 0 into slot 1, the last stage advances slot 0. Readers of this
+ * kernel read the other slot. */
+__device__ __forceinline__ void advance_slots(const Dev& d, const Epi& e) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    if (e.stage == 0) d.ctl->slot[1] = d.ctl->slot[0];
+    if (e.stage == e.nst - 1) d.ctl->slot[0] = d.ctl->slot[1] + 1;
 }
 
 /* End of a pair kernel with the fused epilogue: the work-group that
@@ -497,21 +496,27 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
     constexpr int IB = 64 * WI * IPL;
     /* one LDS area, used in turn by the source tiles, the cross-wave
      * combination and the fused epilogue (barriers separate the uses) */
-    constexpr int TILE_B = TJ * (16 + 16 + 4);
-    constexpr int RED_B = (WJ > 1 ? WJ : 1) * IB * 6 * 4;
-    constexpr int EPI_B = IB * 3 * 8 * 2;
-    constexpr int LDS_B = TILE_B > RED_B ? (TILE_B > EPI_B ? TILE_B : EPI_B) : (RED_B > EPI_B ? RED_B : EPI_B);
-    __shared__ __align__(16) unsigned char lds[LDS_B];
-    float4* sA = reinterpret_cast<float4*>(lds);
-    float4* sB = sA + TJ;
-    float* sC = reinterpret_cast<float*>(sB + TJ);
-    float* red = reinterpret_cast<float*>(lds); /* [WJ][IB][6] */
-    double(*ys)[3] = reinterpret_cast<double(*)[3]>(lds);
-    double(*mv)[3] = reinterpret_cast<double(*)[3]>(lds + IB * 3 * 8);
-    __shared__ unsigned long long s_tk;
+    union Lds {
+        struct {
+            float4 A[TJ];
+            float4 B[TJ];
+            float C[TJ];
+        } tile;
+        float red[WJ > 1 ? WJ : 1][IB][6];
+        struct {
+            double ys[IB][3];
+            double mv[IB][3];
+        } epi;
+    };
+    __shared__ Lds lds;
+    float4* sA = lds.tile.A;
+    float4* sB = lds.tile.B;
+    float* sC = lds.tile.C;
+    double(*ys)[3] = lds.epi.ys;
+    double(*mv)[3] = lds.epi.mv;
     __shared__ int s_last, s_bad;
     const Item it = d.items[blockIdx.x];
-    const long long step = mode ? take_ticket(d, e, &s_tk) : 0;
+    if (mode) advance_slots(d, e);
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -634,7 +639,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
         if (wj > 0) {
 #pragma unroll
             for (int q = 0; q < IPL; ++q) {
-                float* r = red + ((wj * IB) + slot * IPL + q) * 6;
+                float* r = lds.red[wj][slot * IPL + q];
                 r[0] = ax[q]; r[1] = bx[q]; r[2] = ay[q]; r[3] = by[q]; r[4] = az[q]; r[5] = bz[q];
             }
         }
@@ -644,7 +649,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
             for (int w = 1; w < WJ; ++w) {
 #pragma unroll
                 for (int q = 0; q < IPL; ++q) {
-                    const float* r = red + ((w * IB) + slot * IPL + q) * 6;
+                    const float* r = lds.red[w][slot * IPL + q];
                     two_sum_acc(ax[q], bx[q], r[0]); bx[q] = bx[q] + r[1];
                     two_sum_acc(ay[q], by[q], r[2]); by[q] = by[q] + r[3];
                     two_sum_acc(az[q], bz[q], r[4]); bz[q] = bz[q] + r[5];
@@ -665,7 +670,8 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
             }
         }
     }
-    if (mode == 2 && last_of_block(d, it, &s_last)) epi_block(d, e, it.i0, it.ni, step, ys, mv, &s_bad);
+    if (mode == 2 && last_of_block(d, it, &s_last))
+        epi_block(d, e, it.i0, it.ni, d.ctl->slot[e.stage & 1], ys, mv, &s_bad);
 }
 
 /* FP64: the sum in ascending j with the plain operation order
@@ -677,9 +683,8 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
 template <int WG, int IPL>
 __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
     __shared__ double2 sD[3][WG];
-    __shared__ unsigned long long s_tk;
     const Item it = d.items[blockIdx.x];
-    if (mode) take_ticket(d, e, &s_tk);
+    if (mode) advance_slots(d, e);
     const int t = threadIdx.x;
     const int ib = it.i0 + t * IPL;
     const int iend = it.i0 + it.ni;
@@ -866,8 +871,8 @@ __global__ void k_record(Dev d, double* __restrict__ centres, double* __restrict
 
 static inline dim3 blocks_for(int n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
-hipError_t launch_set_ticket(const Dev& d, unsigned long long value, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_ticket, dim3(1), dim3(1), 0, s, d.ctl, value);
+hipError_t launch_set_step(const Dev& d, long long step, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, d.ctl, step);
     return hipGetLastError();
 }
 

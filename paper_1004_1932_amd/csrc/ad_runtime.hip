@@ -462,8 +462,7 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
         int rc = ensure_graph(c);
         if (rc != AD_OK) return rc;
     }
-    const unsigned long long nst = c->p.integrator == AD_RK4 ? 4 : 2;
-    HIPCHECK(c, ad::launch_set_ticket(c->dev, (unsigned long long)c->step * nst * c->items.size(), st));
+    HIPCHECK(c, ad::launch_set_step(c->dev, c->step, st));
     double s0, c0;
     trig_at(c, c->t0 + (double)c->step * c->p.dt, &s0, &c0);
     HIPCHECK(c, ad::launch_pack_state(c->dev, c->coef, prec, s0, c0, st));
