@@ -8,6 +8,7 @@
  *                 + 1/(8 pi eta) sum_{j != i} [F_j/r + r (r.F_j)/r^3],
  *   r = X_i - X_j                       (Sec. II, Eq. e:langevin at zero
  *                                        temperature; Eq. e:Mazur, Oseen part)
+ *   (AD_RPY adds the finite-size correction of Eq. e:Mazur, second line)
  *   F = -grad U, U = sum_s k/2 (d_s - L_s(t))^2,
  *   L_s(t) = ell + lambda sin(omega t + phi_s), omega = 2 pi / T
  *                                       (Sec. II, Eq. e:swimmer_potential)
@@ -64,7 +65,10 @@ extern "C" {
 #define AD_HEUN 1 /* Sec. V: x~ = x + dt u(x,t); x' = x + dt/2 (u(x,t) + u(x~,t+dt)) */
 
 /* pair tensor (ad_params.tensor) */
-#define AD_OSEEN 0
+#define AD_OSEEN 0 /* (I + rr/r^2)/(8 pi eta r), Sec. II, Eq. e:Mazur first line */
+#define AD_RPY 1   /* Oseen plus the Rotne-Prager-Yamakawa-Mazur correction
+                      2a^2/(24 pi eta r^3) (I - 3 rr/r^2), Eq. e:Mazur second line,
+                      applied at every distance */
 
 typedef struct ad_params {
     double a;        /* sphere radius, > 0 */
@@ -78,7 +82,7 @@ typedef struct ad_params {
     double steric_r; /* steric contact distance, force steric_k (steric_r - r) for r < steric_r */
     int32_t precision;  /* AD_FP64 | AD_FP64_TILED | AD_FP32C */
     int32_t integrator; /* AD_RK4 | AD_HEUN */
-    int32_t tensor;     /* AD_OSEEN */
+    int32_t tensor;     /* AD_OSEEN | AD_RPY */
     int32_t reserved;   /* must be 0 */
 } ad_params;
 

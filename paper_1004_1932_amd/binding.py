@@ -16,7 +16,8 @@ LIB_PATH = Path(__file__).resolve().parent / "libad.so"
 AD_OK, AD_EINVAL, AD_ENOMEM, AD_EDEVICE, AD_ESTATE, AD_ENONFINITE, AD_ERANGE = 0, -1, -2, -3, -4, -5, -6
 AD_FP64, AD_FP64_TILED, AD_FP32C = 0, 1, 2
 AD_RK4, AD_HEUN = 0, 1
-AD_OSEEN = 0
+AD_OSEEN, AD_RPY = 0, 1
+TENSORS = {"oseen": AD_OSEEN, "rpy": AD_RPY}
 
 PRECISIONS = {"fp64": AD_FP64, "fp64_tiled": AD_FP64_TILED, "fp32c": AD_FP32C}
 INTEGRATORS = {"rk4": AD_RK4, "heun": AD_HEUN}
@@ -112,15 +113,16 @@ def _dev(t, name, shape=None):
     return C.c_void_p(t.data_ptr())
 
 
-def make_params(p, precision="fp32c", integrator="rk4") -> ad_params:
+def make_params(p, precision="fp32c", integrator="rk4", tensor="oseen") -> ad_params:
     """ad_params from any object with a, eta, k, ell, lam, T, dt (steric_k,
     steric_r optional)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     integ = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    ten = TENSORS[tensor] if isinstance(tensor, str) else int(tensor)
     lam = getattr(p, "lam", getattr(p, "lambda_", None))
     return ad_params(float(p.a), float(p.eta), float(p.k), float(p.ell), float(lam), float(p.T),
                      float(p.dt), float(getattr(p, "steric_k", 0.0)), float(getattr(p, "steric_r", 0.0)),
-                     prec, integ, AD_OSEEN, 0)
+                     prec, integ, ten, 0)
 
 
 # ---------------------------------------------------------------- 1:1 entry points
@@ -243,7 +245,7 @@ class Simulator:
     """A context plus its workspace tensor on one device."""
 
     def __init__(self, params, S_per_sys, precision="fp32c", integrator="rk4", device="cuda:0",
-                 launch=None, graph=False):
+                 launch=None, graph=False, tensor="oseen"):
         """launch: None (library default), a dict of ad_launch fields, or
         "tuned" (the autotuned shape for this size bucket, if any)."""
         import torch
@@ -252,7 +254,7 @@ class Simulator:
         self.nsys = int(self.S_per_sys.shape[0])
         self.Stot = int(self.S_per_sys.sum())
         self.N = 2 * self.Stot
-        self._p = make_params(params, precision, integrator)
+        self._p = make_params(params, precision, integrator, tensor)
         self._graph = bool(graph)
         if launch == "tuned":
             from .autotune import tuned_launch

@@ -48,6 +48,9 @@ struct Coef {
     double dt6;  /* dt/6.0 */
     double ks;   /* steric strength (0: off) */
     double rc;   /* steric contact distance */
+    double cr;   /* 2 a^2/(24 pi eta): Rotne-Prager-Yamakawa-Mazur coefficient */
+    float crr;   /* cr / co = 2 a^2 / 3, for the FP32 pair sum */
+    int rpy;     /* 1: Oseen plus the RPY-Mazur correction; 0: Oseen */
 };
 
 /* Device views into the workspace. */
@@ -81,6 +84,8 @@ struct Dev {
     const double* tab;  /* [ring][8] (sin, cos) of omega*t per epilogue stage */
     int ring;           /* entries in tab */
     int Ntot, Stot, nsys, nitems;
+    int ncomp; /* partial-sum components per sphere: 3, or 6 for FP64 with RPY
+                  (Oseen and correction summed apart, as the plain sum does) */
 };
 
 enum { PREC_FP64 = 0, PREC_FP64_TILED = 1, PREC_FP32C = 2 };
@@ -102,6 +107,7 @@ struct Epi {
  * target spheres. */
 struct Shape {
     int wg, wj, ipl, split;
+    int rpy;    /* pair tensor with the RPY-Mazur correction */
     int steric; /* FP32C: record steric candidates while summing */
     int fuse;   /* FP32C: epilogue in the pair kernel's last work-group per block */
 };

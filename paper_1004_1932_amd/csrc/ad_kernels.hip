@@ -59,6 +59,21 @@ __device__ __forceinline__ void oseen_term64(const double r[3], const double F[3
     out[2] = ir * (F[2] + t * r[2]);
 }
 
+/* Rotne-Prager-Yamakawa-Mazur correction of one source sphere in FP64,
+ * without its 2a^2/(24 pi eta) factor: (F - 3 r (r.F)/r^2)/r^3, in the
+ * operation order of the plain sum. */
+__device__ __forceinline__ void rpy_term64(const double r[3], const double F[3], double out[3]) {
+    double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+    double ir = 1.0 / sqrt(r2);
+    double fr = (r[0] * F[0] + r[1] * F[1]) + r[2] * F[2];
+    double t = fr / r2;
+    double ir3 = ir / r2;
+    double t3 = 3.0 * t;
+    out[0] = ir3 * (F[0] - t3 * r[0]);
+    out[1] = ir3 * (F[1] - t3 * r[1]);
+    out[2] = ir3 * (F[2] - t3 * r[2]);
+}
+
 /* Steric sum for sphere i over the spheres [j0, j1) of its system: for
  * 0 < r < rc, ks (rc - r) (X_i - X_j)/r, ascending j. Positions are read
  * through `get`. Returns non-zero if a coincident sphere was met. */
@@ -125,6 +140,14 @@ __device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const 
         for (int a = 0; a < 3; ++a) {
             d.U0[a * N + i0] = c.cs * f0[a] + c.co * t0[a];
             d.U0[a * N + i1] = c.cs * f1[a] + c.co * t1[a];
+        }
+        if (c.rpy) {
+            rpy_term64(r, f1, t0);
+            rpy_term64(rm, f0, t1);
+            for (int a = 0; a < 3; ++a) {
+                d.U0[a * N + i0] = d.U0[a * N + i0] + c.cr * t0[a];
+                d.U0[a * N + i1] = d.U0[a * N + i1] + c.cr * t1[a];
+            }
         }
         float4* pA = nxt ? d.pA2 : d.pA;
         float4* pB = nxt ? d.pB2 : d.pB;
@@ -306,7 +329,7 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
         const int off = d.sys_off[b];
         const int Nb = d.sys_off[b + 1] - off;
         const int P = d.sys_P[b];
-        const long long stride = 3LL * Nb;
+        const long long stride = (long long)d.ncomp * Nb;
         const double* p = d.part + d.sys_pbase[b] + (long long)a * Nb + (i - off);
         const int o = a * N + i;
         /* independent loads first, so they are in flight together */
@@ -328,7 +351,15 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
             for (int q = 0; q < EPI_MAXP; ++q)
                 if (cc + q < P) acc = acc + v[q];
         }
-        const double k = u0 + c.co * acc;
+        double k = u0 + c.co * acc;
+        if (d.ncomp == 6) {
+            /* FP64 with RPY: the correction's partial sums follow the Oseen
+             * ones, added after them as in the plain sum */
+            const double* p2 = p + 3LL * Nb;
+            double acc2 = p2[0];
+            for (int cc = 1; cc < P; ++cc) acc2 = acc2 + p2[cc * stride];
+            k = k + c.cr * acc2;
+        }
         if (!isfinite(k)) *badf = 1;
         if (apply) {
             e.u_aos[3 * i + a] = k;
@@ -417,6 +448,29 @@ __global__ __launch_bounds__(EPI_T) void k_epilogue(Dev d, Epi e) {
 
 /* ------------------------------------------------------------ pair sums */
 
+/* Accumulate one FP32 pair term given ir = 1/r (0 for a skipped pair):
+ * Oseen: ir (F + t r), t = (r.F) ir^2; with RPY (c' = 2a^2/3):
+ * F (ir + c' ir^3) + r t (ir - 3 c' ir^3). */
+template <int RPY>
+__device__ __forceinline__ void pair_term(float ir, float rx, float ry, float rz, float Fx, float Fy, float Fz,
+                                          float crr, float& px, float& py, float& pz) {
+    const float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Fy, rx * Fx));
+    const float ir2 = ir * ir;
+    const float tt = fr * ir2;
+    if (RPY) {
+        const float ir3 = ir * ir2;
+        const float av = __builtin_fmaf(crr, ir3, ir);
+        const float bv = tt * __builtin_fmaf(-3.0f * crr, ir3, ir);
+        px = __builtin_fmaf(av, Fx, __builtin_fmaf(bv, rx, px));
+        py = __builtin_fmaf(av, Fy, __builtin_fmaf(bv, ry, py));
+        pz = __builtin_fmaf(av, Fz, __builtin_fmaf(bv, rz, pz));
+    } else {
+        px = __builtin_fmaf(ir, __builtin_fmaf(tt, rx, Fx), px);
+        py = __builtin_fmaf(ir, __builtin_fmaf(tt, ry, Fy), py);
+        pz = __builtin_fmaf(ir, __builtin_fmaf(tt, rz, Fz), pz);
+    }
+}
+
 /* One thread's entry of a source tile: sphere t0 + t of the pack, or
  * padding (far away and force-free, so it contributes exactly zero). */
 __device__ __forceinline__ void load_tile_entry(const Dev& d, int t0, int jend, int t, float4& A, float4& B,
@@ -486,9 +540,12 @@ __device__ __forceinline__ bool last_of_block(const Dev& d, const Item& it, int*
  *   STERIC = 1: every pair closer than rc + skin (r^2 is at hand) is appended
  *              to the target's candidate list for the next stage's steric
  *              forces.
+ *   RPY = 1: the pair tensor carries the Rotne-Prager-Yamakawa-Mazur
+ *              correction, summed with the Oseen part as
+ *              F (ir + c' ir^3) + r t (ir - 3 c' ir^3), c' = 2a^2/3.
  * mode: 0 = mobility apply, 1 = step stage, 2 = step stage with the fused
  * epilogue. */
-template <int WG, int IPL, int WJ, int SPLIT, int STERIC>
+template <int WG, int IPL, int WJ, int SPLIT, int STERIC, int RPY>
 __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
     constexpr int WI = WG / 64 / WJ;
     constexpr int TJ = WG;          /* j per LDS tile */
@@ -549,6 +606,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
     const int dlo = it.i0 & ~1;
     const int dhi = (iend + 1) & ~1;
     const int jend = it.j0 + it.nj;
+    const float crr = e.c.crr;
 
     float4 A, B;
     float C;
@@ -587,11 +645,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
                         float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                         if (STERIC && r2 < d.list_r2) add_candidate(d, ib + q, iend, t0 + jj + u);
                         float ir = __builtin_amdgcn_rsqf(r2);
-                        float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Bj.w, rx * Aj.w));
-                        float tt = fr * (ir * ir);
-                        px[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, rx, Aj.w), px[q]);
-                        py[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, ry, Bj.w), py[q]);
-                        pz[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, rz, Fz), pz[q]);
+                        pair_term<RPY>(ir, rx, ry, rz, Aj.w, Bj.w, Fz, crr, px[q], py[q], pz[q]);
                     }
                 }
             }
@@ -616,11 +670,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
                     float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                     if (STERIC && r2 < d.list_r2 && t0 + jj != ib + q) add_candidate(d, ib + q, iend, t0 + jj);
                     float ir = (dj == dq[q]) ? 0.f : __builtin_amdgcn_rsqf(r2);
-                    float fr = __builtin_fmaf(rz, Fz, __builtin_fmaf(ry, Bj.w, rx * Aj.w));
-                    float tt = fr * (ir * ir);
-                    px[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, rx, Aj.w), px[q]);
-                    py[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, ry, Bj.w), py[q]);
-                    pz[q] = __builtin_fmaf(ir, __builtin_fmaf(tt, rz, Fz), pz[q]);
+                    pair_term<RPY>(ir, rx, ry, rz, Aj.w, Bj.w, Fz, crr, px[q], py[q], pz[q]);
                 }
             }
         }
@@ -658,7 +708,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
         }
     }
     if (wj == 0) {
-        const long long base = d.sys_pbase[it.sys] + (long long)it.c * 3 * it.Nb;
+        const long long base = d.sys_pbase[it.sys] + (long long)it.c * d.ncomp * it.Nb;
 #pragma unroll
         for (int q = 0; q < IPL; ++q) {
             const int i = ib + q;
@@ -679,8 +729,9 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
  *   t = fr/r2; acc = acc + ir*(F + t*r)
  * over every j != i of the chunk (partner included). A coincident pair is
  * skipped and raises the flag. With one chunk per system this is the
- * sequential FP64 sum exactly. */
-template <int WG, int IPL>
+ * sequential FP64 sum exactly. With RPY the correction
+ * (F - 3 t r) ir/r2 is summed in a second accumulator. */
+template <int WG, int IPL, int RPY>
 __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
     __shared__ double2 sD[3][WG];
     const Item it = d.items[blockIdx.x];
@@ -688,7 +739,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
     const int t = threadIdx.x;
     const int ib = it.i0 + t * IPL;
     const int iend = it.i0 + it.ni;
-    double xi[IPL], yi[IPL], zi[IPL], ax[IPL], ay[IPL], az[IPL];
+    double xi[IPL], yi[IPL], zi[IPL], ax[IPL], ay[IPL], az[IPL], bx[IPL], by[IPL], bz[IPL];
 #pragma unroll
     for (int q = 0; q < IPL; ++q) {
         const int i = ib + q;
@@ -699,6 +750,7 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
         }
         xi[q] = p0.x; yi[q] = p0.y; zi[q] = p1.x;
         ax[q] = ay[q] = az[q] = 0.0;
+        bx[q] = by[q] = bz[q] = 0.0;
     }
     int bad = 0;
     const int jend = it.j0 + it.nj;
@@ -742,10 +794,20 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
                 ax[q] = skip ? ax[q] : ax[q] + gx;
                 ay[q] = skip ? ay[q] : ay[q] + gy;
                 az[q] = skip ? az[q] : az[q] + gz;
+                if (RPY) {
+                    const double ir3 = ir / r2s;
+                    const double t3 = 3.0 * tt;
+                    const double hx = ir3 * (Fx - t3 * rx);
+                    const double hy = ir3 * (Fy - t3 * ry);
+                    const double hz = ir3 * (Fz - t3 * rz);
+                    bx[q] = skip ? bx[q] : bx[q] + hx;
+                    by[q] = skip ? by[q] : by[q] + hy;
+                    bz[q] = skip ? bz[q] : bz[q] + hz;
+                }
             }
         }
     }
-    const long long base = d.sys_pbase[it.sys] + (long long)it.c * 3 * it.Nb;
+    const long long base = d.sys_pbase[it.sys] + (long long)it.c * d.ncomp * it.Nb;
 #pragma unroll
     for (int q = 0; q < IPL; ++q) {
         const int i = ib + q;
@@ -754,6 +816,11 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
             d.part[base + li] = ax[q];
             d.part[base + it.Nb + li] = ay[q];
             d.part[base + 2 * it.Nb + li] = az[q];
+            if (RPY) {
+                d.part[base + 3 * it.Nb + li] = bx[q];
+                d.part[base + 4 * it.Nb + li] = by[q];
+                d.part[base + 5 * it.Nb + li] = bz[q];
+            }
             if (bad) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
         }
     }
@@ -929,21 +996,31 @@ static hipError_t go(K kern, int wg, const Dev& d, const Epi& e, int mode, hipSt
     return hipGetLastError();
 }
 
-template <int WG, int WJ, int SPLIT, int STERIC>
+template <int WG, int WJ, int SPLIT, int STERIC, int RPY>
 static hipError_t f32c_ipl(const Dev& d, const Epi& e, int ipl, int mode, hipStream_t s, const Timing& tm) {
-    if (ipl == 1) return go(k_pairs_f32c<WG, 1, WJ, SPLIT, STERIC>, WG, d, e, mode, s, tm);
-    if (ipl == 2) return go(k_pairs_f32c<WG, 2, WJ, SPLIT, STERIC>, WG, d, e, mode, s, tm);
-    if (ipl == 4) return go(k_pairs_f32c<WG, 4, WJ, SPLIT, STERIC>, WG, d, e, mode, s, tm);
+    if (ipl == 1) return go(k_pairs_f32c<WG, 1, WJ, SPLIT, STERIC, RPY>, WG, d, e, mode, s, tm);
+    if (ipl == 2) return go(k_pairs_f32c<WG, 2, WJ, SPLIT, STERIC, RPY>, WG, d, e, mode, s, tm);
+    if (ipl == 4) return go(k_pairs_f32c<WG, 4, WJ, SPLIT, STERIC, RPY>, WG, d, e, mode, s, tm);
     return hipErrorInvalidValue;
 }
 
-template <int WG, int WJ>
+template <int WG, int WJ, int RPY>
 static hipError_t f32c_var(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, const Timing& tm) {
     if (sh.steric)
-        return sh.split ? f32c_ipl<WG, WJ, 1, 1>(d, e, sh.ipl, mode, s, tm)
-                        : f32c_ipl<WG, WJ, 0, 1>(d, e, sh.ipl, mode, s, tm);
-    return sh.split ? f32c_ipl<WG, WJ, 1, 0>(d, e, sh.ipl, mode, s, tm)
-                    : f32c_ipl<WG, WJ, 0, 0>(d, e, sh.ipl, mode, s, tm);
+        return sh.split ? f32c_ipl<WG, WJ, 1, 1, RPY>(d, e, sh.ipl, mode, s, tm)
+                        : f32c_ipl<WG, WJ, 0, 1, RPY>(d, e, sh.ipl, mode, s, tm);
+    return sh.split ? f32c_ipl<WG, WJ, 1, 0, RPY>(d, e, sh.ipl, mode, s, tm)
+                    : f32c_ipl<WG, WJ, 0, 0, RPY>(d, e, sh.ipl, mode, s, tm);
+}
+
+template <int WG, int WJ>
+static hipError_t f32c_ten(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, const Timing& tm) {
+    return sh.rpy ? f32c_var<WG, WJ, 1>(d, e, sh, mode, s, tm) : f32c_var<WG, WJ, 0>(d, e, sh, mode, s, tm);
+}
+
+template <int WG, int IPL>
+static hipError_t f64_ten(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, const Timing& tm) {
+    return sh.rpy ? go(k_pairs_f64<WG, IPL, 1>, WG, d, e, mode, s, tm) : go(k_pairs_f64<WG, IPL, 0>, WG, d, e, mode, s, tm);
 }
 
 hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, hipEvent_t ev_start,
@@ -952,19 +1029,19 @@ hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, h
     const Timing tm{ev_start, ev_stop};
     if (e.prec == PREC_FP32C) {
         if (sh.steric && !d.nbr_cnt) return hipErrorInvalidValue;
-        if (sh.wg == 64 && sh.wj == 1) return f32c_var<64, 1>(d, e, sh, mode, s, tm);
-        if (sh.wg == 256 && sh.wj == 1) return f32c_var<256, 1>(d, e, sh, mode, s, tm);
-        if (sh.wg == 256 && sh.wj == 4) return f32c_var<256, 4>(d, e, sh, mode, s, tm);
+        if (sh.wg == 64 && sh.wj == 1) return f32c_ten<64, 1>(d, e, sh, mode, s, tm);
+        if (sh.wg == 256 && sh.wj == 1) return f32c_ten<256, 1>(d, e, sh, mode, s, tm);
+        if (sh.wg == 256 && sh.wj == 4) return f32c_ten<256, 4>(d, e, sh, mode, s, tm);
         return hipErrorInvalidValue;
     }
     /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group and
      * no fused epilogue; the work list was built for this shape, so anything
      * else is refused */
     if (sh.wj != 1 || mode == 2) return hipErrorInvalidValue;
-    if (sh.wg == 64 && sh.ipl == 1) return go(k_pairs_f64<64, 1>, 64, d, e, mode, s, tm);
-    if (sh.wg == 64 && sh.ipl == 2) return go(k_pairs_f64<64, 2>, 64, d, e, mode, s, tm);
-    if (sh.wg == 256 && sh.ipl == 1) return go(k_pairs_f64<256, 1>, 256, d, e, mode, s, tm);
-    if (sh.wg == 256 && sh.ipl == 2) return go(k_pairs_f64<256, 2>, 256, d, e, mode, s, tm);
+    if (sh.wg == 64 && sh.ipl == 1) return f64_ten<64, 1>(d, e, sh, mode, s, tm);
+    if (sh.wg == 64 && sh.ipl == 2) return f64_ten<64, 2>(d, e, sh, mode, s, tm);
+    if (sh.wg == 256 && sh.ipl == 1) return f64_ten<256, 1>(d, e, sh, mode, s, tm);
+    if (sh.wg == 256 && sh.ipl == 2) return f64_ten<256, 2>(d, e, sh, mode, s, tm);
     return hipErrorInvalidValue;
 }
 

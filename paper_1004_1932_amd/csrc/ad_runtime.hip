@@ -160,12 +160,17 @@ static ad::Shape shape_of(const ad_ctx* c) {
     sh.ipl = c->launch.ipl;
     sh.split = c->launch.posmode == AD_POS_HILO ? 1 : 0;
     sh.steric = uses_lists(c) ? 1 : 0;
+    sh.rpy = c->p.tensor == AD_RPY ? 1 : 0;
     sh.fuse = c->launch.fuse == AD_FUSE_ON ? 1 : 0;
     return sh;
 }
 
+/* partial-sum components per sphere: FP64 with RPY keeps the correction apart */
+static int ncomp_of(const ad_ctx* c) { return (c->p.tensor == AD_RPY && c->p.precision != AD_FP32C) ? 6 : 3; }
+
 static void build_items(ad_ctx* c) {
     const ad_launch& L = c->launch;
+    const int NC = ncomp_of(c);
     c->items.clear();
     c->sysP.assign(c->nsys, 1);
     c->pbase.assign(c->nsys, 0);
@@ -177,7 +182,7 @@ static void build_items(ad_ctx* c) {
         const int P = (Nb + jc - 1) / jc;
         c->sysP[b] = P;
         c->pbase[b] = pb;
-        pb += (long long)P * 3 * Nb;
+        pb += (long long)P * NC * Nb;
         for (int ch = 0; ch < P; ++ch) {
             const int j0 = c->off[b] + ch * jc;
             const int nj = std::min(jc, Nb - ch * jc);
@@ -291,6 +296,7 @@ static void make_dev(ad_ctx* c) {
     d.Stot = c->Stot;
     d.nsys = c->nsys;
     d.nitems = (int)c->items.size();
+    d.ncomp = ncomp_of(c);
     Dev& o = c->dev_odd;
     o = d;
     o.pA = d.pA2;
@@ -522,7 +528,7 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
         return fail(nullptr, AD_EINVAL, "unknown precision %d", p->precision);
     if (p->integrator != AD_RK4 && p->integrator != AD_HEUN)
         return fail(nullptr, AD_EINVAL, "unknown integrator %d", p->integrator);
-    if (p->tensor != AD_OSEEN) return fail(nullptr, AD_EINVAL, "unknown tensor %d", p->tensor);
+    if (p->tensor != AD_OSEEN && p->tensor != AD_RPY) return fail(nullptr, AD_EINVAL, "unknown tensor %d", p->tensor);
     if (p->reserved != 0) return fail(nullptr, AD_EINVAL, "reserved must be 0");
     long long Stot = 0;
     for (int b = 0; b < nsys; ++b) {
@@ -553,6 +559,9 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
     k.dt6 = p->dt / 6.0;
     k.ks = p->steric_k;
     k.rc = p->steric_r;
+    k.cr = 2.0 * p->a * p->a / (24.0 * kPi * p->eta);
+    k.crr = (float)(2.0 * p->a * p->a / 3.0);
+    k.rpy = p->tensor == AD_RPY ? 1 : 0;
     c->omega = 2.0 * kPi / p->T;
     c->launch = default_launch(c);
     build_items(c);

@@ -62,6 +62,11 @@ def test_create_rejects_bad_sizes_and_enums():
     bad.integrator = 3
     with pytest.raises(P.ADError):
         P.ad_create(bad, [4])
+    bad = P.make_params(Params())
+    bad.tensor = 5
+    with pytest.raises(P.ADError):
+        P.ad_create(bad, [4])
+    P.ad_destroy(P.ad_create(P.make_params(Params(), tensor="rpy"), [4]))
 
 
 def test_calls_before_workspace_fail_cleanly():

@@ -419,3 +419,59 @@ def test_large_steric_workload_runs_clean(oracle):
     assert np.isfinite(Xg).all() and np.abs(Xg - sus.X).max() < 0.1
     del s
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- RPY-Mazur tensor
+
+@pytest.mark.parametrize("S,side", [(1, 8.0), (8, 40.0), (150, 90.0)])
+def test_rpy_mobility_fp64_bitwise(oracle, S, side):
+    """Eq. (e:Mazur) with its second line: FP64 bitwise against the oracle."""
+    _torch()
+    sus = make_single(S, side, 12)
+    F = np.random.default_rng(13).standard_normal(sus.X.shape)
+    s = P.Simulator(sus.params, [sus.S], precision="fp64", tensor="rpy")
+    u = s.mobility(sus.X, F).cpu().numpy()
+    assert np.array_equal(u, oracle.mobility(sus.params, sus.X, F, tensor=1))
+
+
+def test_rpy_trajectory_fp64_bitwise(oracle):
+    _torch()
+    sus = make_preset("n16")
+    s = P.Simulator(sus.params, [sus.S], precision="fp64", tensor="rpy", graph=True)
+    s.set_state(sus.X, sus.phi)
+    cen, com, code = s.run(1000, 250)
+    assert code == 0
+    Xo, co, mo, _ = oracle.run(sus.params, sus.X, sus.phi, 1000, record_every=250, tensor=1)
+    assert np.array_equal(s.get_state()[0].cpu().numpy(), Xo)
+    assert np.array_equal(com.cpu().numpy(), mo)
+
+
+@pytest.mark.parametrize("precision,launch", [("fp64_tiled", None), ("fp32c", None),
+                                              ("fp32c", dict(wg=256, wj=4, ipl=2, jchunk=512, posmode=2)),
+                                              ("fp32c", dict(wg=64, wj=1, ipl=4, jchunk=128, fuse=1))])
+def test_rpy_mobility_tolerances(oracle, precision, launch):
+    _torch()
+    sus = make_single(900, 160.0, 14)
+    X = perturbed(sus, 0.2)
+    F = oracle.forces(sus.params, X, sus.phi, 3.0)
+    s = P.Simulator(sus.params, [sus.S], precision=precision, tensor="rpy", launch=launch)
+    err = relerr(s.mobility(X, F).cpu().numpy(), oracle.mobility(sus.params, X, F, tensor=1))
+    say(f"  rpy {precision} {launch} rel err {err:.2e}")
+    assert err <= (1e-13 if precision == "fp64_tiled" else 1e-6)
+
+
+def test_rpy_trajectory_fp32c(oracle):
+    """FP32C with the RPY tensor: 2000 RK4 steps of 512 spheres, centre
+    displacement drift <= 1e-4 against the oracle."""
+    _torch()
+    sus = make_preset("n512")
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c", tensor="rpy", graph=True,
+                    launch=dict(wg=256, wj=4, ipl=1, jchunk=256, fuse=2))
+    s.set_state(sus.X, sus.phi)
+    cen, com, code = s.run(2000, 500)
+    assert code == 0
+    Xo, co, mo, _ = oracle.run(sus.params, sus.X, sus.phi, 2000, record_every=500, tensor=1)
+    R0 = 0.5 * (sus.X[0::2] + sus.X[1::2])
+    drift = max(relerr(cen.cpu().numpy()[r] - R0, co[r] - R0) for r in range(len(co)))
+    say(f"  rpy fp32c drift {drift:.2e}")
+    assert drift <= 1e-4
