@@ -370,3 +370,106 @@ int adref_run(const adref_params* p, int32_t nsys, const int64_t* off, double* X
     }
     return status;
 }
+
+/* ------------------------------------------------------------------------
+ * Stroke-averaged far-field equations (Sec. III, Eqs. e:eom, J, K and the
+ * projections s, r, q): for dumbbells with centres R, unit axes N and phases
+ * phi,
+ *   dR_s/dt = sum_{r != s} J^{sr},   dN_s/dt = -(I - N_s N_s) sum_{r != s} K^{sr},
+ *   J^{sr} = a w sin(phi_s - phi_r) (9/64) (lam/ell)^2 (ell/D)^4
+ *            { N_s (2s + 4qr - 10 s r^2)
+ *              + Dhat (1 + 2q^2 - 5s^2 - 5r^2 - 20 q s r + 35 s^2 r^2) },
+ *   K^{sr} = w sin(phi_s - phi_r) (15/64) (a/ell) (lam/ell)^2 (ell/D)^5 Dhat
+ *            (3s + 6rq + 6 s q^2 - 7 s^3 - 21 s r^2 - 42 q s^2 r + 63 s^3 r^2),
+ *   D = R_s - R_r, s = Dhat.N_s, r = Dhat.N_r, q = N_s.N_r, w = 2 pi/T.
+ * Sums in ascending r. The equations are autonomous.
+ * ------------------------------------------------------------------------ */
+int adref_sa_rhs(const adref_params* p, int64_t S, const double* R, const double* N, const double* phi,
+                 double* dR, double* dN) {
+    if (!p || !R || !N || !phi || !dR || !dN || S < 0) return ADREF_EINVAL;
+    double w = 2.0 * PI / p->T;
+    double lr = p->lam / p->ell;
+    double cj = p->a * w * (9.0 / 64.0) * lr * lr;
+    double ck = w * (15.0 / 64.0) * (p->a / p->ell) * lr * lr;
+    int bad = 0;
+    #pragma omp parallel for schedule(static) reduction(+:bad)
+    for (int64_t i = 0; i < S; ++i) {
+        const double* ni = N + 3 * i;
+        double jx = 0.0, jy = 0.0, jz = 0.0, kx = 0.0, ky = 0.0, kz = 0.0;
+        for (int64_t j = 0; j < S; ++j) {
+            if (j == i) continue;
+            const double* nj = N + 3 * j;
+            double Dx = R[3 * i + 0] - R[3 * j + 0];
+            double Dy = R[3 * i + 1] - R[3 * j + 1];
+            double Dz = R[3 * i + 2] - R[3 * j + 2];
+            double D = sqrt((Dx * Dx + Dy * Dy) + Dz * Dz);
+            if (D == 0.0) { bad = 1; continue; }
+            double ux = Dx / D, uy = Dy / D, uz = Dz / D;
+            double s = (ux * ni[0] + uy * ni[1]) + uz * ni[2];
+            double r = (ux * nj[0] + uy * nj[1]) + uz * nj[2];
+            double q = (ni[0] * nj[0] + ni[1] * nj[1]) + ni[2] * nj[2];
+            double sn = sin(phi[i] - phi[j]);
+            double x = p->ell / D;
+            double x4 = (x * x) * (x * x);
+            double aN = 2.0 * s + 4.0 * q * r - 10.0 * s * r * r;
+            double aD = 1.0 + 2.0 * q * q - 5.0 * s * s - 5.0 * r * r - 20.0 * q * s * r + 35.0 * s * s * r * r;
+            double fj = cj * sn * x4;
+            jx = jx + fj * (ni[0] * aN + ux * aD);
+            jy = jy + fj * (ni[1] * aN + uy * aD);
+            jz = jz + fj * (ni[2] * aN + uz * aD);
+            double bK = 3.0 * s + 6.0 * r * q + 6.0 * s * q * q - 7.0 * s * s * s - 21.0 * s * r * r
+                        - 42.0 * q * s * s * r + 63.0 * s * s * s * r * r;
+            double fk = ck * sn * (x4 * x) * bK;
+            kx = kx + fk * ux;
+            ky = ky + fk * uy;
+            kz = kz + fk * uz;
+        }
+        dR[3 * i + 0] = jx;
+        dR[3 * i + 1] = jy;
+        dR[3 * i + 2] = jz;
+        double nk = (ni[0] * kx + ni[1] * ky) + ni[2] * kz;
+        dN[3 * i + 0] = -(kx - ni[0] * nk);
+        dN[3 * i + 1] = -(ky - ni[1] * nk);
+        dN[3 * i + 2] = -(kz - ni[2] * nk);
+    }
+    return bad ? ADREF_ENONFINITE : ADREF_OK;
+}
+
+/* RK4 on (R, N) with time step dt; after each step every axis is scaled back
+ * to unit length (the exact flow keeps |N| = 1, RK4 only to O(dt^5)). */
+int adref_sa_run(const adref_params* p, int64_t S, double* R, double* N, const double* phi, double dt,
+                 int64_t nsteps) {
+    if (!p || !R || !N || !phi || S < 0 || nsteps < 0 || !(dt > 0)) return ADREF_EINVAL;
+    int64_t M = 3 * S;
+    double* buf = (double*)malloc(sizeof(double) * (size_t)(M * 12 + 1));
+    if (!buf) return ADREF_ENOMEM;
+    double *kR[4], *kN[4];
+    for (int s = 0; s < 4; ++s) {
+        kR[s] = buf + (2 * s) * M;
+        kN[s] = buf + (2 * s + 1) * M;
+    }
+    double *YR = buf + 8 * M, *YN = buf + 9 * M;
+    int status = ADREF_OK;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        status |= adref_sa_rhs(p, S, R, N, phi, kR[0], kN[0]);
+        for (int64_t c = 0; c < M; ++c) { YR[c] = R[c] + (0.5 * dt) * kR[0][c]; YN[c] = N[c] + (0.5 * dt) * kN[0][c]; }
+        status |= adref_sa_rhs(p, S, YR, YN, phi, kR[1], kN[1]);
+        for (int64_t c = 0; c < M; ++c) { YR[c] = R[c] + (0.5 * dt) * kR[1][c]; YN[c] = N[c] + (0.5 * dt) * kN[1][c]; }
+        status |= adref_sa_rhs(p, S, YR, YN, phi, kR[2], kN[2]);
+        for (int64_t c = 0; c < M; ++c) { YR[c] = R[c] + dt * kR[2][c]; YN[c] = N[c] + dt * kN[2][c]; }
+        status |= adref_sa_rhs(p, S, YR, YN, phi, kR[3], kN[3]);
+        for (int64_t c = 0; c < M; ++c) {
+            R[c] = R[c] + (dt / 6.0) * (((kR[0][c] + 2.0 * kR[1][c]) + 2.0 * kR[2][c]) + kR[3][c]);
+            N[c] = N[c] + (dt / 6.0) * (((kN[0][c] + 2.0 * kN[1][c]) + 2.0 * kN[2][c]) + kN[3][c]);
+        }
+        for (int64_t i = 0; i < S; ++i) {
+            double* v = N + 3 * i;
+            double nn = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+            v[0] = v[0] / nn;
+            v[1] = v[1] / nn;
+            v[2] = v[2] / nn;
+        }
+    }
+    free(buf);
+    return status ? ADREF_ENONFINITE : ADREF_OK;
+}

@@ -56,6 +56,8 @@ def lib():
         L.adref_energy.restype = C.c_double
         L.adref_rest_length.argtypes = [P, C.c_double, C.c_double]
         L.adref_rest_length.restype = C.c_double
+        L.adref_sa_rhs.argtypes = [P, C.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.adref_sa_run.argtypes = [P, C.c_int64, _dp, _dp, _dp, C.c_double, C.c_int64]
         L.adref_set_threads.argtypes = [C.c_int]
         L.adref_max_threads.restype = C.c_int
         _lib = L
@@ -159,3 +161,21 @@ def run(p, X, phi, nsteps: int, t0: float = 0.0, step0: int = 0, record_every: i
                            _d(cen) if cen is not None else None, _d(com) if com is not None else None)
     _check(code, "adref_run", allow_nonfinite)
     return X, cen, com, code
+
+
+def sa_rhs(p, R, N, phi):
+    """Stroke-averaged far-field velocities (dR/dt, dN/dt) of dumbbells
+    with centres R, unit axes N and phases phi (Sec. III, Eq. e:eom)."""
+    R, N, phi = _arr(R), _arr(N), _arr(phi)
+    dR, dN = np.empty_like(R), np.empty_like(N)
+    _check(lib().adref_sa_rhs(C.byref(_params(p)), R.shape[0], _d(R), _d(N), _d(phi), _d(dR), _d(dN)),
+           "adref_sa_rhs")
+    return dR, dN
+
+
+def sa_run(p, R, N, phi, dt, nsteps):
+    """RK4 of the stroke-averaged equations; returns new (R, N)."""
+    R, N, phi = _arr(R).copy(), _arr(N).copy(), _arr(phi)
+    _check(lib().adref_sa_run(C.byref(_params(p)), R.shape[0], _d(R), _d(N), _d(phi), float(dt), int(nsteps)),
+           "adref_sa_run")
+    return R, N
