@@ -175,6 +175,28 @@ int ad_use_graph(ad_ctx* ctx, int32_t enable);
 int ad_profile_pairs(ad_ctx* ctx, int32_t enable);
 int ad_profile_read(ad_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* ---- Stroke-averaged far-field equations (Sec. III, Eqs. e:eom, J, K) ----
+ * For S dumbbells with centres R, unit axes N and phases phi:
+ *   dR_s/dt = sum_{r != s} J^{sr},  dN_s/dt = -(I - N_s N_s) sum_{r != s} K^{sr},
+ * with J ~ |D|^-4 and K ~ |D|^-5 the stroke-averaged pair terms (uses a, ell,
+ * lambda and T of p; the other fields are ignored). R, N, dR, dN: device
+ * [S][3] f64; phi: device [S] f64. Context-free and asynchronous unless
+ * stated. */
+
+/* dR/dt and dN/dt at (R, N). */
+int ad_sa_rhs(const ad_params* p, int32_t S, const double* R, const double* N, const double* phi,
+              double* dR, double* dN, void* stream);
+
+/* Bytes of device workspace ad_sa_run needs for S dumbbells. */
+int ad_sa_workspace_size(int32_t S, uint64_t* bytes);
+
+/* nsteps RK4 steps of size dt, in place on R and N; every axis is scaled back
+ * to unit length after each step. workspace: device, 256-byte aligned, at
+ * least ad_sa_workspace_size bytes. Synchronises the stream at the end;
+ * returns AD_ENONFINITE if two centres coincided. */
+int ad_sa_run(const ad_params* p, int32_t S, double* R, double* N, const double* phi, double dt,
+              int64_t nsteps, void* workspace, uint64_t ws_bytes, void* stream);
+
 /* Message of the last failure on ctx (never NULL; "" if none). With ctx ==
  * NULL: the last failure of ad_create on the calling thread. */
 const char* ad_last_error(const ad_ctx* ctx);

@@ -26,7 +26,7 @@ INTEGRATORS = {"rk4": AD_RK4, "heun": AD_HEUN}
 EXPORTS = ("ad_create", "ad_destroy", "ad_workspace_size", "ad_bind_workspace", "ad_set_launch",
            "ad_get_launch", "ad_set_state", "ad_get_state", "ad_forces", "ad_mobility_apply",
            "ad_step", "ad_run", "ad_check", "ad_use_graph", "ad_profile_pairs", "ad_profile_read",
-           "ad_last_error")
+           "ad_sa_rhs", "ad_sa_workspace_size", "ad_sa_run", "ad_last_error")
 
 
 class ad_params(C.Structure):
@@ -79,6 +79,9 @@ def lib():
         L.ad_use_graph.argtypes = [vp, i32]
         L.ad_profile_pairs.argtypes = [vp, i32]
         L.ad_profile_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+        L.ad_sa_rhs.argtypes = [C.POINTER(ad_params), i32, vp, vp, vp, vp, vp, vp]
+        L.ad_sa_workspace_size.argtypes = [i32, C.POINTER(C.c_uint64)]
+        L.ad_sa_run.argtypes = [C.POINTER(ad_params), i32, vp, vp, vp, C.c_double, i64, vp, C.c_uint64, vp]
         L.ad_last_error.argtypes = [vp]
         L.ad_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -219,6 +222,36 @@ def ad_profile_read(ctx):
     return float(ms.value), int(n.value)
 
 
+def _sa_check(code: int, what: str) -> None:
+    if code != AD_OK:
+        raise ADError(code, what)
+
+
+def ad_sa_rhs(params: ad_params, R, N, phi, dR_out, dN_out, stream=None) -> None:
+    S = R.shape[0]
+    _sa_check(lib().ad_sa_rhs(C.byref(params), int(S), _dev(R, "R", (S, 3)), _dev(N, "N", (S, 3)),
+                              _dev(phi, "phi", (S,)), _dev(dR_out, "dR", (S, 3)), _dev(dN_out, "dN", (S, 3)),
+                              _stream(stream)), "ad_sa_rhs")
+
+
+def ad_sa_workspace_size(S: int) -> int:
+    n = C.c_uint64()
+    _sa_check(lib().ad_sa_workspace_size(int(S), C.byref(n)), "ad_sa_workspace_size")
+    return int(n.value)
+
+
+def ad_sa_run(params: ad_params, R, N, phi, dt, nsteps, workspace, stream=None) -> int:
+    """Advance (R, N) in place; returns AD_OK or AD_ENONFINITE."""
+    S = R.shape[0]
+    code = lib().ad_sa_run(C.byref(params), int(S), _dev(R, "R", (S, 3)), _dev(N, "N", (S, 3)),
+                           _dev(phi, "phi", (S,)), float(dt), int(nsteps), C.c_void_p(workspace.data_ptr()),
+                           workspace.numel() * workspace.element_size(), _stream(stream))
+    if code == AD_ENONFINITE:
+        return code
+    _sa_check(code, "ad_sa_run")
+    return code
+
+
 def ad_last_error(ctx=None) -> str:
     msg = lib().ad_last_error(ctx)
     return msg.decode() if msg else ""
@@ -348,3 +381,28 @@ class Simulator:
             self.close()
         except Exception:
             pass
+
+
+class StrokeAveraged:
+    """Stroke-averaged far-field dynamics of S dumbbells on one device
+    (Sec. III): device state R, N, phi plus the RK4 workspace."""
+
+    def __init__(self, params, R, N, phi, device="cuda:0"):
+        import torch
+        self.device = torch.device(device)
+        self._p = make_params(params)
+        self.R = torch.as_tensor(R, dtype=torch.float64).to(self.device).contiguous()
+        self.N = torch.as_tensor(N, dtype=torch.float64).to(self.device).contiguous()
+        self.phi = torch.as_tensor(phi, dtype=torch.float64).to(self.device).contiguous()
+        S = self.R.shape[0]
+        nb = ad_sa_workspace_size(S)
+        self.ws = torch.empty((nb + 255) // 256 * 32, dtype=torch.float64, device=self.device)
+
+    def rhs(self):
+        import torch
+        dR, dN = torch.empty_like(self.R), torch.empty_like(self.N)
+        ad_sa_rhs(self._p, self.R, self.N, self.phi, dR, dN)
+        return dR, dN
+
+    def run(self, dt, nsteps):
+        return ad_sa_run(self._p, self.R, self.N, self.phi, dt, nsteps, self.ws)

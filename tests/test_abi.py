@@ -117,3 +117,16 @@ def test_launch_shapes_and_workspace_size():
 
 def test_destroy_null_is_noop():
     assert P.lib().ad_destroy(None) == 0
+
+
+def test_stroke_averaged_entry_points_validate_on_the_host():
+    lib = P.lib()
+    prm = P.make_params(Params())
+    n = C.c_uint64()
+    assert lib.ad_sa_workspace_size(0, C.byref(n)) == B.AD_EINVAL
+    assert lib.ad_sa_workspace_size(125, C.byref(n)) == 0 and n.value >= 6 * 125 * 24
+    fake = C.c_void_p(4096)
+    assert lib.ad_sa_run(C.byref(prm), 125, fake, fake, fake, 1.0, 1, fake, 16, None) == B.AD_ENOMEM
+    assert lib.ad_sa_run(C.byref(prm), 125, fake, fake, fake, -1.0, 1, fake, n.value, None) == B.AD_EINVAL
+    bad = P.make_params(Params(T=0.0))
+    assert lib.ad_sa_rhs(C.byref(bad), 125, fake, fake, fake, fake, fake, None) == B.AD_EINVAL

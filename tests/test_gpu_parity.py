@@ -475,3 +475,62 @@ def test_rpy_trajectory_fp32c(oracle):
     drift = max(relerr(cen.cpu().numpy()[r] - R0, co[r] - R0) for r in range(len(co)))
     say(f"  rpy fp32c drift {drift:.2e}")
     assert drift <= 1e-4
+
+
+# ---------------------------------------------------------------- stroke-averaged equations
+
+def _sa_config(S, spread, seed):
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(-spread, spread, (S, 3))
+    N = rng.standard_normal((S, 3))
+    N /= np.linalg.norm(N, axis=1, keepdims=True)
+    return R, N, rng.uniform(0, 2 * math.pi, S)
+
+
+def _lattice(n, spacing, seed):
+    """n^3 dumbbells on a cubic lattice (Sec. IV.C), random axes and phases."""
+    g = (np.arange(n) - (n - 1) / 2) * spacing
+    R = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(seed)
+    N = rng.standard_normal(R.shape)
+    N /= np.linalg.norm(N, axis=1, keepdims=True)
+    return R, N, rng.uniform(0, 2 * math.pi, len(R))
+
+
+@pytest.mark.parametrize("S", [1, 2, 129, 700])
+def test_sa_rhs_matches_oracle(oracle, S):
+    """Eqs. (e:eom, J, K) on the GPU against the oracle (the phase sine comes
+    from the device's sin, hence a tolerance instead of bit equality)."""
+    torch = _torch()
+    R, N, phi = _sa_config(S, 80.0, S)
+    p = Params()
+    sa = P.StrokeAveraged(p, R, N, phi)
+    dR, dN = (x.cpu().numpy() for x in sa.rhs())
+    oR, oN = oracle.sa_rhs(p, R, N, phi)
+    if S == 1:
+        assert np.abs(dR).max() == 0 and np.abs(dN).max() == 0
+        return
+    assert relerr(dR, oR) <= 1e-13 and relerr(dN, oN) <= 1e-13
+
+
+def test_sa_run_lattice_matches_oracle(oracle):
+    """5^3 dumbbells at spacing 10 ell (the lattice of Sec. IV.C), 400 RK4
+    steps of dt = T/10 of the stroke-averaged equations."""
+    _torch()
+    R, N, phi = _lattice(5, 40.0, 3)
+    p = Params()
+    sa = P.StrokeAveraged(p, R, N, phi)
+    assert sa.run(10.0, 400) == 0
+    Ro, No = oracle.sa_run(p, R, N, phi, 10.0, 400)
+    Rg, Ng = sa.R.cpu().numpy(), sa.N.cpu().numpy()
+    assert relerr(Rg - R, Ro - R) <= 1e-10
+    assert np.abs(Ng - No).max() <= 1e-12
+    np.testing.assert_allclose(np.linalg.norm(Ng, axis=1), 1.0, atol=1e-15)
+
+
+def test_sa_coincident_centres_flagged():
+    _torch()
+    R, N, phi = _sa_config(5, 30.0, 4)
+    R[3] = R[1]
+    sa = P.StrokeAveraged(Params(), R, N, phi)
+    assert sa.run(1.0, 2) == P.binding.AD_ENONFINITE
