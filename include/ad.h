@@ -62,7 +62,11 @@ extern "C" {
 
 /* time integrator (ad_params.integrator) */
 #define AD_RK4 0
-#define AD_HEUN 1 /* Sec. V: x~ = x + dt u(x,t); x' = x + dt/2 (u(x,t) + u(x~,t+dt)) */
+#define AD_HEUN 1 /* Sec. V: x~ = x + dt u(x,t); x' = x + dt/2 (u(x,t) + u(x~,t+dt)).
+                     With kT > 0 both stages add g xi, g = sqrt(2 kT dt/(6 pi eta a)):
+                     the additive noise with constant C of Sec. V (Eq. e:cholesky on the
+                     diagonal of H). xi: three standard normals per sphere and step, from
+                     Philox4x32-10 (key = seed, counter = (sphere, step)) and Box-Muller. */
 
 /* pair tensor (ad_params.tensor) */
 #define AD_OSEEN 0 /* (I + rr/r^2)/(8 pi eta r), Sec. II, Eq. e:Mazur first line */
@@ -84,6 +88,8 @@ typedef struct ad_params {
     int32_t integrator; /* AD_RK4 | AD_HEUN */
     int32_t tensor;     /* AD_OSEEN | AD_RPY */
     int32_t reserved;   /* must be 0 */
+    double kT;          /* thermal energy k_B T >= 0; > 0 needs AD_HEUN (additive noise, below) */
+    uint64_t seed;      /* key of the noise generator */
 } ad_params;
 
 /* Launch shape of the pair kernel. Zero fields mean "library default for

@@ -24,6 +24,14 @@
  *   - Time stepping: classical RK4 (default) or the paper's Heun
  *     predictor-corrector (Sec. V), x~ = x + dt u(x,t),
  *     x' = x + dt/2 (u(x,t) + u(x~,t+dt)).
+ *   - Optional Brownian noise with Heun: the additive form with a constant
+ *     matrix C the paper recommends for dilute suspensions (Sec. V). With H
+ *     replaced by its diagonal, 2H = C C^T (Eq. e:cholesky) gives
+ *     C = sqrt(2/(6 pi eta a)) I, so both Heun stages add
+ *     sqrt(2 kT dt/(6 pi eta a)) xi with the same standard normal xi.
+ *     xi comes from the counter-based generator Philox4x32-10 (Salmon,
+ *     Moraes, Dror, Shaw, SC'11), key = seed, counter = (sphere, step), and
+ *     the Box-Muller transform.
  *
  * Readings where the paper leaves freedom (each is fixed here on purpose):
  *   - sin(omega t + phi) is evaluated by the addition theorem,
@@ -55,6 +63,8 @@ typedef struct adref_params {
     double steric_k, steric_r;
     int32_t integrator; /* 0 = RK4, 1 = Heun */
     int32_t tensor;     /* 0 = Oseen, 1 = Oseen + RPY-Mazur correction */
+    double kT;          /* thermal energy k_B T (0: deterministic; Heun only) */
+    uint64_t seed;      /* key of the noise generator */
 } adref_params;
 
 static const double PI = 3.14159265358979323846;
@@ -74,6 +84,50 @@ int adref_max_threads(void) {
     return 1;
 #endif
 }
+
+/* Philox4x32-10: ten rounds of two 32x32->64 multiplications with the
+ * published multipliers, the key bumped by the Weyl constants between
+ * rounds. */
+static void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void adref_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    philox4x32_10(ctr, key, out);
+}
+
+/* Three standard normals for sphere i at step n: Box-Muller on the four
+ * uniforms (x + 1/2) 2^-32 of one Philox block. */
+static void gauss3(uint64_t seed, int64_t i, int64_t n, double z[3]) {
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)n, (uint32_t)((uint64_t)n >> 32), 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    philox4x32_10(ctr, key, x);
+    double u[4];
+    for (int q = 0; q < 4; ++q) u[q] = ((double)x[q] + 0.5) / 4294967296.0;
+    double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    z[0] = r0 * cos((2.0 * PI) * u[1]);
+    z[1] = r0 * sin((2.0 * PI) * u[1]);
+    z[2] = r1 * cos((2.0 * PI) * u[3]);
+}
+
+void adref_gauss3(uint64_t seed, int64_t i, int64_t n, double z[3]) { gauss3(seed, i, n, z); }
 
 /* Rest length L(t) of dumbbell s (Eq. e:swimmer_potential). */
 static double rest_length(const adref_params* p, double t, double phi) {
@@ -286,12 +340,14 @@ static int all_finite(const double* v, int64_t n) {
 static int advance_system(const adref_params* p, int64_t N, double* X, const double* phi, double t0,
                           int64_t step0, int64_t nsteps, int64_t record_every,
                           double* centres, int64_t centre_stride, double* com, int64_t com_stride,
-                          int threaded) {
+                          int threaded, int64_t ioff) {
     int64_t M = 3 * N;
     double* buf = (double*)malloc(sizeof(double) * (size_t)(M * 7 + 1));
     if (!buf) return ADREF_ENOMEM;
     double *F = buf, *k1 = buf + M, *k2 = buf + 2 * M, *k3 = buf + 3 * M, *k4 = buf + 4 * M;
     double* Y = buf + 5 * M;
+    double* xi = buf + 6 * M;
+    const double g = sqrt(2.0 * p->kT * (1.0 / (6.0 * PI * p->eta * p->a)) * p->dt);
     int status = ADREF_OK;
     double dt = p->dt;
     int64_t rec = 0;
@@ -300,11 +356,19 @@ static int advance_system(const adref_params* p, int64_t N, double* X, const dou
         double tn = t0 + (double)step * dt;
         int st = 0;
         if (p->integrator == 1) {
-            /* Heun predictor-corrector */
+            /* Heun predictor-corrector, with the same noise in both stages */
+            if (p->kT > 0.0)
+                for (int64_t i = 0; i < N; ++i) gauss3(p->seed, ioff + i, step, xi + 3 * i);
             st |= velocity(p, N, X, phi, tn, F, k1, threaded);
-            for (int64_t c = 0; c < M; ++c) Y[c] = X[c] + dt * k1[c];
+            if (p->kT > 0.0)
+                for (int64_t c = 0; c < M; ++c) Y[c] = (X[c] + dt * k1[c]) + g * xi[c];
+            else
+                for (int64_t c = 0; c < M; ++c) Y[c] = X[c] + dt * k1[c];
             st |= velocity(p, N, Y, phi, tn + dt, F, k2, threaded);
-            for (int64_t c = 0; c < M; ++c) X[c] = X[c] + (0.5 * dt) * (k1[c] + k2[c]);
+            if (p->kT > 0.0)
+                for (int64_t c = 0; c < M; ++c) X[c] = (X[c] + (0.5 * dt) * (k1[c] + k2[c])) + g * xi[c];
+            else
+                for (int64_t c = 0; c < M; ++c) X[c] = X[c] + (0.5 * dt) * (k1[c] + k2[c]);
         } else {
             double th = tn + 0.5 * dt, te = tn + dt;
             st |= velocity(p, N, X, phi, tn, F, k1, threaded);
@@ -349,20 +413,21 @@ int adref_run(const adref_params* p, int32_t nsys, const int64_t* off, double* X
               double t0, int64_t step0, int64_t nsteps, int64_t record_every,
               double* centres_out, double* com_out) {
     if (!p || !off || !X || !phi || nsys <= 0 || nsteps < 0 || record_every < 0) return ADREF_EINVAL;
+    if (p->kT < 0.0 || (p->kT > 0.0 && p->integrator != 1)) return ADREF_EINVAL;
     for (int32_t b = 0; b < nsys; ++b)
         if (off[b + 1] < off[b] || ((off[b + 1] - off[b]) & 1) || (off[b] & 1)) return ADREF_EINVAL;
     int64_t S_total = off[nsys] / 2;
     int status = ADREF_OK;
     if (nsys == 1) {
         return advance_system(p, off[1] - off[0], X + 3 * off[0], phi + off[0] / 2, t0, step0, nsteps,
-                              record_every, centres_out, 3 * S_total, com_out, 3, 1);
+                              record_every, centres_out, 3 * S_total, com_out, 3, 1, off[0]);
     }
     #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t b = 0; b < nsys; ++b) {
         int64_t N = off[b + 1] - off[b];
         int st = advance_system(p, N, X + 3 * off[b], phi + off[b] / 2, t0, step0, nsteps, record_every,
                                 centres_out ? centres_out + 3 * (off[b] / 2) : NULL, 3 * S_total,
-                                com_out ? com_out + 3 * b : NULL, 3 * (int64_t)nsys, 0);
+                                com_out ? com_out + 3 * b : NULL, 3 * (int64_t)nsys, 0, off[b]);
         if (st != ADREF_OK) {
             #pragma omp critical
             status = st;

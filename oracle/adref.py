@@ -31,7 +31,8 @@ class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("eta", C.c_double), ("k", C.c_double), ("ell", C.c_double),
                 ("lam", C.c_double), ("T", C.c_double), ("dt", C.c_double),
                 ("steric_k", C.c_double), ("steric_r", C.c_double),
-                ("integrator", C.c_int32), ("tensor", C.c_int32)]
+                ("integrator", C.c_int32), ("tensor", C.c_int32),
+                ("kT", C.c_double), ("seed", C.c_uint64)]
 
 
 _lib = None
@@ -58,15 +59,17 @@ def lib():
         L.adref_rest_length.restype = C.c_double
         L.adref_sa_rhs.argtypes = [P, C.c_int64, _dp, _dp, _dp, _dp, _dp]
         L.adref_sa_run.argtypes = [P, C.c_int64, _dp, _dp, _dp, C.c_double, C.c_int64]
+        L.adref_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        L.adref_gauss3.argtypes = [C.c_uint64, C.c_int64, C.c_int64, _dp]
         L.adref_set_threads.argtypes = [C.c_int]
         L.adref_max_threads.restype = C.c_int
         _lib = L
     return _lib
 
 
-def _params(p, integrator: int = 0, tensor: int = 0) -> _Params:
+def _params(p, integrator: int = 0, tensor: int = 0, kT: float = 0.0, seed: int = 0) -> _Params:
     return _Params(p.a, p.eta, p.k, p.ell, p.lam, p.T, p.dt, p.steric_k, p.steric_r,
-                   integrator, tensor)
+                   integrator, tensor, float(kT), int(seed))
 
 
 def _d(a: np.ndarray):
@@ -142,7 +145,8 @@ def rest_length(p, t: float, phi: float) -> float:
 
 
 def run(p, X, phi, nsteps: int, t0: float = 0.0, step0: int = 0, record_every: int = 0,
-        S_per_sys=None, integrator: int = 0, tensor: int = 0, allow_nonfinite: bool = False):
+        S_per_sys=None, integrator: int = 0, tensor: int = 0, allow_nonfinite: bool = False,
+        kT: float = 0.0, seed: int = 0):
     """Advance a copy of X by nsteps. Returns (X_new, centres[nrec,S,3], com[nrec,nsys,3], status)."""
     X = _arr(X).copy()
     phi = _arr(phi)
@@ -156,7 +160,7 @@ def run(p, X, phi, nsteps: int, t0: float = 0.0, step0: int = 0, record_every: i
     nrec = nsteps // record_every if record_every > 0 else 0
     cen = np.zeros((nrec, N // 2, 3)) if nrec else None
     com = np.zeros((nrec, nsys, 3)) if nrec else None
-    code = lib().adref_run(C.byref(_params(p, integrator, tensor)), nsys, off.ctypes.data_as(_ip),
+    code = lib().adref_run(C.byref(_params(p, integrator, tensor, kT, seed)), nsys, off.ctypes.data_as(_ip),
                            _d(X), _d(phi), float(t0), int(step0), int(nsteps), int(record_every),
                            _d(cen) if cen is not None else None, _d(com) if com is not None else None)
     _check(code, "adref_run", allow_nonfinite)
@@ -179,3 +183,18 @@ def sa_run(p, R, N, phi, dt, nsteps):
     _check(lib().adref_sa_run(C.byref(_params(p)), R.shape[0], _d(R), _d(N), _d(phi), float(dt), int(nsteps)),
            "adref_sa_run")
     return R, N
+
+
+def philox(ctr, key):
+    """Philox4x32-10 block for a 4-word counter and a 2-word key."""
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().adref_philox(c, k, o)
+    return [int(v) for v in o]
+
+
+def gauss3(seed, i, n):
+    z = np.empty(3)
+    lib().adref_gauss3(int(seed), int(i), int(n), _d(z))
+    return z

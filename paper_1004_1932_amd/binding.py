@@ -34,7 +34,7 @@ class ad_params(C.Structure):
                 ("lambda_", C.c_double), ("T", C.c_double), ("dt", C.c_double),
                 ("steric_k", C.c_double), ("steric_r", C.c_double),
                 ("precision", C.c_int32), ("integrator", C.c_int32), ("tensor", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("kT", C.c_double), ("seed", C.c_uint64)]
 
 
 class ad_launch(C.Structure):
@@ -116,7 +116,7 @@ def _dev(t, name, shape=None):
     return C.c_void_p(t.data_ptr())
 
 
-def make_params(p, precision="fp32c", integrator="rk4", tensor="oseen") -> ad_params:
+def make_params(p, precision="fp32c", integrator="rk4", tensor="oseen", kT=0.0, seed=0) -> ad_params:
     """ad_params from any object with a, eta, k, ell, lam, T, dt (steric_k,
     steric_r optional)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -125,7 +125,7 @@ def make_params(p, precision="fp32c", integrator="rk4", tensor="oseen") -> ad_pa
     lam = getattr(p, "lam", getattr(p, "lambda_", None))
     return ad_params(float(p.a), float(p.eta), float(p.k), float(p.ell), float(lam), float(p.T),
                      float(p.dt), float(getattr(p, "steric_k", 0.0)), float(getattr(p, "steric_r", 0.0)),
-                     prec, integ, ten, 0)
+                     prec, integ, ten, 0, float(kT), int(seed))
 
 
 # ---------------------------------------------------------------- 1:1 entry points
@@ -278,7 +278,7 @@ class Simulator:
     """A context plus its workspace tensor on one device."""
 
     def __init__(self, params, S_per_sys, precision="fp32c", integrator="rk4", device="cuda:0",
-                 launch=None, graph=False, tensor="oseen"):
+                 launch=None, graph=False, tensor="oseen", kT=0.0, seed=0):
         """launch: None (library default), a dict of ad_launch fields, or
         "tuned" (the autotuned shape for this size bucket, if any)."""
         import torch
@@ -287,7 +287,7 @@ class Simulator:
         self.nsys = int(self.S_per_sys.shape[0])
         self.Stot = int(self.S_per_sys.sum())
         self.N = 2 * self.Stot
-        self._p = make_params(params, precision, integrator, tensor)
+        self._p = make_params(params, precision, integrator, tensor, kT, seed)
         self._graph = bool(graph)
         if launch == "tuned":
             from .autotune import tuned_launch

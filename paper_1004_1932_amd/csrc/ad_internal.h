@@ -51,6 +51,9 @@ struct Coef {
     double cr;   /* 2 a^2/(24 pi eta): Rotne-Prager-Yamakawa-Mazur coefficient */
     float crr;   /* cr / co = 2 a^2 / 3, for the FP32 pair sum */
     int rpy;     /* 1: Oseen plus the RPY-Mazur correction; 0: Oseen */
+    int noise;   /* 1: Heun with additive noise */
+    double g;    /* noise amplitude sqrt(2 kT dt/(6 pi eta a)) */
+    unsigned long long seed; /* noise key */
 };
 
 /* Device views into the workspace. */

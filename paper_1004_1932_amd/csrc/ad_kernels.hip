@@ -122,6 +122,39 @@ __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float v) {
 }
 
 
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+ * 32x32->64 multiplications by the published multipliers, the key bumped by
+ * the Weyl constants between rounds. */
+__device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsigned k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const unsigned hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const unsigned hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+/* Standard normal component a (0..2) of sphere i at step n: Box-Muller on
+ * the four uniforms (x + 1/2) 2^-32 of one Philox block with counter
+ * (i, n) and key seed. */
+__device__ double gauss_component(unsigned long long seed, int i, long long n, int a) {
+    unsigned c[4] = {(unsigned)i, (unsigned)n, (unsigned)((unsigned long long)n >> 32), 0u};
+    philox4x32_10(c, (unsigned)seed, (unsigned)(seed >> 32));
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    const int pr = (a == 2) ? 2 : 0;
+    const double u0 = ((double)c[pr] + 0.5) / 4294967296.0;
+    const double u1 = ((double)c[pr + 1] + 0.5) / 4294967296.0;
+    const double rr = sqrt(-2.0 * log(u0));
+    return (a == 1) ? rr * sin(two_pi * u1) : rr * cos(two_pi * u1);
+}
+
 /* Write the pair-kernel pack and the self (+partner) velocity u0 of the two
  * spheres of one dumbbell at positions y0, y1 with forces f0, f1; into the
  * next-stage pack buffers when nxt != 0. */
@@ -380,14 +413,16 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
                 y = x + c.dt6 * (r + k);
                 d.X[o] = y;
             }
-        } else { /* Heun */
+        } else { /* Heun, with the same noise in both stages */
+            const double nz = c.noise ? c.g * gauss_component(c.seed, i, step, a) : 0.0;
             if (stage == 0) {
                 d.R[o] = k;
                 y = x + c.dt * k;
             } else {
                 y = x + c.h2 * (r + k);
-                d.X[o] = y;
             }
+            if (c.noise) y = y + nz;
+            if (stage == 1) d.X[o] = y;
         }
         ys[sl][a] = y;
         const double dd = y - yold;

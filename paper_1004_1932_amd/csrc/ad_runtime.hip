@@ -518,7 +518,7 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
     if (!p || !S_per_sys || !out) return fail(nullptr, AD_EINVAL, "null argument");
     *out = nullptr;
     if (nsys <= 0) return fail(nullptr, AD_EINVAL, "nsys must be >= 1");
-    const double vals[] = {p->a, p->eta, p->k, p->ell, p->lambda, p->T, p->dt, p->steric_k, p->steric_r};
+    const double vals[] = {p->a, p->eta, p->k, p->ell, p->lambda, p->T, p->dt, p->steric_k, p->steric_r, p->kT};
     for (double v : vals)
         if (!isfinite(v)) return fail(nullptr, AD_EINVAL, "parameters must be finite");
     if (!(p->a > 0) || !(p->eta > 0) || !(p->T > 0) || !(p->dt > 0))
@@ -530,6 +530,8 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
         return fail(nullptr, AD_EINVAL, "unknown integrator %d", p->integrator);
     if (p->tensor != AD_OSEEN && p->tensor != AD_RPY) return fail(nullptr, AD_EINVAL, "unknown tensor %d", p->tensor);
     if (p->reserved != 0) return fail(nullptr, AD_EINVAL, "reserved must be 0");
+    if (p->kT < 0.0) return fail(nullptr, AD_EINVAL, "kT must be >= 0");
+    if (p->kT > 0.0 && p->integrator != AD_HEUN) return fail(nullptr, AD_EINVAL, "noise (kT > 0) needs AD_HEUN");
     long long Stot = 0;
     for (int b = 0; b < nsys; ++b) {
         if (S_per_sys[b] < 1) return fail(nullptr, AD_EINVAL, "S_per_sys[%d] must be >= 1", b);
@@ -562,6 +564,9 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
     k.cr = 2.0 * p->a * p->a / (24.0 * kPi * p->eta);
     k.crr = (float)(2.0 * p->a * p->a / 3.0);
     k.rpy = p->tensor == AD_RPY ? 1 : 0;
+    k.noise = p->kT > 0.0 ? 1 : 0;
+    k.g = sqrt(2.0 * p->kT * (1.0 / (6.0 * kPi * p->eta * p->a)) * p->dt);
+    k.seed = p->seed;
     c->omega = 2.0 * kPi / p->T;
     c->launch = default_launch(c);
     build_items(c);

@@ -34,8 +34,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    # 9 doubles + 4 int32 / 4 int32
-    assert C.sizeof(B.ad_params) == 9 * 8 + 4 * 4
+    # 9 doubles, 4 int32, kT, seed
+    assert C.sizeof(B.ad_params) == 9 * 8 + 4 * 4 + 8 + 8
     assert C.sizeof(B.ad_launch) == 24
 
 
@@ -67,6 +67,11 @@ def test_create_rejects_bad_sizes_and_enums():
     with pytest.raises(P.ADError):
         P.ad_create(bad, [4])
     P.ad_destroy(P.ad_create(P.make_params(Params(), tensor="rpy"), [4]))
+    with pytest.raises(P.ADError):  # noise needs Heun
+        P.ad_create(P.make_params(Params(), integrator="rk4", kT=0.1), [4])
+    with pytest.raises(P.ADError):
+        P.ad_create(P.make_params(Params(), integrator="heun", kT=-1.0), [4])
+    P.ad_destroy(P.ad_create(P.make_params(Params(), integrator="heun", kT=0.1, seed=3), [4]))
 
 
 def test_calls_before_workspace_fail_cleanly():

@@ -534,3 +534,46 @@ def test_sa_coincident_centres_flagged():
     R[3] = R[1]
     sa = P.StrokeAveraged(Params(), R, N, phi)
     assert sa.run(1.0, 2) == P.binding.AD_ENONFINITE
+
+
+# ---------------------------------------------------------------- Brownian noise (Heun)
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32c", 1e-7)])
+def test_heun_noise_matches_oracle(oracle, precision, tol):
+    """Additive noise with constant C (Sec. V), Philox4x32-10 + Box-Muller on
+    both sides: the same random numbers, so the GPU follows the oracle's
+    Brownian trajectory (normals agree to the last bits of log/sin/cos)."""
+    _torch()
+    sizes = np.array([8, 3, 20], dtype=np.int32)
+    ens = make_ensemble(nsys=3, sizes=sizes)
+    kT, seed = 0.01, 77
+    s = P.Simulator(ens.params, sizes, precision=precision, integrator="heun", kT=kT, seed=seed, graph=True)
+    s.set_state(ens.X, ens.phi)
+    cen, com, code = s.run(300, 100)
+    assert code == 0
+    Xg = s.get_state()[0].cpu().numpy()
+    Xo, co, mo, _ = oracle.run(ens.params, ens.X, ens.phi, 300, record_every=100, S_per_sys=sizes,
+                               integrator=1, kT=kT, seed=seed)
+    Xd, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 300, S_per_sys=sizes, integrator=1)
+    assert np.abs(Xo - Xd).max() > 1e-3  # the noise matters
+    err = np.abs(Xg - Xo).max()
+    say(f"  noise {precision} max position error {err:.2e}")
+    assert err <= tol
+
+
+def test_heun_noise_deterministic_and_resumable():
+    _torch()
+    sus = make_single(50, 40.0, 5)
+    kw = dict(precision="fp32c", integrator="heun", kT=0.02, seed=5, graph=True)
+    s = P.Simulator(sus.params, [sus.S], **kw)
+    s.set_state(sus.X, sus.phi)
+    s.step(120)
+    a = s.get_state()[0].cpu().numpy()
+    s2 = P.Simulator(sus.params, [sus.S], **kw)
+    s2.set_state(sus.X, sus.phi)
+    s2.step(60)
+    Xh, t0, st = s2.get_state()
+    s3 = P.Simulator(sus.params, [sus.S], **kw)
+    s3.set_state(Xh, sus.phi, t0, st)
+    s3.step(60)
+    assert np.array_equal(s3.get_state()[0].cpu().numpy(), a)
