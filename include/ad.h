@@ -101,14 +101,11 @@ typedef struct ad_launch {
     int32_t wg;       /* work-group size: 64 or 256 */
     int32_t wj;       /* waves splitting each j-tile: 1, or 4 with wg = 256 (AD_FP32C) */
     int32_t posmode;  /* AD_FP32C positions: 1 = hi/lo float pair, 2 = single float */
-    int32_t fuse;     /* 1 = epilogue as its own kernel; 2 = epilogue in the pair kernel's
-                         last work-group per target block (AD_FP32C) */
+    int32_t reserved; /* must be 0 */
 } ad_launch;
 
 #define AD_POS_HILO 1
 #define AD_POS_SINGLE 2
-#define AD_FUSE_OFF 1
-#define AD_FUSE_ON 2
 
 typedef struct ad_ctx ad_ctx;
 

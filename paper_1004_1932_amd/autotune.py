@@ -58,7 +58,6 @@ def candidates(N: int, ensemble: bool):
                 jc *= 2
         for ipl in (1, 2):
             out.append(dict(wg=256, wj=1, ipl=ipl, jchunk=256, posmode=posmode))
-    out = out + [dict(c, fuse=B.AD_FUSE_ON) for c in out]
     uniq = []
     for c in out:
         if c not in uniq:

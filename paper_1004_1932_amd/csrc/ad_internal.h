@@ -64,7 +64,6 @@ struct Dev {
     double* U0;         /* [3][Ntot] self (+partner) velocity of the stage */
     double* Y;          /* [3][Ntot] stage positions (steric path only) */
     double* Fs;         /* [3][Ntot] stage forces (steric path only) */
-    int* blk_cnt;       /* [Ntot] finished j-chunks of the target block starting at i */
     int* nbr_cnt;       /* [Ntot] candidate count (FP32C steric path) */
     int* nbr_idx;       /* [Ntot][NBR_CAP] candidate source spheres */
     float list_r2;      /* (rc + skin)^2: pairs closer than this are listed */
@@ -112,7 +111,6 @@ struct Shape {
     int wg, wj, ipl, split;
     int rpy;    /* pair tensor with the RPY-Mazur correction */
     int steric; /* FP32C: record steric candidates while summing */
-    int fuse;   /* FP32C: epilogue in the pair kernel's last work-group per block */
 };
 
 /* kernel launchers (ad_kernels.hip) */
@@ -129,8 +127,8 @@ hipError_t launch_pack_apply(const Dev& d, const Coef& c, int prec, const double
 /* forces at caller positions (row-major) and time (st, ct), spring + steric */
 hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xaos, double st, double ct,
                          double* Faos, hipStream_t s);
-/* pair sum; mode 0 = mobility apply, 1 = step stage, 2 = step stage with the
- * epilogue fused (FP32C). With events, they time the dispatch itself. */
+/* pair sum; mode 0 = mobility apply, 1 = step stage. With events, they time
+ * the dispatch itself. */
 hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s,
                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_epilogue(const Dev& d, const Epi& e, hipStream_t s);

@@ -3,19 +3,16 @@
  * active spring dumbbell suspensions (Putz, Dunkel, Yeomans, Sec. II and
  * Sec. V).
  *
- * One RK4 stage is one or two launches:
+ * One RK4 stage is two launches:
  *   k_pairs_*   the O(N^2) pair sum over a work list of (i-block, j-chunk)
  *               items; each item stages its j-tiles through LDS and every
  *               lane holds IPL consecutive target spheres in registers.
- *   epilogue    for each target block: sums the j-chunk partials in chunk
- *               order, forms the stage velocity k = u0 + kappa*acc, updates
- *               the RK accumulator and the state, and evaluates the spring
- *               forces of the next stage (Eq. e:swimmer_potential) into the
- *               pack the next pair sum reads. It runs either as its own
- *               kernel (k_epilogue) or, fused, in the last work-group of the
- *               pair kernel to finish each target block.
- * Packs are double-buffered: stage s reads one and writes the other, so a
- * fused epilogue never overwrites sources another work-group still reads.
+ *   k_epilogue  sums the j-chunk partials in chunk order, forms the stage
+ *               velocity k = u0 + kappa*acc, updates the RK accumulator and
+ *               the state, and evaluates the spring forces of the next stage
+ *               (Eq. e:swimmer_potential) into the pack the next pair sum
+ *               reads.
+ * Packs are double-buffered: stage s reads one and writes the other.
  *
  * All FP64 arithmetic is written in a fixed order and built without FMA
  * contraction; FP32 FMAs are spelled out with __builtin_fmaf.
@@ -226,12 +223,11 @@ __global__ void k_state_out(Dev d, double* __restrict__ Xa) {
     for (int a = 0; a < 3; ++a) Xa[3 * i + a] = d.X[a * d.Ntot + i];
 }
 
-/* empty every steric candidate list and every block counter */
+/* empty every steric candidate list */
 __global__ void k_clear_counts(Dev d) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.Ntot) return;
-    if (d.nbr_cnt) d.nbr_cnt[i] = 0;
-    d.blk_cnt[i] = 0;
+    if (i >= d.Ntot || !d.nbr_cnt) return;
+    d.nbr_cnt[i] = 0;
 }
 
 /* pack from the state at time (st, ct); spring (+ steric) forces */
@@ -333,8 +329,8 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
 
 /* ------------------------------------------------------------ epilogue */
 
-/* Epilogue of one target block [i0, i0 + ni) (ni even), run by all
- * blockDim.x threads of a work-group.
+/* Epilogue of the spheres [i0, i0 + ni) (ni even), run by all blockDim.x
+ * threads of a work-group.
  * Phase 1, one thread per sphere component: issue the loads of that
  * component's j-chunk partials, u0, X and R together, sum the partials in
  * chunk order, form k = u0 + kappa*acc and apply the (componentwise) RK
@@ -541,29 +537,11 @@ __device__ __forceinline__ void advance_slots(const Dev& d, const Epi& e) {
     if (e.stage == e.nst - 1) d.ctl->slot[0] = d.ctl->slot[1] + 1;
 }
 
-/* End of a pair kernel with the fused epilogue: the work-group that
- * completes a target block (the last of its P j-chunks) runs the epilogue
- * of that block. Returns true in that work-group. */
-__device__ __forceinline__ bool last_of_block(const Dev& d, const Item& it, int* s_last) {
-    __threadfence(); /* this group's partial sums are visible device-wide */
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int old = atomicAdd(&d.blk_cnt[it.i0], 1);
-        *s_last = (old == d.sys_P[it.sys] - 1);
-        if (*s_last) d.blk_cnt[it.i0] = 0; /* ready for the next launch */
-    }
-    __syncthreads();
-    if (!*s_last) return false;
-    __threadfence(); /* and the other groups' are visible here */
-    return true;
-}
-
 /* FP32C pair sum. A work-group of WG threads is WI x WJ waves: WI waves own
  * different target spheres (IPL consecutive spheres per lane), and the WJ
  * waves that share the same targets take interleaved parts of every j-tile.
  * A tile of WG source spheres is staged through LDS once and read as
- * broadcasts; tiles are software pipelined (the next one is loaded into
- * registers while the current one is summed).
+ * broadcasts.
  *   SPLIT = 1: positions are hi + lo floats, r = (hi_i - hi_j) + (lo_i - lo_j)
  *              (r rounded relative to itself).
  *   SPLIT = 0: positions are single floats, r = x_i - x_j (error ~ eps |x|).
@@ -578,16 +556,15 @@ __device__ __forceinline__ bool last_of_block(const Dev& d, const Item& it, int*
  *   RPY = 1: the pair tensor carries the Rotne-Prager-Yamakawa-Mazur
  *              correction, summed with the Oseen part as
  *              F (ir + c' ir^3) + r t (ir - 3 c' ir^3), c' = 2a^2/3.
- * mode: 0 = mobility apply, 1 = step stage, 2 = step stage with the fused
- * epilogue. */
+ * mode: 0 = mobility apply, 1 = step stage. */
 template <int WG, int IPL, int WJ, int SPLIT, int STERIC, int RPY>
 __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
     constexpr int WI = WG / 64 / WJ;
     constexpr int TJ = WG;          /* j per LDS tile */
     constexpr int JW = TJ / WJ;     /* j per wave per tile */
     constexpr int IB = 64 * WI * IPL;
-    /* one LDS area, used in turn by the source tiles, the cross-wave
-     * combination and the fused epilogue (barriers separate the uses) */
+    /* one LDS area, used in turn by the source tiles and the cross-wave
+     * combination (a barrier separates the uses) */
     union Lds {
         struct {
             float4 A[TJ];
@@ -595,18 +572,11 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
             float C[TJ];
         } tile;
         float red[WJ > 1 ? WJ : 1][IB][6];
-        struct {
-            double ys[IB][3];
-            double mv[IB][3];
-        } epi;
     };
     __shared__ Lds lds;
     float4* sA = lds.tile.A;
     float4* sB = lds.tile.B;
     float* sC = lds.tile.C;
-    double(*ys)[3] = lds.epi.ys;
-    double(*mv)[3] = lds.epi.mv;
-    __shared__ int s_last, s_bad;
     const Item it = d.items[blockIdx.x];
     if (mode) advance_slots(d, e);
     const int t = threadIdx.x;
@@ -643,17 +613,16 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
     const int jend = it.j0 + it.nj;
     const float crr = e.c.crr;
 
-    float4 A, B;
-    float C;
-    load_tile_entry(d, it.j0, jend, t, A, B, C);
     for (int t0 = it.j0; t0 < jend; t0 += TJ) {
         const int n = min(TJ, jend - t0);
+        float4 A, B;
+        float C;
+        load_tile_entry(d, t0, jend, t, A, B, C);
         __syncthreads();
         sA[t] = A;
         sB[t] = B;
         sC[t] = C;
         __syncthreads();
-        if (t0 + TJ < jend) load_tile_entry(d, t0 + TJ, jend, t, A, B, C);
         const bool diag = (t0 < dhi) && (t0 + n > dlo);
         const int jb = wj * JW;                     /* this wave's part of the tile */
         const int nw = max(0, min(JW, n - jb));
@@ -755,8 +724,6 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
             }
         }
     }
-    if (mode == 2 && last_of_block(d, it, &s_last))
-        epi_block(d, e, it.i0, it.ni, d.ctl->slot[e.stage & 1], ys, mv, &s_bad);
 }
 
 /* FP64: the sum in ascending j with the plain operation order
@@ -1069,10 +1036,9 @@ hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, h
         if (sh.wg == 256 && sh.wj == 4) return f32c_ten<256, 4>(d, e, sh, mode, s, tm);
         return hipErrorInvalidValue;
     }
-    /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group and
-     * no fused epilogue; the work list was built for this shape, so anything
-     * else is refused */
-    if (sh.wj != 1 || mode == 2) return hipErrorInvalidValue;
+    /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group; the
+     * work list was built for this shape, so anything else is refused */
+    if (sh.wj != 1) return hipErrorInvalidValue;
     if (sh.wg == 64 && sh.ipl == 1) return f64_ten<64, 1>(d, e, sh, mode, s, tm);
     if (sh.wg == 64 && sh.ipl == 2) return f64_ten<64, 2>(d, e, sh, mode, s, tm);
     if (sh.wg == 256 && sh.ipl == 1) return f64_ten<256, 1>(d, e, sh, mode, s, tm);

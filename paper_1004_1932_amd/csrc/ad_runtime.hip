@@ -110,7 +110,6 @@ static ad_launch default_launch(const ad_ctx* c) {
     for (int b = 0; b < c->nsys; ++b) maxN = std::max(maxN, 2 * c->S[b]);
     L.wj = 1;
     L.posmode = c->p.precision == AD_FP32C ? AD_POS_HILO : 0;
-    L.fuse = AD_FUSE_OFF;
     if (c->p.precision == AD_FP64) {
         L.ipl = 1;
         L.wg = 64;
@@ -145,8 +144,7 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (c->p.precision == AD_FP32C && L.posmode != AD_POS_HILO && L.posmode != AD_POS_SINGLE)
         return fail(c, AD_EINVAL, "launch.posmode must be AD_POS_HILO or AD_POS_SINGLE");
     if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
-    if (L.fuse != AD_FUSE_OFF && !(L.fuse == AD_FUSE_ON && c->p.precision == AD_FP32C))
-        return fail(c, AD_EINVAL, "launch.fuse must be AD_FUSE_OFF, or AD_FUSE_ON in AD_FP32C");
+    if (L.reserved != 0) return fail(c, AD_EINVAL, "launch.reserved must be 0");
     return AD_OK;
 }
 
@@ -161,7 +159,6 @@ static ad::Shape shape_of(const ad_ctx* c) {
     sh.split = c->launch.posmode == AD_POS_HILO ? 1 : 0;
     sh.steric = uses_lists(c) ? 1 : 0;
     sh.rpy = c->p.tensor == AD_RPY ? 1 : 0;
-    sh.fuse = c->launch.fuse == AD_FUSE_ON ? 1 : 0;
     return sh;
 }
 
@@ -211,7 +208,7 @@ static void build_items(ad_ctx* c) {
 /* ------------------------------------------------------------ workspace */
 
 struct Layout {
-    size_t ctl, X, R, U0, Y, Fs, blk_cnt, nbr_cnt, nbr_idx, phitrig, dsys, sys_off, sys_P, sys_pbase, items, pA,
+    size_t ctl, X, R, U0, Y, Fs, nbr_cnt, nbr_idx, phitrig, dsys, sys_off, sys_P, sys_pbase, items, pA,
         pB, pC, pD, pA2, pB2, pC2, pD2, part, tab, total;
 };
 
@@ -231,7 +228,6 @@ static Layout layout(const ad_ctx* c) {
     const bool steric = c->p.steric_k != 0.0;
     L.Y = take(steric ? 3 * N * 8 : 0);
     L.Fs = take(steric ? 3 * N * 8 : 0);
-    L.blk_cnt = take(N * 4);
     L.nbr_cnt = take(uses_lists(c) ? N * 4 : 0);
     L.nbr_idx = take(uses_lists(c) ? N * 4 * ad::NBR_CAP : 0);
     L.phitrig = take(S * 16);
@@ -265,7 +261,6 @@ static void make_dev(ad_ctx* c) {
     d.U0 = reinterpret_cast<double*>(b + L.U0);
     d.Y = reinterpret_cast<double*>(b + L.Y);
     d.Fs = reinterpret_cast<double*>(b + L.Fs);
-    d.blk_cnt = reinterpret_cast<int*>(b + L.blk_cnt);
     d.nbr_cnt = uses_lists(c) ? reinterpret_cast<int*>(b + L.nbr_cnt) : nullptr;
     d.nbr_idx = uses_lists(c) ? reinterpret_cast<int*>(b + L.nbr_idx) : nullptr;
     {
@@ -428,13 +423,12 @@ static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mod
 static int launch_step_kernels(ad_ctx* c, hipStream_t st) {
     const int nst = c->p.integrator == AD_RK4 ? 4 : 2;
     const bool steric = c->p.steric_k != 0.0;
-    const bool fuse = shape_of(c).fuse != 0;
     for (int s = 0; s < nst; ++s) {
         const Dev& d = (s & 1) ? c->dev_odd : c->dev;
         const ad::Epi e = epi_of(c, s, nullptr);
-        int rc = launch_pairs_timed(c, d, e, fuse ? 2 : 1, st);
+        int rc = launch_pairs_timed(c, d, e, 1, st);
         if (rc != AD_OK) return rc;
-        if (!fuse) HIPCHECK(c, ad::launch_epilogue(d, e, st));
+        HIPCHECK(c, ad::launch_epilogue(d, e, st));
         if (steric) HIPCHECK(c, ad::launch_steric_pack(d, c->coef, e.prec, st));
     }
     return AD_OK;
@@ -623,7 +617,6 @@ int ad_set_launch(ad_ctx* c, const ad_launch* L) {
     if (want.jchunk == 0) want.jchunk = def.jchunk;
     if (want.wj == 0) want.wj = (want.wg == def.wg) ? def.wj : 1;
     if (want.posmode == 0) want.posmode = def.posmode;
-    if (want.fuse == 0) want.fuse = def.fuse;
     int rc = validate_launch(c, want);
     if (rc != AD_OK) return rc;
     ad_launch old = c->launch;

@@ -97,13 +97,13 @@ def test_launch_shapes_and_workspace_size():
         P.ad_set_launch(ctx, ipl=4, jchunk=4096, wg=256)
         one_chunk = P.ad_workspace_size(ctx)
         P.ad_set_launch(ctx, ipl=4, jchunk=64, wg=256)
-        assert P.ad_get_launch(ctx) == {"ipl": 4, "jchunk": 64, "wg": 256, "wj": 4, "posmode": 1, "fuse": 1}
+        assert P.ad_get_launch(ctx) == {"ipl": 4, "jchunk": 64, "wg": 256, "wj": 4, "posmode": 1}
         # 64 j-chunks hold 64 partial sums per sphere instead of one
         assert P.ad_workspace_size(ctx) - one_chunk >= 63 * 3 * 4096 * 8
-        P.ad_set_launch(ctx, ipl=2, jchunk=512, wg=256, wj=4, posmode=2, fuse=2)
-        assert P.ad_get_launch(ctx)["fuse"] == 2
+        P.ad_set_launch(ctx, ipl=2, jchunk=512, wg=256, wj=4, posmode=2)
+        assert P.ad_get_launch(ctx)["posmode"] == 2
         for bad in (dict(ipl=3), dict(wg=128), dict(jchunk=32), dict(wg=256, wj=2), dict(wg=64, wj=4),
-                    dict(posmode=3), dict(fuse=3)):
+                    dict(posmode=3)):
             with pytest.raises(P.ADError):
                 P.ad_set_launch(ctx, **bad)
     finally:
@@ -114,8 +114,6 @@ def test_launch_shapes_and_workspace_size():
             P.ad_set_launch(ctx, ipl=4)
         with pytest.raises(P.ADError):
             P.ad_set_launch(ctx, wg=256, wj=4)
-        with pytest.raises(P.ADError):
-            P.ad_set_launch(ctx, fuse=2)
     finally:
         P.ad_destroy(ctx)
 
