@@ -54,6 +54,10 @@ struct ad_ctx {
     Dev dev{};     /* even stages: read pack 0, write pack 1 */
     Dev dev_odd{}; /* odd stages: read pack 1, write pack 0 */
     bool state = false;
+    /* the first pack holds the state's stage-0 pack (written by the last
+     * stage of the previous step call); anything that overwrites or moves it
+     * clears this */
+    bool pack_valid = false;
     double t0 = 0.0;
     long long step = 0;
 
@@ -463,9 +467,12 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
         if (rc != AD_OK) return rc;
     }
     HIPCHECK(c, ad::launch_set_step(c->dev, c->step, st));
-    double s0, c0;
-    trig_at(c, c->t0 + (double)c->step * c->p.dt, &s0, &c0);
-    HIPCHECK(c, ad::launch_pack_state(c->dev, c->coef, prec, s0, c0, st));
+    if (!c->pack_valid) {
+        double s0, c0;
+        trig_at(c, c->t0 + (double)c->step * c->p.dt, &s0, &c0);
+        HIPCHECK(c, ad::launch_pack_state(c->dev, c->coef, prec, s0, c0, st));
+    }
+    c->pack_valid = false; /* until this call completes */
     long long done = 0, rec = 0;
     while (done < nsteps) {
         const int chunk = (int)std::min<long long>(nsteps - done, kTabSteps);
@@ -489,6 +496,7 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
         done += chunk;
     }
     c->step += nsteps;
+    c->pack_valid = true;
     return AD_OK;
 }
 
@@ -604,6 +612,7 @@ int ad_bind_workspace(ad_ctx* c, void* ptr, uint64_t bytes) {
     c->ws = ptr;
     c->ws_bytes = bytes;
     c->state = false;
+    c->pack_valid = false;
     make_dev(c);
     return upload_tables(c);
 }
@@ -629,8 +638,9 @@ int ad_set_launch(ad_ctx* c, const ad_launch* L) {
             return fail(c, AD_ENOMEM, "workspace too small for this launch shape");
         }
         /* regions ahead of the work list (state, phases, tables) keep their
-         * offsets; the packs, partials and step table are rebuilt per step */
+         * offsets; the packs, partials and step table move */
         drop_graph(c);
+        c->pack_valid = false;
         make_dev(c);
         return upload_tables(c);
     }
@@ -662,6 +672,7 @@ int ad_set_state(ad_ctx* c, const double* X, const double* phi, double t0, int64
     c->t0 = t0;
     c->step = step0;
     c->state = true;
+    c->pack_valid = false;
     return AD_OK;
 }
 
@@ -693,6 +704,7 @@ int ad_mobility_apply(ad_ctx* c, const double* X, const double* F, double* u, vo
     if (!X || !F || !u) return fail(c, AD_EINVAL, "null X, F or u");
     hipStream_t st = as_stream(stream);
     const int prec = prec_of(c);
+    c->pack_valid = false; /* the apply pack overwrites the state's */
     HIPCHECK(c, ad::launch_pack_apply(c->dev, c->coef, prec, X, F, st));
     ad::Shape sh = shape_of(c);
     sh.steric = 0; /* candidate lists belong to the step loop */

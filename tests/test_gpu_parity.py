@@ -572,3 +572,26 @@ def test_heun_noise_deterministic_and_resumable():
     s3.set_state(Xh, sus.phi, t0, st)
     s3.step(60)
     assert np.array_equal(s3.get_state()[0].cpu().numpy(), a)
+
+
+@pytest.mark.parametrize("precision,steric", [("fp32c", False), ("fp32c", True), ("fp64", True)])
+def test_split_step_calls_equal_one_call(oracle, precision, steric):
+    """A step call leaves the next step's pack in place; later calls reuse it.
+    Four calls of 50 steps, with a mobility apply and a record run in between
+    (which must not disturb the state), equal one call of 200 steps bit for
+    bit."""
+    _torch()
+    p = Params(steric_k=100.0, steric_r=2.0) if steric else Params()
+    sus = make_single(60, 22.0, 6, p, rmin=1.6 if steric else None)
+    one = P.Simulator(p, [sus.S], precision=precision, graph=True)
+    one.set_state(sus.X, sus.phi)
+    one.step(200)
+    parts = P.Simulator(p, [sus.S], precision=precision, graph=True)
+    parts.set_state(sus.X, sus.phi)
+    parts.step(50)
+    parts.mobility(sus.X, np.ones_like(sus.X))
+    parts.step(50)
+    _, _, code = parts.run(50, 25)
+    assert code == 0
+    parts.step(50)
+    assert np.array_equal(one.get_state()[0].cpu().numpy(), parts.get_state()[0].cpu().numpy())
