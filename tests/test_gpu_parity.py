@@ -121,15 +121,20 @@ def test_mobility_fp32c(oracle, S, side, launch):
     assert e1 <= 1e-6 and e2 <= 1e-6
 
 
-def test_mobility_fp32c_full_size_sampled(oracle):
-    """65536 spheres in the default launch: 64 sampled target spheres against
-    the oracle's rows, error relative to the sampled velocity norm."""
+@pytest.mark.parametrize("launch", [None, "tuned",
+                                    {"ipl": 2, "jchunk": 4096, "wg": 256, "wj": 4, "posmode": 1},
+                                    {"ipl": 4, "jchunk": 2048, "wg": 256, "wj": 1, "posmode": 1}])
+def test_mobility_fp32c_full_size_sampled(oracle, launch):
+    """65536 spheres, default, tuned and large-N launch shapes: 64 sampled
+    target spheres against the oracle's rows, error relative to the sampled
+    velocity norm."""
     torch = _torch()
     sus = make_preset("n65536")
-    say("mobility fp32c n65536 sampled")
+    say(f"mobility fp32c n65536 sampled, launch {launch}")
     X = perturbed(sus, 0.2)
     F = oracle.forces(sus.params, X, sus.phi, 3.0)
-    s = sim(sus, sus.params, "fp32c")
+    s = sim(sus, sus.params, "fp32c", launch=launch)
+    say(f"  launch {s.launch}")
     u = s.mobility(X, F).cpu().numpy()
     rows = np.random.default_rng(7).choice(sus.N, 64, replace=False)
     uo = oracle.mobility_rows(sus.params, X, F, rows)
