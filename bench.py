@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--fp64-steps", type=int, default=200)
+    ap.add_argument("--dense-steps", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -154,6 +155,17 @@ def main():
     v64 = pairs_per_step * args.fp64_steps / secs64
     log(f"fp64_tiled: {secs64 / args.fp64_steps * 1e3:.4f} ms/step, {v64:.4e} pairs/s")
 
+    # the paper's own design: assembled full tensor, then the product (Sec. V)
+    simd = P.Simulator(sus.params, [S], precision="fp64_dense", graph=not args.no_graph)
+    simd.set_state(sus.X, sus.phi)
+    secsd, _ = time_steps(simd, args.dense_steps, max(1, args.dense_steps // 10))
+    assert simd.check() == 0
+    vd = pairs_per_step * args.dense_steps / secsd
+    dense_bytes = 4 * 2 * 72.0 * N * N  # per step: 4 stages, tensor written once and read once
+    log(f"fp64_dense: {secsd / args.dense_steps * 1e3:.4f} ms/step, {vd:.4e} pairs/s")
+    simd.close()
+    del simd
+
     out = {
         "metric": "Oseen pair interactions/s and sphere-steps/s at N=4096, FP32-comp vs FP64",
         "value": value,
@@ -174,6 +186,10 @@ def main():
         "fp64_tiled": {"value": v64, "unit": "pair interactions/s", "ms_per_step": secs64 / args.fp64_steps * 1e3,
                        "steps": args.fp64_steps},
         "speedup_vs_fp64": value / v64,
+        "fp64_dense": {"value": vd, "unit": "pair interactions/s", "ms_per_step": secsd / args.dense_steps * 1e3,
+                       "steps": args.dense_steps,
+                       "tensor_GBps": dense_bytes * args.dense_steps / secsd / 1e9},
+        "speedup_vs_dense": value / vd,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counted_traffic(sim.launch), "traffic_unit": "B per launch",
                      "kernel": "k_pairs_f32c", "avg_launch_us": avg_ms * 1e3,

@@ -59,6 +59,12 @@ extern "C" {
 #define AD_FP32C 2     /* FP32 pair math on hi/lo-split positions with
                           compensated (TwoSum) accumulation over j; self and
                           dumbbell-partner terms, state and RK4 in FP64 */
+#define AD_FP64_DENSE 3 /* the paper's own GPU design (Sec. V): every stage
+                          assembles each system's full 3Nb x 3Nb pair tensor
+                          (FP64, 72 Nb^2 bytes of workspace per system, at most
+                          32 GiB in all) and multiplies it by the forces. An
+                          HBM-bound baseline for comparison; same results as
+                          AD_FP64 up to rounding order */
 
 /* time integrator (ad_params.integrator) */
 #define AD_RK4 0
@@ -84,7 +90,7 @@ typedef struct ad_params {
     double dt;       /* time step, > 0 */
     double steric_k; /* steric repulsion strength; 0 disables (not in the paper) */
     double steric_r; /* steric contact distance, force steric_k (steric_r - r) for r < steric_r */
-    int32_t precision;  /* AD_FP64 | AD_FP64_TILED | AD_FP32C */
+    int32_t precision;  /* AD_FP64 | AD_FP64_TILED | AD_FP32C | AD_FP64_DENSE */
     int32_t integrator; /* AD_RK4 | AD_HEUN */
     int32_t tensor;     /* AD_OSEEN | AD_RPY */
     int32_t reserved;   /* must be 0 */
@@ -96,9 +102,10 @@ typedef struct ad_params {
  * this size". A work-group of wg threads holds wg/64/wj waves on distinct
  * target spheres (ipl per lane) and wj waves that split every j-tile. */
 typedef struct ad_launch {
-    int32_t ipl;      /* target spheres per lane: 1, 2 or 4 (FP64 modes: 1 or 2) */
-    int32_t jchunk;   /* source spheres per work-group, >= 64 (AD_FP64: whole system) */
-    int32_t wg;       /* work-group size: 64 or 256 */
+    int32_t ipl;      /* target spheres per lane: 1, 2 or 4 (FP64 modes: 1 or 2; dense: 1) */
+    int32_t jchunk;   /* source spheres per work-group, >= 64 (AD_FP64: whole system;
+                         AD_FP64_DENSE: tensor columns of 64..1024 spheres per product item) */
+    int32_t wg;       /* work-group size: 64 or 256 (AD_FP64_DENSE: 256 tensor rows) */
     int32_t wj;       /* waves splitting each j-tile: 1, or 4 with wg = 256 (AD_FP32C) */
     int32_t posmode;  /* AD_FP32C positions: 1 = hi/lo float pair, 2 = single float */
     int32_t reserved; /* must be 0 */

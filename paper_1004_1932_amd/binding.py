@@ -14,12 +14,12 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "libad.so"
 
 AD_OK, AD_EINVAL, AD_ENOMEM, AD_EDEVICE, AD_ESTATE, AD_ENONFINITE, AD_ERANGE = 0, -1, -2, -3, -4, -5, -6
-AD_FP64, AD_FP64_TILED, AD_FP32C = 0, 1, 2
+AD_FP64, AD_FP64_TILED, AD_FP32C, AD_FP64_DENSE = 0, 1, 2, 3
 AD_RK4, AD_HEUN = 0, 1
 AD_OSEEN, AD_RPY = 0, 1
 TENSORS = {"oseen": AD_OSEEN, "rpy": AD_RPY}
 
-PRECISIONS = {"fp64": AD_FP64, "fp64_tiled": AD_FP64_TILED, "fp32c": AD_FP32C}
+PRECISIONS = {"fp64": AD_FP64, "fp64_tiled": AD_FP64_TILED, "fp32c": AD_FP32C, "fp64_dense": AD_FP64_DENSE}
 INTEGRATORS = {"rk4": AD_RK4, "heun": AD_HEUN}
 
 # the exported entry points, in the order include/ad.h declares them

@@ -36,6 +36,11 @@ enum {
  * previous stage positions, at most NBR_CAP per sphere */
 constexpr int NBR_CAP = 16;
 
+/* dense mode: tensor rows per product work item, and the largest j-chunk
+ * (its forces are staged in LDS) */
+constexpr int DENSE_ROWS = 256;
+constexpr int DENSE_JMAX = 1024;
+
 /* Constants of the model, precomputed on the host. */
 struct Coef {
     double cs;   /* 1/(6 pi eta a) */
@@ -83,6 +88,8 @@ struct Dev {
     float* pC2;
     double2* pD2;
     double* part;       /* partial sums */
+    double* H;          /* dense mode: per system the 3Nb x 3Nb pair tensor, column-major */
+    const long long* sys_hbase; /* [nsys] dense mode: first element of the system's tensor */
     const double* tab;  /* [ring][8] (sin, cos) of omega*t per epilogue stage */
     int ring;           /* entries in tab */
     int Ntot, Stot, nsys, nitems;
@@ -102,6 +109,15 @@ struct Epi {
     int pack_next;  /* 1: write the next pack; 0: stage positions and spring forces for the steric kernel */
     double* u_aos;  /* mobility apply: velocities out, row-major [N][3]; else nullptr */
 };
+
+/* Step bookkeeping, done by the first kernel of every stage (block 0,
+ * thread 0): stage 0 copies slot 0 into slot 1, the last stage advances slot
+ * 0. Readers in the same stage read the other slot. */
+__device__ __forceinline__ void advance_slots(const Dev& d, const Epi& e) {
+    if (blockIdx.x != 0 || blockIdx.y != 0 || threadIdx.x != 0) return;
+    if (e.stage == 0) d.ctl->slot[1] = d.ctl->slot[0];
+    if (e.stage == e.nst - 1) d.ctl->slot[0] = d.ctl->slot[1] + 1;
+}
 
 /* Launch shape of the pair kernel: WG threads = (WG/64/wj) waves on distinct
  * targets x wj waves splitting each j-tile; ipl targets per lane; split = 1
@@ -130,6 +146,11 @@ hipError_t launch_forces(const Dev& d, const Coef& c, const double* Xaos, double
 /* pair sum; mode 0 = mobility apply, 1 = step stage. With events, they time
  * the dispatch itself. */
 hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s,
+                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+/* dense mode (ad_dense.hip): assemble every system's pair tensor from the
+ * FP64 pack, then multiply it by the packed forces into the partial sums;
+ * the events, if given, bracket both launches */
+hipError_t launch_dense(const Dev& d, const Epi& e, int mode, int maxNb, hipStream_t s,
                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_epilogue(const Dev& d, const Epi& e, hipStream_t s);
 /* steric forces at stage positions Y, then the next pack (steric path) */

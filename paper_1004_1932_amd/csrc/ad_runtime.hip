@@ -47,6 +47,9 @@ struct ad_ctx {
     std::vector<int32_t> sysP;
     std::vector<long long> pbase;
     long long npart = 0;
+    std::vector<long long> hbase; /* dense mode: first tensor element per system */
+    long long nH = 0;             /* dense mode: tensor elements over all systems */
+    int maxNb = 0;
 
     /* workspace */
     void* ws = nullptr;
@@ -108,12 +111,33 @@ static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 
 /* ------------------------------------------------------------ work list */
 
+static bool is_dense(const ad_ctx* c) { return c->p.precision == AD_FP64_DENSE; }
+
+/* dense mode: tensor bytes over all systems, 72 Nb^2 each */
+static double dense_bytes(int nsys, const int32_t* S) {
+    double b = 0.0;
+    for (int q = 0; q < nsys; ++q) b += 72.0 * (2.0 * S[q]) * (2.0 * S[q]);
+    return b;
+}
+constexpr double kDenseMaxBytes = 34359738368.0; /* 32 GiB */
+
 static ad_launch default_launch(const ad_ctx* c) {
     ad_launch L{};
     int maxN = 0;
     for (int b = 0; b < c->nsys; ++b) maxN = std::max(maxN, 2 * c->S[b]);
     L.wj = 1;
     L.posmode = c->p.precision == AD_FP32C ? AD_POS_HILO : 0;
+    if (is_dense(c)) {
+        /* about 2048 product items: row blocks x j-chunks */
+        L.wg = ad::DENSE_ROWS;
+        L.ipl = 1;
+        const int rb = (3 * maxN + ad::DENSE_ROWS - 1) / ad::DENSE_ROWS;
+        const int P = std::max(1, 2048 / rb);
+        int jc = (maxN + P - 1) / P;
+        jc = std::min(ad::DENSE_JMAX, std::max(64, (jc + 63) / 64 * 64));
+        L.jchunk = jc;
+        return L;
+    }
     if (c->p.precision == AD_FP64) {
         L.ipl = 1;
         L.wg = 64;
@@ -140,6 +164,13 @@ static ad_launch default_launch(const ad_ctx* c) {
 }
 
 static int validate_launch(ad_ctx* c, const ad_launch& L) {
+    if (is_dense(c)) {
+        if (L.wg != ad::DENSE_ROWS || L.ipl != 1 || L.wj != 1 || L.posmode != 0 || L.reserved != 0)
+            return fail(c, AD_EINVAL, "AD_FP64_DENSE takes wg %d, ipl 1, wj 1, posmode 0", ad::DENSE_ROWS);
+        if (L.jchunk < 64 || L.jchunk > ad::DENSE_JMAX)
+            return fail(c, AD_EINVAL, "AD_FP64_DENSE: launch.jchunk must be in [64, %d]", ad::DENSE_JMAX);
+        return AD_OK;
+    }
     if (L.wg != 64 && L.wg != 256) return fail(c, AD_EINVAL, "launch.wg must be 64 or 256 (got %d)", L.wg);
     if (L.ipl != 1 && L.ipl != 2 && L.ipl != 4) return fail(c, AD_EINVAL, "launch.ipl must be 1, 2 or 4");
     if (L.wj != 1 && !(L.wj == 4 && L.wg == 256 && c->p.precision == AD_FP32C))
@@ -167,14 +198,61 @@ static ad::Shape shape_of(const ad_ctx* c) {
 }
 
 /* partial-sum components per sphere: FP64 with RPY keeps the correction apart */
-static int ncomp_of(const ad_ctx* c) { return (c->p.tensor == AD_RPY && c->p.precision != AD_FP32C) ? 6 : 3; }
+static int ncomp_of(const ad_ctx* c) {
+    return (c->p.tensor == AD_RPY && (c->p.precision == AD_FP64 || c->p.precision == AD_FP64_TILED)) ? 6 : 3;
+}
+
+/* dense mode: product items of DENSE_ROWS tensor rows x jchunk source
+ * spheres; i0 and ni count local tensor rows */
+static void build_dense_items(ad_ctx* c) {
+    const int jc0 = c->launch.jchunk;
+    c->items.clear();
+    c->sysP.assign(c->nsys, 1);
+    c->pbase.assign(c->nsys, 0);
+    c->hbase.assign(c->nsys, 0);
+    long long pb = 0, hb = 0;
+    for (int b = 0; b < c->nsys; ++b) {
+        const int Nb = 2 * c->S[b];
+        const int jc = std::min(jc0, Nb);
+        const int P = (Nb + jc - 1) / jc;
+        c->sysP[b] = P;
+        c->pbase[b] = pb;
+        c->hbase[b] = hb;
+        pb += (long long)P * 3 * Nb;
+        hb += 9LL * Nb * Nb;
+        for (int ch = 0; ch < P; ++ch)
+            for (int r = 0; r < 3 * Nb; r += ad::DENSE_ROWS) {
+                Item it;
+                it.sys = b;
+                it.i0 = r;
+                it.ni = std::min(ad::DENSE_ROWS, 3 * Nb - r);
+                it.j0 = c->off[b] + ch * jc;
+                it.nj = std::min(jc, Nb - ch * jc);
+                it.c = ch;
+                it.Nb = Nb;
+                it.ioff = c->off[b];
+                c->items.push_back(it);
+            }
+    }
+    c->npart = pb;
+    c->nH = hb;
+    std::stable_sort(c->items.begin(), c->items.end(), [](const Item& a, const Item& b) {
+        return (long long)a.ni * a.nj > (long long)b.ni * b.nj;
+    });
+}
 
 static void build_items(ad_ctx* c) {
     const ad_launch& L = c->launch;
     const int NC = ncomp_of(c);
+    if (is_dense(c)) {
+        build_dense_items(c);
+        return;
+    }
     c->items.clear();
     c->sysP.assign(c->nsys, 1);
     c->pbase.assign(c->nsys, 0);
+    c->hbase.assign(c->nsys, 0);
+    c->nH = 0;
     long long pb = 0;
     const int IB = L.ipl * L.wg / L.wj;
     for (int b = 0; b < c->nsys; ++b) {
@@ -212,8 +290,8 @@ static void build_items(ad_ctx* c) {
 /* ------------------------------------------------------------ workspace */
 
 struct Layout {
-    size_t ctl, X, R, U0, Y, Fs, nbr_cnt, nbr_idx, phitrig, dsys, sys_off, sys_P, sys_pbase, items, pA,
-        pB, pC, pD, pA2, pB2, pC2, pD2, part, tab, total;
+    size_t ctl, X, R, U0, Y, Fs, nbr_cnt, nbr_idx, phitrig, dsys, sys_off, sys_P, sys_pbase, sys_hbase, items,
+        pA, pB, pC, pD, pA2, pB2, pC2, pD2, part, tab, H, total;
 };
 
 static Layout layout(const ad_ctx* c) {
@@ -239,6 +317,7 @@ static Layout layout(const ad_ctx* c) {
     L.sys_off = take((c->nsys + 1) * 4);
     L.sys_P = take(c->nsys * 4);
     L.sys_pbase = take(c->nsys * 8);
+    L.sys_hbase = take(c->nsys * 8);
     L.items = take(std::max<size_t>(1, c->items.size()) * sizeof(Item));
     const bool f32 = c->p.precision == AD_FP32C;
     L.pA = take(f32 ? N * 16 : 0);
@@ -251,6 +330,7 @@ static Layout layout(const ad_ctx* c) {
     L.pD2 = take(f32 ? 0 : 3 * N * 16);
     L.part = take((size_t)c->npart * 8);
     L.tab = take((size_t)kRing * 8 * 8);
+    L.H = take((size_t)c->nH * 8);
     L.total = o;
     return L;
 }
@@ -279,6 +359,8 @@ static void make_dev(ad_ctx* c) {
     d.sys_off = reinterpret_cast<const int*>(b + L.sys_off);
     d.sys_P = reinterpret_cast<const int*>(b + L.sys_P);
     d.sys_pbase = reinterpret_cast<const long long*>(b + L.sys_pbase);
+    d.sys_hbase = reinterpret_cast<const long long*>(b + L.sys_hbase);
+    d.H = c->nH ? reinterpret_cast<double*>(b + L.H) : nullptr;
     d.items = reinterpret_cast<const Item*>(b + L.items);
     d.pA = reinterpret_cast<float4*>(b + L.pA);
     d.pB = reinterpret_cast<float4*>(b + L.pB);
@@ -323,6 +405,7 @@ static int upload_tables(ad_ctx* c) {
     HIPCHECK(c, hipMemcpy(b + L.sys_off, c->off.data(), (c->nsys + 1) * 4, hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(b + L.sys_P, c->sysP.data(), c->nsys * 4, hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(b + L.sys_pbase, c->pbase.data(), c->nsys * 8, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(b + L.sys_hbase, c->hbase.data(), c->nsys * 8, hipMemcpyHostToDevice));
     if (!c->items.empty())
         HIPCHECK(c, hipMemcpy(b + L.items, c->items.data(), c->items.size() * sizeof(Item), hipMemcpyHostToDevice));
     return AD_OK;
@@ -407,7 +490,10 @@ static ad::Epi epi_of(const ad_ctx* c, int stage, double* u_aos) {
 static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mode, hipStream_t st) {
     const ad::Shape sh = shape_of(c);
     if (!c->profile) {
-        HIPCHECK(c, ad::launch_pairs(d, e, sh, mode, st));
+        if (is_dense(c))
+            HIPCHECK(c, ad::launch_dense(d, e, mode, c->maxNb, st));
+        else
+            HIPCHECK(c, ad::launch_pairs(d, e, sh, mode, st));
         return AD_OK;
     }
     if (c->ev.empty()) {
@@ -418,7 +504,10 @@ static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mod
         int rc = profile_flush(c);
         if (rc != AD_OK) return rc;
     }
-    HIPCHECK(c, ad::launch_pairs(d, e, sh, mode, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
+    if (is_dense(c))
+        HIPCHECK(c, ad::launch_dense(d, e, mode, c->maxNb, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
+    else
+        HIPCHECK(c, ad::launch_pairs(d, e, sh, mode, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
     c->ev_used += 1;
     return AD_OK;
 }
@@ -526,7 +615,8 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
     if (!(p->a > 0) || !(p->eta > 0) || !(p->T > 0) || !(p->dt > 0))
         return fail(nullptr, AD_EINVAL, "a, eta, T and dt must be > 0");
     if (p->steric_k != 0.0 && !(p->steric_r > 0)) return fail(nullptr, AD_EINVAL, "steric_r must be > 0");
-    if (p->precision != AD_FP64 && p->precision != AD_FP64_TILED && p->precision != AD_FP32C)
+    if (p->precision != AD_FP64 && p->precision != AD_FP64_TILED && p->precision != AD_FP32C &&
+        p->precision != AD_FP64_DENSE)
         return fail(nullptr, AD_EINVAL, "unknown precision %d", p->precision);
     if (p->integrator != AD_RK4 && p->integrator != AD_HEUN)
         return fail(nullptr, AD_EINVAL, "unknown integrator %d", p->integrator);
@@ -540,6 +630,9 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
         Stot += S_per_sys[b];
     }
     if (2 * Stot > (1LL << 30)) return fail(nullptr, AD_EINVAL, "too many spheres");
+    if (p->precision == AD_FP64_DENSE && dense_bytes(nsys, S_per_sys) > kDenseMaxBytes)
+        return fail(nullptr, AD_EINVAL, "AD_FP64_DENSE: the pair tensors would take %.3g GB (limit 32 GiB)",
+                    dense_bytes(nsys, S_per_sys) / 1e9);
     ad_ctx* c = new (std::nothrow) ad_ctx();
     if (!c) return fail(nullptr, AD_ENOMEM, "out of host memory");
     c->p = *p;
@@ -570,6 +663,7 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
     k.g = sqrt(2.0 * p->kT * (1.0 / (6.0 * kPi * p->eta * p->a)) * p->dt);
     k.seed = p->seed;
     c->omega = 2.0 * kPi / p->T;
+    for (int b = 0; b < nsys; ++b) c->maxNb = std::max(c->maxNb, 2 * c->S[b]);
     c->launch = default_launch(c);
     build_items(c);
     *out = c;
@@ -709,7 +803,10 @@ int ad_mobility_apply(ad_ctx* c, const double* X, const double* F, double* u, vo
     ad::Shape sh = shape_of(c);
     sh.steric = 0; /* candidate lists belong to the step loop */
     const ad::Epi e = epi_of(c, 0, u);
-    HIPCHECK(c, ad::launch_pairs(c->dev, e, sh, 0, st));
+    if (is_dense(c))
+        HIPCHECK(c, ad::launch_dense(c->dev, e, 0, c->maxNb, st));
+    else
+        HIPCHECK(c, ad::launch_pairs(c->dev, e, sh, 0, st));
     HIPCHECK(c, ad::launch_epilogue(c->dev, e, st));
     return AD_OK;
 }

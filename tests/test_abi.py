@@ -118,6 +118,33 @@ def test_launch_shapes_and_workspace_size():
         P.ad_destroy(ctx)
 
 
+def test_dense_mode_launch_rules_and_workspace():
+    """AD_FP64_DENSE keeps each system's 3Nb x 3Nb FP64 tensor in the
+    workspace (72 Nb^2 bytes) and takes only its own launch shape."""
+    S = [64, 40]
+    sizes = {}
+    for prec in ("fp64_tiled", "fp64_dense"):
+        ctx = P.ad_create(P.make_params(Params(), prec), S)
+        try:
+            sizes[prec] = P.ad_workspace_size(ctx)
+            if prec == "fp64_dense":
+                L = P.ad_get_launch(ctx)
+                assert L["wg"] == 256 and L["ipl"] == 1 and L["wj"] == 1 and 64 <= L["jchunk"] <= 1024
+                P.ad_set_launch(ctx, jchunk=64)
+                assert P.ad_get_launch(ctx)["jchunk"] == 64
+                for bad in (dict(jchunk=2048), dict(jchunk=32), dict(wg=64), dict(ipl=2), dict(posmode=1)):
+                    with pytest.raises(P.ADError):
+                        P.ad_set_launch(ctx, **bad)
+        finally:
+            P.ad_destroy(ctx)
+    tensor = sum(72 * (2 * s) ** 2 for s in S)
+    assert sizes["fp64_dense"] - sizes["fp64_tiled"] >= tensor
+    # 32 GiB of tensors at most: N = 2 * 12000 needs 41 GB
+    with pytest.raises(P.ADError):
+        P.ad_create(P.make_params(Params(), "fp64_dense"), [12000])
+    P.ad_destroy(P.ad_create(P.make_params(Params(), "fp64_dense"), [8000]))
+
+
 def test_destroy_null_is_noop():
     assert P.lib().ad_destroy(None) == 0
 
