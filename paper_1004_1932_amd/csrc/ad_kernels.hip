@@ -349,6 +349,17 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
     const Coef& c = e.c;
     const int stage = e.stage;
     const bool apply = (e.u_aos != nullptr);
+    /* the second pass's inputs are loaded first, so their latency overlaps
+     * the partial-sum loads: (sin, cos) of omega t for the next stage's
+     * forces, and the phase of this thread's dumbbell */
+    double st = 0.0, ct = 0.0;
+    double2 tp = make_double2(0.0, 0.0);
+    if (!apply) {
+        const long long row = step % d.ring;
+        st = d.tab[row * 8 + 2 * stage];
+        ct = d.tab[row * 8 + 2 * stage + 1];
+        if (t < ni / 2) tp = d.phitrig[(i0 >> 1) + t];
+    }
     if (t == 0) *badf = 0;
     __syncthreads();
     for (int idx = t; idx < 3 * ni; idx += nt) {
@@ -427,18 +438,14 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
     __syncthreads();
     if (t == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
     if (apply) return;
-    /* forces of the next stage: (sin, cos) of omega t from the step table */
-    const long long row = step % d.ring;
-    const double st = d.tab[row * 8 + 2 * stage];
-    const double ct = d.tab[row * 8 + 2 * stage + 1];
-    for (int q = t; q < ni / 2; q += nt) {
-        const int s = (i0 >> 1) + q;
-        const int ia = 2 * s;
+    /* forces of the next stage, one thread per dumbbell (ni/2 <= blockDim) */
+    if (t < ni / 2) {
+        const int q = t;
+        const int ia = i0 + 2 * q;
         double y[2][3];
         for (int h = 0; h < 2; ++h)
             for (int a = 0; a < 3; ++a) y[h][a] = ys[2 * q + h][a];
         double f0[3], f1[3];
-        const double2 tp = d.phitrig[s];
         spring_forces(c, y[0], y[1], tp.x, tp.y, st, ct, f0, f1);
         if (e.pack_next) {
             store_pack(d, c, e.prec, ia, y[0], y[1], f0, f1, 1);
@@ -466,6 +473,7 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
  * stage */
 constexpr int EPI_S = 32;
 constexpr int EPI_T = 96;
+static_assert(EPI_S / 2 <= EPI_T, "one thread per dumbbell in the second pass");
 
 __global__ __launch_bounds__(EPI_T) void k_epilogue(Dev d, Epi e) {
     __shared__ double ys[EPI_S][3];
@@ -528,14 +536,6 @@ __device__ __noinline__ void add_candidate(const Dev& d, int i, int iend, int j)
         atomicOr(&d.ctl->flag, FLAG_NBR_FULL);
 }
 
-/* Step bookkeeping of a pair kernel in a step (one thread): stage 0 copies
- * slot 0 into slot 1, the last stage advances slot 0. Readers of this
- * kernel read the other slot. */
-__device__ __forceinline__ void advance_slots(const Dev& d, const Epi& e) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    if (e.stage == 0) d.ctl->slot[1] = d.ctl->slot[0];
-    if (e.stage == e.nst - 1) d.ctl->slot[0] = d.ctl->slot[1] + 1;
-}
 
 /* FP32C pair sum. A work-group of WG threads is WI x WJ waves: WI waves own
  * different target spheres (IPL consecutive spheres per lane), and the WJ
