@@ -52,7 +52,7 @@ def candidates(N: int, ensemble: bool):
         # j-chunks from 256 up to a size that leaves about 256 work-groups
         top = max(256, min(N, 256 * (1 << max(0, math.ceil(math.log2(max(1.0, N * N / (64 * 256 * 256))))))))
         for ipl in (1, 2, 4):
-            jc = 256
+            jc = 128
             while jc <= top:
                 out.append(dict(wg=256, wj=4, ipl=ipl, jchunk=jc, posmode=posmode))
                 jc *= 2

@@ -561,7 +561,6 @@ template <int WG, int IPL, int WJ, int SPLIT, int STERIC, int RPY>
 __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
     constexpr int WI = WG / 64 / WJ;
     constexpr int TJ = WG;          /* j per LDS tile */
-    constexpr int JW = TJ / WJ;     /* j per wave per tile */
     constexpr int IB = 64 * WI * IPL;
     /* one LDS area, used in turn by the source tiles and the cross-wave
      * combination (a barrier separates the uses) */
@@ -624,8 +623,11 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
         sC[t] = C;
         __syncthreads();
         const bool diag = (t0 < dhi) && (t0 + n > dlo);
-        const int jb = wj * JW;                     /* this wave's part of the tile */
-        const int nw = max(0, min(JW, n - jb));
+        /* this wave's part of the tile: the n entries in WJ runs of a
+         * multiple of 4 (WJ runs of 4 ceil(n / 4WJ) never pass TJ) */
+        const int jw = WJ == 1 ? n : (n + 4 * WJ - 1) / (4 * WJ) * 4;
+        const int jb = wj * jw;
+        const int nw = max(0, min(jw, n - jb));
         if (!diag) {
             const int n4 = (nw + 3) & ~3;
             for (int jj = jb; jj < jb + n4; jj += 4) {

@@ -98,7 +98,8 @@ def test_mobility_fp64_tiled(oracle, launch):
 FP32C_LAUNCHES = [None, dict(ipl=1, jchunk=64, wg=64), dict(ipl=2, jchunk=320, wg=256, wj=1),
                   dict(ipl=4, jchunk=256, wg=256, wj=4), dict(ipl=1, jchunk=1000, wg=256, wj=4),
                   dict(ipl=4, jchunk=1000, wg=64), dict(ipl=2, jchunk=512, wg=256, wj=4, posmode=2),
-                  dict(ipl=1, jchunk=64, wg=64, posmode=2)]
+                  dict(ipl=1, jchunk=64, wg=64, posmode=2), dict(ipl=1, jchunk=128, wg=256, wj=4, posmode=2),
+                  dict(ipl=2, jchunk=100, wg=256, wj=4)]
 
 
 @pytest.mark.parametrize("launch", FP32C_LAUNCHES)
