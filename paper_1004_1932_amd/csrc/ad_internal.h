@@ -24,6 +24,10 @@ struct Ctl {
     long long slot[2];
     int flag; /* FLAG_* bits, sticky until cleared */
     int pad[11];
+    /* (sin, cos) of omega t at which stage s's epilogue forms the next
+     * forces, copied from the step table by stage s's first kernel, so the
+     * epilogue reads it without first reading the step index */
+    double trig[4][2];
 };
 
 enum {
@@ -112,11 +116,21 @@ struct Epi {
 
 /* Step bookkeeping, done by the first kernel of every stage (block 0,
  * thread 0): stage 0 copies slot 0 into slot 1, the last stage advances slot
- * 0. Readers in the same stage read the other slot. */
+ * 0; readers in the same stage read the other slot. It also copies the
+ * stage's (sin, cos)(omega t) row of the step table into ctl->trig. */
 __device__ __forceinline__ void advance_slots(const Dev& d, const Epi& e) {
     if (blockIdx.x != 0 || blockIdx.y != 0 || threadIdx.x != 0) return;
-    if (e.stage == 0) d.ctl->slot[1] = d.ctl->slot[0];
-    if (e.stage == e.nst - 1) d.ctl->slot[0] = d.ctl->slot[1] + 1;
+    long long step;
+    if (e.stage == 0) {
+        step = d.ctl->slot[0];
+        d.ctl->slot[1] = step;
+    } else {
+        step = d.ctl->slot[1];
+    }
+    if (e.stage == e.nst - 1) d.ctl->slot[0] = step + 1;
+    const long long row = step % d.ring;
+    d.ctl->trig[e.stage][0] = d.tab[row * 8 + 2 * e.stage];
+    d.ctl->trig[e.stage][1] = d.tab[row * 8 + 2 * e.stage + 1];
 }
 
 /* Launch shape of the pair kernel: WG threads = (WG/64/wj) waves on distinct

@@ -351,13 +351,13 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
     const bool apply = (e.u_aos != nullptr);
     /* the second pass's inputs are loaded first, so their latency overlaps
      * the partial-sum loads: (sin, cos) of omega t for the next stage's
-     * forces, and the phase of this thread's dumbbell */
+     * forces (left by this stage's pair kernel), and the phase of this
+     * thread's dumbbell */
     double st = 0.0, ct = 0.0;
     double2 tp = make_double2(0.0, 0.0);
     if (!apply) {
-        const long long row = step % d.ring;
-        st = d.tab[row * 8 + 2 * stage];
-        ct = d.tab[row * 8 + 2 * stage + 1];
+        st = d.ctl->trig[stage][0];
+        ct = d.ctl->trig[stage][1];
         if (t < ni / 2) tp = d.phitrig[(i0 >> 1) + t];
     }
     if (t == 0) *badf = 0;
@@ -481,7 +481,8 @@ __global__ __launch_bounds__(EPI_T) void k_epilogue(Dev d, Epi e) {
     __shared__ int badf;
     const int i0 = blockIdx.x * EPI_S;
     const int ni = min(EPI_S, d.Ntot - i0);
-    const long long step = e.u_aos ? 0 : d.ctl->slot[e.stage & 1];
+    /* the step index only numbers the noise of the Heun integrator */
+    const long long step = (e.u_aos || !e.c.noise) ? 0 : d.ctl->slot[e.stage & 1];
     epi_block(d, e, i0, ni, step, ys, mv, &badf);
 }
 
