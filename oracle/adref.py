@@ -15,7 +15,11 @@ import numpy as np
 HERE = Path(__file__).resolve().parent
 SRC = HERE / "adref.c"
 LIB = HERE / "libadref.so"
-CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c99", "-fPIC", "-shared"]
+# sin and cos stay separate libm calls, as written: without -fno-builtin-*
+# gcc merges sin(x) and cos(x) into one sincos(x) call, whose last bit can
+# differ from the separate calls
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fno-builtin-sin", "-fno-builtin-cos",
+          "-fno-builtin-sincos", "-fopenmp", "-std=c99", "-fPIC", "-shared"]
 
 
 def build(force: bool = True) -> Path:
