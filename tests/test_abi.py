@@ -160,3 +160,18 @@ def test_stroke_averaged_entry_points_validate_on_the_host():
     assert lib.ad_sa_run(C.byref(prm), 125, fake, fake, fake, -1.0, 1, fake, n.value, None) == B.AD_EINVAL
     bad = P.make_params(Params(T=0.0))
     assert lib.ad_sa_rhs(C.byref(bad), 125, fake, fake, fake, fake, fake, None) == B.AD_EINVAL
+
+
+def test_oracle_keeps_sin_and_cos_separate():
+    """The oracle's library calls libm sin and cos, never a merged sincos
+    (whose last bit differs for some arguments from the separate calls the
+    library's host table makes)."""
+    import shutil
+    import subprocess
+    from oracle import adref
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    adref.build(force=False)
+    out = subprocess.run(["nm", "-D", str(adref.LIB)], capture_output=True, text=True, check=True).stdout
+    undefined = {line.split()[-1].split("@")[0] for line in out.splitlines() if " U " in line}
+    assert {"sin", "cos"} <= undefined and "sincos" not in undefined

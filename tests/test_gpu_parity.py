@@ -58,6 +58,26 @@ def test_forces_bitwise(oracle):
             assert np.array_equal(F, oracle.forces(sus.params, X, sus.phi, t))
 
 
+def test_forces_bitwise_over_stage_times(oracle):
+    """Spring forces at 2000 RK4 stage times spread over the first 60 000
+    steps, t = 487.305 among them (the half-step time of step 48 730, where
+    the oracle's sin and cos once came from a merged sincos call): the host
+    (sin, cos)(omega t) of the library and of the oracle agree bitwise."""
+    _torch()
+    sus = make_preset("n512")
+    s = sim(sus, sus.params, "fp64")
+    s.set_state(sus.X, sus.phi)
+    dt = sus.params.dt
+    steps = np.random.default_rng(9).integers(0, 60_000, 1999)
+    times = [48_730 * dt + 0.5 * dt] + [n * dt + 0.5 * dt for n in steps[:999]] + [n * dt + dt for n in steps[999:]]
+    bad = []
+    for t in times:
+        F = s.forces(sus.X, t).cpu().numpy()
+        if not np.array_equal(F, oracle.forces(sus.params, sus.X, sus.phi, t)):
+            bad.append(t)
+    assert not bad, bad[:5]
+
+
 def test_forces_steric_bitwise(oracle):
     _torch()
     p = Params(steric_k=100.0, steric_r=2.0)
