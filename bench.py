@@ -5,7 +5,10 @@ the O(N^2) Oseen pair sum and the RK4 update, for S = 2048 dumbbells
 (N = 4096 spheres) in a cube of side 240 (seed 0, a = eta = k = 1, ell = 4,
 lambda = 1, T = 100, dt = 0.01), FP32 pair arithmetic with compensated
 accumulation and FP64 state. The inputs are resident on the device before
-the timed region starts. Prints one JSON line.
+the timed region starts. Prints one JSON line. `--workload` selects another
+of the seeded workloads (the 512-sphere suspension, the 512-system ensemble,
+the 65536-sphere suspension with steric repulsion) for profiles; N = 4096 is
+the default and the measured configuration.
 """
 from __future__ import annotations
 
@@ -28,10 +31,11 @@ FLOPS_PER_PAIR = 28           # algorithmic flops of one ordered pair term
 # each scaled by what the counter reads for a plain 256 MiB device copy.
 # Valid only for the kernel source and launch shape they were taken with.
 COUNTED = {
-    "source_sha256": "cb6da36fb2869faf13392b589956e851daaea7458590eb5b0c66677197dc3c6d",
+    "workload": "n4096",
+    "source_sha256": "131523fc33d0ca5aae4dc2ff368858a0c70cbcaf9fd6c3da72f85e160253ff60",
     "launch": {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 2},
-    "fetch_kib": 666.66, "fetch_scale": 262144.0 / 131092.44,
-    "write_kib": 1536.01, "write_scale": 262144.0 / 262144.0,
+    "fetch_kib": 669.58, "fetch_scale": 262144.0 / 131092.56,
+    "write_kib": 1536.05, "write_scale": 262144.0 / 262144.0,
 }
 
 
@@ -54,24 +58,37 @@ def time_steps(sim, steps, warmup):
     return start.elapsed_time(stop) / 1e3, wall
 
 
-def cpu_baseline(sus, budget_s):
-    """The oracle on the host cores: RK4 steps of the same suspension."""
+def cpu_baseline(w, sizes, budget_s):
+    """The oracle on the host cores: RK4 steps of the same workload."""
     from oracle import adref
     adref.build(force=False)
-    p = sus.params
-    N = sus.N
+    p = w.params
+    N = w.X.shape[0]
+    Nb = 2.0 * np.asarray(sizes, dtype=np.float64)
     t = time.perf_counter()
-    X, _, _, _ = adref.run(p, sus.X, sus.phi, 1)
+    X, _, _, _ = adref.run(p, w.X, w.phi, 1, S_per_sys=sizes)
     one = time.perf_counter() - t
     n = max(1, int(budget_s / max(one, 1e-6)) - 1)
     t = time.perf_counter()
-    adref.run(p, X, sus.phi, n, step0=1)
+    adref.run(p, X, w.phi, n, step0=1, S_per_sys=sizes)
     dt = time.perf_counter() - t
-    pairs = 4.0 * N * (N - 1) * n
+    pairs = 4.0 * float((Nb * (Nb - 1)).sum()) * n
     return {"value": pairs / dt, "unit": "pair interactions/s", "cores": adref.max_threads(),
             "kind": "oracle",
-            "sample": f"{n} RK4 steps of the N={N} suspension ({dt:.1f} s), FP64, OpenMP over target spheres",
+            "sample": f"{n} RK4 steps of the {N}-sphere workload ({dt:.1f} s), FP64, OpenMP over target spheres",
             "sphere_steps_per_s": N * n / dt}
+
+
+DESCRIPTIONS = {
+    "n4096": "suspension of S=2048 active dumbbells (N=4096 spheres), cube side 240, RK4 dt=0.01, Oseen, "
+             "FP32-compensated pair sum, FP64 state",
+    "n512": "suspension of S=256 active dumbbells (N=512 spheres), cube side 120, RK4 dt=0.01, Oseen, "
+            "FP32-compensated pair sum, FP64 state",
+    "ens512": "ensemble of 512 suspensions, S uniform in [16, 400] (221,234 spheres in all), density 0.02, "
+              "RK4 dt=0.01, Oseen, FP32-compensated pair sum, FP64 state",
+    "n65536": "suspension of S=32768 active dumbbells (N=65536 spheres), cube side 800, steric repulsion "
+              "100 (2a - r), RK4 dt=0.01, Oseen, FP32-compensated pair sum, FP64 state",
+}
 
 
 def counted_traffic(launch):
@@ -90,6 +107,8 @@ def counted_traffic(launch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="n4096", choices=sorted(DESCRIPTIONS),
+                    help="the N = 4096 suspension is the measured configuration; the others are for profiles")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--fp64-steps", type=int, default=200)
@@ -110,9 +129,13 @@ def main():
     from workload import make_preset
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    sus = make_preset("n4096")
-    N, S = sus.N, sus.S
-    pairs_per_step = 4.0 * N * (N - 1)
+    w = make_preset(args.workload)
+    sizes = [int(v) for v in w.S_per_sys] if hasattr(w, "S_per_sys") else [w.S]
+    Nb = 2.0 * np.asarray(sizes, dtype=np.float64)
+    N, S = w.X.shape[0], int(sum(sizes))
+    pairs_per_step = 4.0 * float((Nb * (Nb - 1)).sum())
+    # the dumbbell partner is summed in FP64 outside the pair kernel
+    kernel_pairs = float((Nb * (Nb - 2)).sum())
 
     if args.counter_probe:
         # a known-size copy calibrates FETCH_SIZE / WRITE_SIZE against bytes
@@ -121,16 +144,16 @@ def main():
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
-        sim = P.Simulator(sus.params, [S], precision="fp32c", launch="tuned")
-        sim.set_state(sus.X, sus.phi)
+        sim = P.Simulator(w.params, sizes, precision="fp32c", launch="tuned")
+        sim.set_state(w.X, w.phi)
         sim.step(3)
         torch.cuda.synchronize()
         print(json.dumps({"counter_probe": True, "copy_bytes": src.numel() * 8, "launch": sim.launch}), flush=True)
         return
 
     # FP32-compensated path, graph-replayed steps
-    sim = P.Simulator(sus.params, [S], precision="fp32c", graph=not args.no_graph, launch="tuned")
-    sim.set_state(sus.X, sus.phi)
+    sim = P.Simulator(w.params, sizes, precision="fp32c", graph=not args.no_graph, launch="tuned")
+    sim.set_state(w.X, w.phi)
     log(f"fp32c launch {sim.launch}")
     secs, wall = time_steps(sim, args.steps, args.warmup)
     assert sim.check() == 0
@@ -144,27 +167,34 @@ def main():
     kern_ms, launches = P.ad_profile_read(sim.ctx)
     P.ad_profile_pairs(sim.ctx, False)
     avg_ms = kern_ms / launches
-    kernel_pairs = N * (N - 2)  # the dumbbell partner is summed in FP64 outside the kernel
     achieved = FLOPS_PER_PAIR * kernel_pairs / (avg_ms * 1e-3) / 1e12
     log(f"pair kernel: {avg_ms * 1e3:.2f} us avg over {launches} launches, {achieved:.2f} TFLOP/s")
 
-    # plain FP64 form (tiled) timed beside it
-    sim64 = P.Simulator(sus.params, [S], precision="fp64_tiled", graph=not args.no_graph)
-    sim64.set_state(sus.X, sus.phi)
-    secs64, _ = time_steps(sim64, args.fp64_steps, max(1, args.fp64_steps // 10))
-    v64 = pairs_per_step * args.fp64_steps / secs64
-    log(f"fp64_tiled: {secs64 / args.fp64_steps * 1e3:.4f} ms/step, {v64:.4e} pairs/s")
+    # plain FP64 form (tiled) timed beside it, on about 2e11 pair terms at most
+    fp64_steps = max(2, min(args.fp64_steps, int(2e11 / pairs_per_step)))
+    sim64 = P.Simulator(w.params, sizes, precision="fp64_tiled", graph=not args.no_graph)
+    sim64.set_state(w.X, w.phi)
+    secs64, _ = time_steps(sim64, fp64_steps, max(1, fp64_steps // 10))
+    v64 = pairs_per_step * fp64_steps / secs64
+    log(f"fp64_tiled: {secs64 / fp64_steps * 1e3:.4f} ms/step, {v64:.4e} pairs/s")
+    sim64.close()
+    del sim64
 
-    # the paper's own design: assembled full tensor, then the product (Sec. V)
-    simd = P.Simulator(sus.params, [S], precision="fp64_dense", graph=not args.no_graph)
-    simd.set_state(sus.X, sus.phi)
-    secsd, _ = time_steps(simd, args.dense_steps, max(1, args.dense_steps // 10))
-    assert simd.check() == 0
-    vd = pairs_per_step * args.dense_steps / secsd
-    dense_bytes = 4 * 2 * 72.0 * N * N  # per step: 4 stages, tensor written once and read once
-    log(f"fp64_dense: {secsd / args.dense_steps * 1e3:.4f} ms/step, {vd:.4e} pairs/s")
-    simd.close()
-    del simd
+    # the paper's own design: assembled full tensor, then the product (Sec. V);
+    # per step 4 stages, each tensor written once and read once
+    dense_bytes = 4 * 2 * 72.0 * float((Nb * Nb).sum())
+    dense = None
+    if dense_bytes / 8 <= 8e9:
+        simd = P.Simulator(w.params, sizes, precision="fp64_dense", graph=not args.no_graph)
+        simd.set_state(w.X, w.phi)
+        secsd, _ = time_steps(simd, args.dense_steps, max(1, args.dense_steps // 10))
+        assert simd.check() == 0
+        vd = pairs_per_step * args.dense_steps / secsd
+        log(f"fp64_dense: {secsd / args.dense_steps * 1e3:.4f} ms/step, {vd:.4e} pairs/s")
+        dense = {"value": vd, "unit": "pair interactions/s", "ms_per_step": secsd / args.dense_steps * 1e3,
+                 "steps": args.dense_steps, "tensor_GBps": dense_bytes * args.dense_steps / secsd / 1e9}
+        simd.close()
+        del simd
 
     out = {
         "metric": "Oseen pair interactions/s and sphere-steps/s at N=4096, FP32-comp vs FP64",
@@ -179,25 +209,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "suspension of S=2048 active dumbbells (N=4096 spheres), cube side 240, "
-                               "RK4 dt=0.01, Oseen, FP32-compensated pair sum, FP64 state",
-                   "N": N, "S": S, "launch": sim.launch, "graph": not args.no_graph},
+        "config": {"workload": DESCRIPTIONS[args.workload], "name": args.workload,
+                   "N": N, "S": S, "systems": len(sizes), "launch": sim.launch, "graph": not args.no_graph},
         "sphere_steps_per_s": N * args.steps / secs,
-        "fp64_tiled": {"value": v64, "unit": "pair interactions/s", "ms_per_step": secs64 / args.fp64_steps * 1e3,
-                       "steps": args.fp64_steps},
+        "fp64_tiled": {"value": v64, "unit": "pair interactions/s", "ms_per_step": secs64 / fp64_steps * 1e3,
+                       "steps": fp64_steps},
         "speedup_vs_fp64": value / v64,
-        "fp64_dense": {"value": vd, "unit": "pair interactions/s", "ms_per_step": secsd / args.dense_steps * 1e3,
-                       "steps": args.dense_steps,
-                       "tensor_GBps": dense_bytes * args.dense_steps / secsd / 1e9},
-        "speedup_vs_dense": value / vd,
+        "fp64_dense": dense,
+        "speedup_vs_dense": value / dense["value"] if dense else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counted_traffic(sim.launch), "traffic_unit": "B per launch",
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": counted_traffic(sim.launch) if args.workload == COUNTED["workload"] else None,
+                     "traffic_unit": "B per launch",
                      "kernel": "k_pairs_f32c", "avg_launch_us": avg_ms * 1e3,
                      "flops_per_launch": FLOPS_PER_PAIR * kernel_pairs},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(sus, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, sizes, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
