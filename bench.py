@@ -33,7 +33,7 @@ FLOPS_PER_PAIR = 28           # algorithmic flops of one ordered pair term
 COUNTED = {
     "workload": "n4096",
     "source_sha256": "131523fc33d0ca5aae4dc2ff368858a0c70cbcaf9fd6c3da72f85e160253ff60",
-    "launch": {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 2},
+    "launch": {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 2, "fused": 0},
     "fetch_kib": 669.58, "fetch_scale": 262144.0 / 131092.56,
     "write_kib": 1536.05, "write_scale": 262144.0 / 262144.0,
 }

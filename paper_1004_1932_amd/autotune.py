@@ -60,6 +60,10 @@ def candidates(N: int, ensemble: bool):
             out.append(dict(wg=256, wj=1, ipl=ipl, jchunk=256, posmode=posmode))
             for jc in (128, 256):
                 out.append(dict(wg=64, wj=1, ipl=ipl, jchunk=jc, posmode=posmode))
+    if not ensemble:
+        # one kernel per stage with every source in LDS (refused where it does not apply)
+        for posmode in (B.AD_POS_HILO, B.AD_POS_SINGLE):
+            out.append(dict(wg=256, wj=4, ipl=1, jchunk=256, posmode=posmode, fused=1))
     uniq = []
     for c in out:
         if c not in uniq:
@@ -99,7 +103,8 @@ def tune(params, S_per_sys, X, phi, gate: float = 5e-7, steps: int = 50, cands=N
     """Tune on the state (X, phi). Returns {"launch", "ms_per_step", "err",
     "tried"}. A shape's error is the largest, over the gate states, relative
     difference between its velocities and AD_FP64_TILED velocities at the
-    same positions and forces (forces from ad_forces)."""
+    same positions and forces (forces from ad_forces), and between its
+    displacement over one step from that state and AD_FP64_TILED's."""
     import torch
     S_per_sys = np.asarray(S_per_sys, dtype=np.int32).reshape(-1)
     ref = B.Simulator(params, S_per_sys, precision="fp64_tiled")
@@ -108,7 +113,10 @@ def tune(params, S_per_sys, X, phi, gate: float = 5e-7, steps: int = 50, cands=N
     for Xs, t in gate_states(params, X):
         Xd = torch.as_tensor(Xs, dtype=torch.float64, device=ref.device).contiguous()
         F = ref.forces(Xd, t)
-        states.append((Xd, F, ref.mobility(Xd, F)))
+        u = ref.mobility(Xd, F)
+        ref.set_state(Xs, phi)
+        ref.step(1)
+        states.append((Xs, Xd, F, u, ref.get_state()[0] - Xd))
     ref.close()
     sim = B.Simulator(params, S_per_sys, precision="fp32c", graph=True)
     sim.set_state(X, phi)
@@ -121,8 +129,14 @@ def tune(params, S_per_sys, X, phi, gate: float = 5e-7, steps: int = 50, cands=N
         except B.ADError as e:
             tried.append({"launch": c, "error": str(e)})
             continue
+        err = 0.0
+        for Xs, Xd, F, u_ref, dX_ref in states:
+            err = max(err, _relerr(sim.mobility(Xd, F), u_ref))
+            # one step from the same state: the step path (fused or not)
+            sim.set_state(Xs, phi)
+            sim.step(1)
+            err = max(err, _relerr(sim.get_state()[0] - Xd, dX_ref))
         sim.set_state(X, phi)
-        err = max(_relerr(sim.mobility(Xd, F), u_ref) for Xd, F, u_ref in states)
         rec = {"launch": sim.launch, "err": err}
         if err <= gate:
             rec["ms_per_step"] = _step_time(sim, steps)

@@ -39,7 +39,7 @@ class ad_params(C.Structure):
 
 class ad_launch(C.Structure):
     _fields_ = [("ipl", C.c_int32), ("jchunk", C.c_int32), ("wg", C.c_int32), ("wj", C.c_int32),
-                ("posmode", C.c_int32), ("reserved", C.c_int32)]
+                ("posmode", C.c_int32), ("fused", C.c_int32)]
 
 
 AD_POS_HILO, AD_POS_SINGLE = 1, 2
@@ -151,15 +151,15 @@ def ad_bind_workspace(ctx, ws) -> None:
     _check(lib().ad_bind_workspace(ctx, C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()), ctx)
 
 
-def ad_set_launch(ctx, ipl=0, jchunk=0, wg=0, wj=0, posmode=0) -> None:
-    L = ad_launch(int(ipl), int(jchunk), int(wg), int(wj), int(posmode), 0)
+def ad_set_launch(ctx, ipl=0, jchunk=0, wg=0, wj=0, posmode=0, fused=0) -> None:
+    L = ad_launch(int(ipl), int(jchunk), int(wg), int(wj), int(posmode), int(fused))
     _check(lib().ad_set_launch(ctx, C.byref(L)), ctx)
 
 
 def ad_get_launch(ctx) -> dict:
     L = ad_launch()
     _check(lib().ad_get_launch(ctx, C.byref(L)), ctx)
-    return {"ipl": L.ipl, "jchunk": L.jchunk, "wg": L.wg, "wj": L.wj, "posmode": L.posmode}
+    return {"ipl": L.ipl, "jchunk": L.jchunk, "wg": L.wg, "wj": L.wj, "posmode": L.posmode, "fused": L.fused}
 
 
 def ad_set_state(ctx, X, phi, t0=0.0, step0=0, stream=None) -> None:

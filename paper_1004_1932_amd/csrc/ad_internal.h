@@ -166,6 +166,26 @@ hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, h
  * the events, if given, bracket both launches */
 hipError_t launch_dense(const Dev& d, const Epi& e, int mode, int maxNb, hipStream_t s,
                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+/* one system, FP32C, no steric forces: pair sum and epilogue of a stage in
+ * one kernel with every source in LDS (at most FUSED_LDS_MAX bytes, i.e.
+ * 6784 spheres with single-float, 4544 with hi/lo positions) */
+constexpr int FUSED_LDS_MAX = 160 * 1024; /* the kernel has no static LDS */
+/* LDS of the fused kernel after its pair sum: partial sums of 16 waves x 16
+ * targets x 6 floats, 16 x 3 stage positions (double) and a flag */
+constexpr int FUSED_RED_BYTES = 16 * 16 * 6 * 4 + 16 * 3 * 8 + 16;
+/* LDS bytes of the fused kernel for n sources (padded to 64): 36 B per
+ * source with hi/lo positions, 24 B with single-float, and at least the
+ * area its combination step reuses */
+__host__ __device__ inline int fused_lds_bytes(int n, int split) {
+    const int np = (n + 63) & ~63;
+    const int b = np * (split ? 36 : 24);
+    return b > FUSED_RED_BYTES ? b : FUSED_RED_BYTES;
+}
+/* allow the fused kernels FUSED_LDS_MAX bytes of dynamic LDS (host call,
+ * outside any stream capture) */
+hipError_t prepare_fused();
+hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, hipStream_t s,
+                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_epilogue(const Dev& d, const Epi& e, hipStream_t s);
 /* steric forces at stage positions Y, then the next pack (steric path) */
 hipError_t launch_steric_pack(const Dev& d, const Coef& c, int prec, hipStream_t s);

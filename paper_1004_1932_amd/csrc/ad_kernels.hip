@@ -329,6 +329,45 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
 
 /* ------------------------------------------------------------ epilogue */
 
+/* Stage update of one state component o = a N + i from its velocity k:
+ * RK4 keeps the weighted sum of the stage velocities in R and writes X at the
+ * last stage; Heun adds the same noise in both stages. Returns the position
+ * at which the next stage evaluates the velocity. */
+__device__ __forceinline__ double stage_update(const Dev& d, const Epi& e, int o, int i, int a, double k,
+                                               double x, double r, long long step) {
+    const Coef& c = e.c;
+    const int stage = e.stage;
+    double y;
+    if (e.integ == 0) { /* RK4 */
+        if (stage == 0) {
+            d.R[o] = k;
+            y = x + c.h2 * k;
+        } else if (stage == 1) {
+            d.R[o] = r + 2.0 * k;
+            y = x + c.h2 * k;
+        } else if (stage == 2) {
+            d.R[o] = r + 2.0 * k;
+            y = x + c.dt * k;
+        } else {
+            y = x + c.dt6 * (r + k);
+            d.X[o] = y;
+        }
+    } else { /* Heun, with the same noise in both stages */
+        const double nz = c.noise ? c.g * gauss_component(c.seed, i, step, a) : 0.0;
+        if (stage == 0) {
+            d.R[o] = k;
+            y = x + c.dt * k;
+        } else {
+            y = x + c.h2 * (r + k);
+        }
+        if (c.noise) y = y + nz;
+        if (stage == 1) d.X[o] = y;
+    }
+    return y;
+}
+
+constexpr int EPI_MAXP = 16; /* partials loaded per batch */
+
 /* Epilogue of the spheres [i0, i0 + ni) (ni even), run by all blockDim.x
  * threads of a work-group.
  * Phase 1, one thread per sphere component: issue the loads of that
@@ -337,10 +376,8 @@ __global__ void k_forces(Dev d, Coef c, const double* __restrict__ Xa, double st
  * update: R, X to global memory, the next stage position y to LDS.
  * Phase 2, one thread per dumbbell: the next stage's spring forces at y and
  * the next pack (or, with steric forces, y and the spring forces for the
- * steric kernel). `step` selects the (sin, cos) row of the step table;
- * ys and mv are LDS scratch of ni x 3 doubles. */
-constexpr int EPI_MAXP = 16; /* partials loaded per batch */
-
+ * steric kernel). `step` numbers the noise of the Heun integrator; ys and
+ * mv are LDS scratch of ni x 3 doubles. */
 __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long step, double (*ys)[3],
                           double (*mv)[3], int* badf) {
     const int N = d.Ntot;
@@ -405,32 +442,7 @@ __device__ void epi_block(const Dev& d, const Epi& e, int i0, int ni, long long 
             e.u_aos[3 * i + a] = k;
             continue;
         }
-        double y;
-        if (e.integ == 0) { /* RK4 */
-            if (stage == 0) {
-                d.R[o] = k;
-                y = x + c.h2 * k;
-            } else if (stage == 1) {
-                d.R[o] = r + 2.0 * k;
-                y = x + c.h2 * k;
-            } else if (stage == 2) {
-                d.R[o] = r + 2.0 * k;
-                y = x + c.dt * k;
-            } else {
-                y = x + c.dt6 * (r + k);
-                d.X[o] = y;
-            }
-        } else { /* Heun, with the same noise in both stages */
-            const double nz = c.noise ? c.g * gauss_component(c.seed, i, step, a) : 0.0;
-            if (stage == 0) {
-                d.R[o] = k;
-                y = x + c.dt * k;
-            } else {
-                y = x + c.h2 * (r + k);
-            }
-            if (c.noise) y = y + nz;
-            if (stage == 1) d.X[o] = y;
-        }
+        const double y = stage_update(d, e, o, i, a, k, x, r, step);
         ys[sl][a] = y;
         const double dd = y - yold;
         mv[sl][a] = dd * dd;
@@ -726,6 +738,196 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
                 d.part[base + 2 * it.Nb + li] = (double)az[q] + (double)bz[q];
             }
         }
+    }
+}
+
+/* ------------------------------------------------ fused single-system stage */
+
+/* One stage of a single system in one kernel. A work-group of FS_T lanes
+ * holds every source of the system in LDS and FS_I target spheres: lane
+ * (wave w, quarter g, target t) sums target t over the sources
+ * j = 4w + g + 64m, m = 0, 1, ..., in FP32 with a TwoSum into a (hi, lo)
+ * pair every FS_M sources. The 64 pairs of a target are combined in a fixed
+ * order (two shuffles inside the wave, then the 16 waves through LDS), and
+ * the work-group then does its 8 dumbbells' stage update, next spring forces
+ * and next pack, as the epilogue does, so a stage needs no partial sums in
+ * HBM and no second launch. Only the 64-source block that holds the
+ * work-group's own dumbbells needs the self/partner mask. */
+constexpr int FS_T = 1024;
+constexpr int FS_I = 16;
+constexpr int FS_M = 16;
+
+template <int SPLIT, int RPY>
+__global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
+    extern __shared__ float4 fs_lds[];
+    const int N = d.Ntot;
+    const int np = (N + 63) & ~63;
+    /* sources: A = (x, y, z, Fx) [np]; with hi/lo B = (lo.x, lo.y, lo.z, Fy)
+     * [np] and Fz [np], else (Fy, Fz) [np] */
+    float4* sA = fs_lds;
+    float4* sB = fs_lds + np;
+    float* sC = reinterpret_cast<float*>(fs_lds + 2 * np);
+    float2* sF = reinterpret_cast<float2*>(fs_lds + np);
+    const int tid = threadIdx.x;
+    advance_slots(d, e);
+
+    /* inputs of the closing update, loaded first */
+    const int i0 = blockIdx.x * FS_I;
+    const int ni = min(FS_I, N - i0);
+    const long long step = (e.stage == 0) ? d.ctl->slot[0] : d.ctl->slot[1];
+    double st = 0.0, ct = 0.0, u0[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0}, rv[3] = {0.0, 0.0, 0.0};
+    double2 tp = make_double2(0.0, 0.0);
+    if (tid < ni) {
+        for (int a = 0; a < 3; ++a) {
+            const int o = a * N + i0 + tid;
+            u0[a] = d.U0[o];
+            xv[a] = d.X[o];
+            if (e.stage > 0) rv[a] = d.R[o];
+        }
+    }
+    if (tid < ni / 2) {
+        const long long row = step % d.ring;
+        st = d.tab[row * 8 + 2 * e.stage];
+        ct = d.tab[row * 8 + 2 * e.stage + 1];
+        tp = d.phitrig[(i0 >> 1) + tid];
+    }
+
+    /* every source into LDS (padding far away and force-free) */
+    for (int j = tid; j < np; j += FS_T) {
+        float4 A, B;
+        float C;
+        load_tile_entry(d, 0, N, j, A, B, C);
+        sA[j] = A;
+        if (SPLIT) {
+            sB[j] = B;
+            sC[j] = C;
+        } else {
+            sF[j] = make_float2(B.w, C);
+        }
+    }
+    const int w = tid >> 6, l = tid & 63, t = l & 15, g = l >> 4;
+    const int js = 4 * w + g;
+    const int i = i0 + t;
+    float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
+    if (i < N) {
+        const float4 A = d.pA[i];
+        hx = A.x; hy = A.y; hz = A.z;
+        if (SPLIT) {
+            const float4 B = d.pB[i];
+            lx = B.x; ly = B.y; lz = B.z;
+        }
+    }
+    const int di = i >> 1;
+    __syncthreads();
+
+    const float crr = e.c.crr;
+    float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+    auto term = [&](int j, bool masked, float& px, float& py, float& pz) {
+        const float4 Aj = sA[j];
+        float Fy, Fz, qx = 0.f, qy = 0.f, qz = 0.f;
+        if (SPLIT) {
+            const float4 Bj = sB[j];
+            qx = Bj.x; qy = Bj.y; qz = Bj.z;
+            Fy = Bj.w;
+            Fz = sC[j];
+        } else {
+            const float2 f = sF[j];
+            Fy = f.x;
+            Fz = f.y;
+        }
+        float rx, ry, rz;
+        if (SPLIT) {
+            rx = (hx - Aj.x) + (lx - qx);
+            ry = (hy - Aj.y) + (ly - qy);
+            rz = (hz - Aj.z) + (lz - qz);
+        } else {
+            rx = hx - Aj.x;
+            ry = hy - Aj.y;
+            rz = hz - Aj.z;
+        }
+        const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+        float ir = __builtin_amdgcn_rsqf(r2);
+        if (masked && (j >> 1) == di) ir = 0.f;
+        pair_term<RPY>(ir, rx, ry, rz, Aj.w, Fy, Fz, crr, px, py, pz);
+    };
+    const int M = np >> 6;
+    const int ms = i0 >> 6; /* the source block holding this group's dumbbells */
+    for (int m0 = 0; m0 < M; m0 += FS_M) {
+        const int m1 = min(M, m0 + FS_M);
+        float px = 0.f, py = 0.f, pz = 0.f;
+        if (ms >= m0 && ms < m1) {
+            for (int m = m0; m < m1; ++m) term(js + 64 * m, m == ms, px, py, pz);
+        } else if (m1 - m0 == FS_M) {
+#pragma unroll 4
+            for (int m = m0; m < m0 + FS_M; ++m) term(js + 64 * m, false, px, py, pz);
+        } else {
+            for (int m = m0; m < m1; ++m) term(js + 64 * m, false, px, py, pz);
+        }
+        two_sum_acc(ax, bx, px);
+        two_sum_acc(ay, by, py);
+        two_sum_acc(az, bz, pz);
+    }
+
+    /* combine the 64 partial sums of each target in a fixed order: the four
+     * quarters of a wave by shuffles (both partners get the same sum), then
+     * the 16 waves through LDS, in wave order */
+    auto combine = [](float& hi, float& lo, float oh, float ol) {
+        const float s = hi + oh;
+        const float bb = s - hi;
+        const float err = (hi - (s - bb)) + (oh - bb);
+        hi = s;
+        lo = (lo + ol) + err;
+    };
+#pragma unroll
+    for (int sh = 16; sh <= 32; sh *= 2) {
+        const float oax = __shfl_xor(ax, sh), obx = __shfl_xor(bx, sh);
+        const float oay = __shfl_xor(ay, sh), oby = __shfl_xor(by, sh);
+        const float oaz = __shfl_xor(az, sh), obz = __shfl_xor(bz, sh);
+        combine(ax, bx, oax, obx);
+        combine(ay, by, oay, oby);
+        combine(az, bz, oaz, obz);
+    }
+    __syncthreads(); /* the sources are no longer read */
+    float* red = reinterpret_cast<float*>(fs_lds);      /* [16 waves][FS_I][6] */
+    double* ys = reinterpret_cast<double*>(fs_lds) + 16 * FS_I * 3; /* [FS_I][3], after red */
+    int* badf = reinterpret_cast<int*>(ys + FS_I * 3);
+    if (g == 0) {
+        float* r = red + (w * FS_I + t) * 6;
+        r[0] = ax; r[1] = bx; r[2] = ay; r[3] = by; r[4] = az; r[5] = bz;
+    }
+    if (tid == 0) *badf = 0;
+    __syncthreads();
+    if (tid < ni) {
+        float v[6];
+        const float* r0 = red + tid * 6;
+        for (int q = 0; q < 6; ++q) v[q] = r0[q];
+        for (int ww = 1; ww < 16; ++ww) {
+            const float* r = red + (ww * FS_I + tid) * 6;
+            combine(v[0], v[1], r[0], r[1]);
+            combine(v[2], v[3], r[2], r[3]);
+            combine(v[4], v[5], r[4], r[5]);
+        }
+        const Coef& c = e.c;
+        const int ii = i0 + tid;
+        bool bad = false;
+        for (int a = 0; a < 3; ++a) {
+            const double acc = (double)v[2 * a] + (double)v[2 * a + 1];
+            const double k = u0[a] + c.co * acc;
+            if (!isfinite(k)) bad = true;
+            ys[tid * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv[a], rv[a], step);
+        }
+        if (bad) *badf = 1;
+    }
+    __syncthreads();
+    if (tid == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+    if (tid < ni / 2) {
+        double y0[3], y1[3], f0[3], f1[3];
+        for (int a = 0; a < 3; ++a) {
+            y0[a] = ys[(2 * tid) * 3 + a];
+            y1[a] = ys[(2 * tid + 1) * 3 + a];
+        }
+        spring_forces(e.c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+        store_pack(d, e.c, e.prec, i0 + 2 * tid, y0, y1, f0, f1, 1);
     }
 }
 
@@ -1047,6 +1249,39 @@ hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, h
     if (sh.wg == 256 && sh.ipl == 1) return f64_ten<256, 1>(d, e, sh, mode, s, tm);
     if (sh.wg == 256 && sh.ipl == 2) return f64_ten<256, 2>(d, e, sh, mode, s, tm);
     return hipErrorInvalidValue;
+}
+
+template <int SPLIT, int RPY>
+static hipError_t go_fused(const Dev& d, const Epi& e, hipStream_t s, const Timing& tm) {
+    const int lds = fused_lds_bytes(d.Ntot, SPLIT);
+    const dim3 grid((d.Ntot + FS_I - 1) / FS_I);
+    auto kern = k_stage_fused<SPLIT, RPY>;
+    if (tm.start)
+        hipExtLaunchKernelGGL(kern, grid, dim3(FS_T), lds, s, tm.start, tm.stop, 0, d, e);
+    else
+        hipLaunchKernelGGL(kern, grid, dim3(FS_T), lds, s, d, e);
+    return hipGetLastError();
+}
+
+hipError_t prepare_fused() {
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_fused<0, 0>),
+                             reinterpret_cast<const void*>(&k_stage_fused<0, 1>),
+                             reinterpret_cast<const void*>(&k_stage_fused<1, 0>),
+                             reinterpret_cast<const void*>(&k_stage_fused<1, 1>)};
+    for (const void* k : kernels) {
+        hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, FUSED_LDS_MAX);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, hipStream_t s, hipEvent_t ev_start,
+                        hipEvent_t ev_stop) {
+    if (e.prec != PREC_FP32C || d.nsys != 1 || sh.steric || d.Ntot < 2) return hipErrorInvalidValue;
+    if (fused_lds_bytes(d.Ntot, sh.split) > FUSED_LDS_MAX) return hipErrorInvalidValue;
+    const Timing tm{ev_start, ev_stop};
+    if (sh.split) return sh.rpy ? go_fused<1, 1>(d, e, s, tm) : go_fused<1, 0>(d, e, s, tm);
+    return sh.rpy ? go_fused<0, 1>(d, e, s, tm) : go_fused<0, 0>(d, e, s, tm);
 }
 
 hipError_t launch_epilogue(const Dev& d, const Epi& e, hipStream_t s) {

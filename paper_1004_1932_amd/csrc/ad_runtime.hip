@@ -48,6 +48,7 @@ struct ad_ctx {
     std::vector<long long> pbase;
     long long npart = 0;
     std::vector<long long> hbase; /* dense mode: first tensor element per system */
+    bool fused_ready = false;     /* the fused kernels may use all of LDS */
     long long nH = 0;             /* dense mode: tensor elements over all systems */
     int maxNb = 0;
 
@@ -165,7 +166,7 @@ static ad_launch default_launch(const ad_ctx* c) {
 
 static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (is_dense(c)) {
-        if (L.wg != ad::DENSE_ROWS || L.ipl != 1 || L.wj != 1 || L.posmode != 0 || L.reserved != 0)
+        if (L.wg != ad::DENSE_ROWS || L.ipl != 1 || L.wj != 1 || L.posmode != 0 || L.fused != 0)
             return fail(c, AD_EINVAL, "AD_FP64_DENSE takes wg %d, ipl 1, wj 1, posmode 0", ad::DENSE_ROWS);
         if (L.jchunk < 64 || L.jchunk > ad::DENSE_JMAX)
             return fail(c, AD_EINVAL, "AD_FP64_DENSE: launch.jchunk must be in [64, %d]", ad::DENSE_JMAX);
@@ -179,7 +180,14 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (c->p.precision == AD_FP32C && L.posmode != AD_POS_HILO && L.posmode != AD_POS_SINGLE)
         return fail(c, AD_EINVAL, "launch.posmode must be AD_POS_HILO or AD_POS_SINGLE");
     if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
-    if (L.reserved != 0) return fail(c, AD_EINVAL, "launch.reserved must be 0");
+    if (L.fused != 0 && L.fused != 1) return fail(c, AD_EINVAL, "launch.fused must be 0 or 1");
+    if (L.fused) {
+        if (c->p.precision != AD_FP32C || c->nsys != 1 || c->p.steric_k != 0.0 || c->Ntot < 2)
+            return fail(c, AD_EINVAL, "launch.fused needs one system, AD_FP32C and no steric forces");
+        if (ad::fused_lds_bytes(c->Ntot, L.posmode == AD_POS_HILO) > ad::FUSED_LDS_MAX)
+            return fail(c, AD_EINVAL, "launch.fused: %d spheres do not fit in LDS with this position mode",
+                        c->Ntot);
+    }
     return AD_OK;
 }
 
@@ -489,7 +497,12 @@ static ad::Epi epi_of(const ad_ctx* c, int stage, double* u_aos) {
 
 static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mode, hipStream_t st) {
     const ad::Shape sh = shape_of(c);
+    const bool fused = mode == 1 && c->launch.fused;
     if (!c->profile) {
+        if (fused) {
+            HIPCHECK(c, ad::launch_fused(d, e, sh, st));
+            return AD_OK;
+        }
         if (is_dense(c))
             HIPCHECK(c, ad::launch_dense(d, e, mode, c->maxNb, st));
         else
@@ -504,7 +517,9 @@ static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mod
         int rc = profile_flush(c);
         if (rc != AD_OK) return rc;
     }
-    if (is_dense(c))
+    if (fused)
+        HIPCHECK(c, ad::launch_fused(d, e, sh, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
+    else if (is_dense(c))
         HIPCHECK(c, ad::launch_dense(d, e, mode, c->maxNb, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
     else
         HIPCHECK(c, ad::launch_pairs(d, e, sh, mode, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
@@ -521,6 +536,7 @@ static int launch_step_kernels(ad_ctx* c, hipStream_t st) {
         const ad::Epi e = epi_of(c, s, nullptr);
         int rc = launch_pairs_timed(c, d, e, 1, st);
         if (rc != AD_OK) return rc;
+        if (c->launch.fused) continue; /* the fused kernel did the epilogue */
         HIPCHECK(c, ad::launch_epilogue(d, e, st));
         if (steric) HIPCHECK(c, ad::launch_steric_pack(d, c->coef, e.prec, st));
     }
@@ -547,6 +563,11 @@ static int ensure_graph(ad_ctx* c) {
 static int advance(ad_ctx* c, long long nsteps, int record_every, double* centres, double* com, hipStream_t st) {
     if (!c->ws) return fail(c, AD_ESTATE, "no workspace bound");
     if (!c->state) return fail(c, AD_ESTATE, "no state loaded (ad_set_state)");
+    if (c->launch.fused && !c->fused_ready) {
+        /* before any launch or capture of the step */
+        HIPCHECK(c, ad::prepare_fused());
+        c->fused_ready = true;
+    }
     if (nsteps < 0) return fail(c, AD_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return AD_OK;
     const int prec = prec_of(c);

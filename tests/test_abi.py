@@ -97,7 +97,7 @@ def test_launch_shapes_and_workspace_size():
         P.ad_set_launch(ctx, ipl=4, jchunk=4096, wg=256)
         one_chunk = P.ad_workspace_size(ctx)
         P.ad_set_launch(ctx, ipl=4, jchunk=64, wg=256)
-        assert P.ad_get_launch(ctx) == {"ipl": 4, "jchunk": 64, "wg": 256, "wj": 4, "posmode": 1}
+        assert P.ad_get_launch(ctx) == {"ipl": 4, "jchunk": 64, "wg": 256, "wj": 4, "posmode": 1, "fused": 0}
         # 64 j-chunks hold 64 partial sums per sphere instead of one
         assert P.ad_workspace_size(ctx) - one_chunk >= 63 * 3 * 4096 * 8
         P.ad_set_launch(ctx, ipl=2, jchunk=512, wg=256, wj=4, posmode=2)
@@ -143,6 +143,36 @@ def test_dense_mode_launch_rules_and_workspace():
     with pytest.raises(P.ADError):
         P.ad_create(P.make_params(Params(), "fp64_dense"), [12000])
     P.ad_destroy(P.ad_create(P.make_params(Params(), "fp64_dense"), [8000]))
+
+
+def test_fused_stage_launch_rules():
+    """launch.fused: one system, AD_FP32C, no steric forces, every source in
+    LDS (6784 spheres with single-float positions, 4544 with hi/lo)."""
+    ctx = P.ad_create(P.make_params(Params(), "fp32c"), [2048])
+    try:
+        P.ad_set_launch(ctx, fused=1, posmode=2)
+        assert P.ad_get_launch(ctx)["fused"] == 1
+        P.ad_set_launch(ctx, fused=1, posmode=1)
+        with pytest.raises(P.ADError):
+            P.ad_set_launch(ctx, fused=2)
+    finally:
+        P.ad_destroy(ctx)
+    ok = P.ad_create(P.make_params(Params(), "fp32c"), [3392])      # 6784 spheres
+    try:
+        P.ad_set_launch(ok, fused=1, posmode=2)
+        with pytest.raises(P.ADError):
+            P.ad_set_launch(ok, fused=1, posmode=1)                    # hi/lo: 4544 at most
+    finally:
+        P.ad_destroy(ok)
+    for prec, sizes, params in (("fp64", [64], Params()), ("fp64_tiled", [64], Params()),
+                                ("fp32c", [64, 32], Params()), ("fp32c", [3400], Params()),
+                                ("fp32c", [64], Params(steric_k=100.0, steric_r=2.0))):
+        ctx = P.ad_create(P.make_params(params, prec), sizes)
+        try:
+            with pytest.raises(P.ADError):
+                P.ad_set_launch(ctx, fused=1, posmode=2 if prec == "fp32c" else 0)
+        finally:
+            P.ad_destroy(ctx)
 
 
 def test_destroy_null_is_noop():

@@ -213,8 +213,13 @@ def _oracle_run_cached(oracle, name, nsteps, rec):
     return _ORACLE_RUNS[key]
 
 
+FUSED_SINGLE = {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 2, "fused": 1}
+FUSED_HILO = {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 1, "fused": 1}
+
+
 @pytest.mark.parametrize("name,nsteps,launch", [("n512", 10_000, None), ("n512", 10_000, "tuned"),
-                                                ("n4096", 1_000, "tuned")])
+                                                ("n4096", 1_000, "tuned"), ("n512", 10_000, FUSED_HILO),
+                                                ("n4096", 1_000, FUSED_SINGLE)])
 def test_trajectory_fp32c_drift(oracle, name, nsteps, launch):
     """FP32C trajectories against the FP64 oracle: dumbbell-centre
     displacement relative drift <= 1e-4 at every record, and velocity error
@@ -580,6 +585,64 @@ def test_heun_noise_matches_oracle(oracle, precision, tol):
     err = np.abs(Xg - Xo).max()
     say(f"  noise {precision} max position error {err:.2e}")
     assert err <= tol
+
+
+# ---------------------------------------------------------------- fused stage kernel
+
+@pytest.mark.parametrize("launch", [FUSED_SINGLE, FUSED_HILO])
+@pytest.mark.parametrize("integrator,tensor", [("rk4", "oseen"), ("heun", "oseen"), ("rk4", "rpy")])
+def test_fused_stage_matches_oracle(oracle, launch, integrator, tensor):
+    """Pair sum and stage update in one kernel per stage, on systems that are
+    not a multiple of the 16-sphere target block or the 64-sphere source
+    block: positions after 300 steps within 1e-6 of the oracle's, relative to
+    the displacement, and within rounding of the two-kernel path."""
+    _torch()
+    for S, side in ((5, 20.0), (57, 60.0), (300, 120.0)):
+        sus = make_single(S, side, 31)
+        say(f"fused {launch['posmode']} {integrator} {tensor} S={S}")
+        s = P.Simulator(sus.params, [S], precision="fp32c", integrator=integrator, tensor=tensor,
+                        launch=launch, graph=True)
+        s.set_state(sus.X, sus.phi)
+        _, _, code = s.run(300, 0)
+        assert code == 0
+        Xf = s.get_state()[0].cpu().numpy()
+        plain = dict(launch, fused=0)
+        s2 = P.Simulator(sus.params, [S], precision="fp32c", integrator=integrator, tensor=tensor,
+                         launch=plain, graph=True)
+        s2.set_state(sus.X, sus.phi)
+        s2.run(300, 0)
+        Xu = s2.get_state()[0].cpu().numpy()
+        Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 300, integrator=1 if integrator == "heun" else 0,
+                                 tensor=1 if tensor == "rpy" else 0)
+        e_orc = relerr(Xf - sus.X, Xo - sus.X)
+        e_two = relerr(Xf - sus.X, Xu - sus.X)
+        say(f"  vs oracle {e_orc:.2e}, vs two-kernel path {e_two:.2e}")
+        assert e_orc <= 1e-6 and e_two <= 1e-6
+
+
+def test_fused_stage_deterministic_resumable_and_noise(oracle):
+    """Fused stages: two runs give the same bits, split step calls equal one
+    call, and the Heun noise follows the oracle's Brownian trajectory."""
+    _torch()
+    sus = make_preset("n512")
+    out = []
+    for calls in ((400,), (400,), (150, 250)):
+        s = P.Simulator(sus.params, [sus.S], precision="fp32c", launch=FUSED_SINGLE, graph=True)
+        s.set_state(sus.X, sus.phi)
+        for n in calls:
+            _, _, code = s.run(n, 0)
+            assert code == 0
+        out.append(s.get_state()[0].cpu().numpy())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    sus = make_single(20, 40.0, 5)
+    kT, seed = 0.01, 77
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c", integrator="heun", kT=kT, seed=seed,
+                    launch=FUSED_HILO, graph=True)
+    s.set_state(sus.X, sus.phi)
+    _, _, code = s.run(300, 0)
+    assert code == 0
+    Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 300, integrator=1, kT=kT, seed=seed)
+    assert np.abs(s.get_state()[0].cpu().numpy() - Xo).max() <= 1e-7
 
 
 def test_heun_noise_deterministic_and_resumable():
