@@ -171,8 +171,9 @@ hipError_t launch_dense(const Dev& d, const Epi& e, int mode, int maxNb, hipStre
  * 6784 spheres with single-float, 4544 with hi/lo positions) */
 constexpr int FUSED_LDS_MAX = 160 * 1024; /* the kernel has no static LDS */
 /* LDS of the fused kernel after its pair sum: partial sums of 16 waves x 16
- * targets x 6 floats, 16 x 3 stage positions (double) and a flag */
-constexpr int FUSED_RED_BYTES = 16 * 16 * 6 * 4 + 16 * 3 * 8 + 16;
+ * targets x 6 floats, 16 x 3 stage positions and 16 x 3 spring forces
+ * (double) and a flag */
+constexpr int FUSED_RED_BYTES = 16 * 16 * 6 * 4 + 2 * 16 * 3 * 8 + 16;
 /* LDS bytes of the fused kernel for n sources (padded to 64): 36 B per
  * source with hi/lo positions, 24 B with single-float, and at least the
  * area its combination step reuses */

@@ -155,42 +155,37 @@ __device__ double gauss_component(unsigned long long seed, int i, long long n, i
 /* Write the pair-kernel pack and the self (+partner) velocity u0 of the two
  * spheres of one dumbbell at positions y0, y1 with forces f0, f1; into the
  * next-stage pack buffers when nxt != 0. */
+/* FP32C pack of sphere i at stage position y with spring force f, its
+ * dumbbell partner at yp with force fp: u0 = self term plus the partner's
+ * term in FP64 (the pair kernels skip the partner), then the FP32 hi/lo
+ * position and force. */
+__device__ __forceinline__ void store_pack_sphere(const Dev& d, const Coef& c, int i, const double y[3],
+                                                  const double yp[3], const double f[3], const double fp[3],
+                                                  int nxt) {
+    const int N = d.Ntot;
+    const double r[3] = {y[0] - yp[0], y[1] - yp[1], y[2] - yp[2]};
+    double t[3], q[3];
+    oseen_term64(r, fp, t);
+    if (c.rpy) rpy_term64(r, fp, q);
+    for (int a = 0; a < 3; ++a) {
+        double u = c.cs * f[a] + c.co * t[a];
+        if (c.rpy) u = u + c.cr * q[a];
+        d.U0[a * N + i] = u;
+    }
+    float h[3], l[3];
+    for (int a = 0; a < 3; ++a) split_f32(y[a], h[a], l[a]);
+    (nxt ? d.pA2 : d.pA)[i] = make_float4(h[0], h[1], h[2], (float)f[0]);
+    (nxt ? d.pB2 : d.pB)[i] = make_float4(l[0], l[1], l[2], (float)f[1]);
+    (nxt ? d.pC2 : d.pC)[i] = (float)f[2];
+}
+
 __device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const double y0[3],
                            const double y1[3], const double f0[3], const double f1[3], int nxt) {
     const int N = d.Ntot;
     const int i1 = i0 + 1;
     if (prec == PREC_FP32C) {
-        /* self term and dumbbell-partner term in FP64; the pair kernel skips
-         * the partner */
-        double r[3] = {y0[0] - y1[0], y0[1] - y1[1], y0[2] - y1[2]};
-        double t0[3], t1[3];
-        oseen_term64(r, f1, t0);
-        double rm[3] = {y1[0] - y0[0], y1[1] - y0[1], y1[2] - y0[2]};
-        oseen_term64(rm, f0, t1);
-        for (int a = 0; a < 3; ++a) {
-            d.U0[a * N + i0] = c.cs * f0[a] + c.co * t0[a];
-            d.U0[a * N + i1] = c.cs * f1[a] + c.co * t1[a];
-        }
-        if (c.rpy) {
-            rpy_term64(r, f1, t0);
-            rpy_term64(rm, f0, t1);
-            for (int a = 0; a < 3; ++a) {
-                d.U0[a * N + i0] = d.U0[a * N + i0] + c.cr * t0[a];
-                d.U0[a * N + i1] = d.U0[a * N + i1] + c.cr * t1[a];
-            }
-        }
-        float4* pA = nxt ? d.pA2 : d.pA;
-        float4* pB = nxt ? d.pB2 : d.pB;
-        float* pC = nxt ? d.pC2 : d.pC;
-        float h[3], l[3];
-        for (int a = 0; a < 3; ++a) split_f32(y0[a], h[a], l[a]);
-        pA[i0] = make_float4(h[0], h[1], h[2], (float)f0[0]);
-        pB[i0] = make_float4(l[0], l[1], l[2], (float)f0[1]);
-        pC[i0] = (float)f0[2];
-        for (int a = 0; a < 3; ++a) split_f32(y1[a], h[a], l[a]);
-        pA[i1] = make_float4(h[0], h[1], h[2], (float)f1[0]);
-        pB[i1] = make_float4(l[0], l[1], l[2], (float)f1[1]);
-        pC[i1] = (float)f1[2];
+        store_pack_sphere(d, c, i0, y0, y1, f0, f1, nxt);
+        store_pack_sphere(d, c, i1, y1, y0, f1, f0, nxt);
     } else {
         for (int a = 0; a < 3; ++a) {
             d.U0[a * N + i0] = c.cs * f0[a];
@@ -771,19 +766,19 @@ __global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
     const int tid = threadIdx.x;
     advance_slots(d, e);
 
-    /* inputs of the closing update, loaded first */
+    /* inputs of the closing update, loaded first: lane 3t + a owns
+     * component a of target i0 + t, lane q < ni/2 the forces of dumbbell q */
     const int i0 = blockIdx.x * FS_I;
     const int ni = min(FS_I, N - i0);
     const long long step = (e.stage == 0) ? d.ctl->slot[0] : d.ctl->slot[1];
-    double st = 0.0, ct = 0.0, u0[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0}, rv[3] = {0.0, 0.0, 0.0};
+    double st = 0.0, ct = 0.0, u0 = 0.0, xv = 0.0, rv = 0.0;
     double2 tp = make_double2(0.0, 0.0);
-    if (tid < ni) {
-        for (int a = 0; a < 3; ++a) {
-            const int o = a * N + i0 + tid;
-            u0[a] = d.U0[o];
-            xv[a] = d.X[o];
-            if (e.stage > 0) rv[a] = d.R[o];
-        }
+    if (tid < 3 * ni) {
+        const int tt = tid / 3, a = tid - 3 * tt;
+        const int o = a * N + i0 + tt;
+        u0 = d.U0[o];
+        xv = d.X[o];
+        if (e.stage > 0) rv = d.R[o];
     }
     if (tid < ni / 2) {
         const long long row = step % d.ring;
@@ -888,46 +883,47 @@ __global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
         combine(az, bz, oaz, obz);
     }
     __syncthreads(); /* the sources are no longer read */
-    float* red = reinterpret_cast<float*>(fs_lds);      /* [16 waves][FS_I][6] */
-    double* ys = reinterpret_cast<double*>(fs_lds) + 16 * FS_I * 3; /* [FS_I][3], after red */
-    int* badf = reinterpret_cast<int*>(ys + FS_I * 3);
+    float* red = reinterpret_cast<float*>(fs_lds);                  /* [16 waves][FS_I][6] */
+    double* ys = reinterpret_cast<double*>(fs_lds) + 16 * FS_I * 3; /* [FS_I][3] stage positions */
+    double* fsp = ys + FS_I * 3;                                    /* [FS_I][3] spring forces */
+    int* badf = reinterpret_cast<int*>(fsp + FS_I * 3);
     if (g == 0) {
         float* r = red + (w * FS_I + t) * 6;
         r[0] = ax; r[1] = bx; r[2] = ay; r[3] = by; r[4] = az; r[5] = bz;
     }
     if (tid == 0) *badf = 0;
     __syncthreads();
-    if (tid < ni) {
-        float v[6];
-        const float* r0 = red + tid * 6;
-        for (int q = 0; q < 6; ++q) v[q] = r0[q];
+    if (tid < 3 * ni) {
+        /* component a of target tt: the 16 waves' sums in wave order, then
+         * the stage update */
+        const int tt = tid / 3, a = tid - 3 * tt;
+        const float* r0 = red + tt * 6 + 2 * a;
+        float hi = r0[0], lo = r0[1];
         for (int ww = 1; ww < 16; ++ww) {
-            const float* r = red + (ww * FS_I + tid) * 6;
-            combine(v[0], v[1], r[0], r[1]);
-            combine(v[2], v[3], r[2], r[3]);
-            combine(v[4], v[5], r[4], r[5]);
+            const float* r = red + (ww * FS_I + tt) * 6 + 2 * a;
+            combine(hi, lo, r[0], r[1]);
         }
-        const Coef& c = e.c;
-        const int ii = i0 + tid;
-        bool bad = false;
+        const int ii = i0 + tt;
+        const double k = u0 + e.c.co * ((double)hi + (double)lo);
+        if (!isfinite(k)) *badf = 1;
+        ys[tt * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv, rv, step);
+    }
+    __syncthreads();
+    if (tid < ni / 2) {
+        /* spring forces of dumbbell tid at the stage positions */
+        double f0[3], f1[3];
+        spring_forces(e.c, ys + (2 * tid) * 3, ys + (2 * tid + 1) * 3, tp.x, tp.y, st, ct, f0, f1);
         for (int a = 0; a < 3; ++a) {
-            const double acc = (double)v[2 * a] + (double)v[2 * a + 1];
-            const double k = u0[a] + c.co * acc;
-            if (!isfinite(k)) bad = true;
-            ys[tid * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv[a], rv[a], step);
+            fsp[(2 * tid) * 3 + a] = f0[a];
+            fsp[(2 * tid + 1) * 3 + a] = f1[a];
         }
-        if (bad) *badf = 1;
     }
     __syncthreads();
     if (tid == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
-    if (tid < ni / 2) {
-        double y0[3], y1[3], f0[3], f1[3];
-        for (int a = 0; a < 3; ++a) {
-            y0[a] = ys[(2 * tid) * 3 + a];
-            y1[a] = ys[(2 * tid + 1) * 3 + a];
-        }
-        spring_forces(e.c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
-        store_pack(d, e.c, e.prec, i0 + 2 * tid, y0, y1, f0, f1, 1);
+    if (tid < ni) {
+        /* one lane per sphere: partner term and the next pack */
+        const int p = tid ^ 1;
+        store_pack_sphere(d, e.c, i0 + tid, ys + tid * 3, ys + p * 3, fsp + tid * 3, fsp + p * 3, 1);
     }
 }
 
