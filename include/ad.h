@@ -108,11 +108,11 @@ typedef struct ad_launch {
     int32_t wg;       /* work-group size: 64 or 256 (AD_FP64_DENSE: 256 tensor rows) */
     int32_t wj;       /* waves splitting each j-tile: 1, or 4 with wg = 256 (AD_FP32C) */
     int32_t posmode;  /* AD_FP32C positions: 1 = hi/lo float pair, 2 = single float */
-    int32_t fused;    /* 1: each step stage is one kernel that holds every source in LDS and
-                         also does the stage update (one system, AD_FP32C, no steric forces,
-                         at most 6784 spheres with single-float or 4544 with hi/lo positions;
-                         ad_mobility_apply still uses the other fields); 0: pair kernel and
-                         epilogue as two kernels */
+    int32_t fused;    /* 1: each step stage is one kernel whose work-groups hold their
+                         system's sources in LDS and also do the stage update (AD_FP32C, no
+                         steric forces, at most 6784 spheres per system with single-float or
+                         4544 with hi/lo positions; ad_mobility_apply still uses the other
+                         fields); 0: pair kernel and epilogue as two kernels */
 } ad_launch;
 
 #define AD_POS_HILO 1

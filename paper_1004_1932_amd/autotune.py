@@ -60,9 +60,12 @@ def candidates(N: int, ensemble: bool):
             out.append(dict(wg=256, wj=1, ipl=ipl, jchunk=256, posmode=posmode))
             for jc in (128, 256):
                 out.append(dict(wg=64, wj=1, ipl=ipl, jchunk=jc, posmode=posmode))
-    if not ensemble:
-        # one kernel per stage with every source in LDS (refused where it does not apply)
-        for posmode in (B.AD_POS_HILO, B.AD_POS_SINGLE):
+    # one kernel per stage with every source of a system in LDS (refused where
+    # it does not apply); the other fields serve ad_mobility_apply
+    for posmode in (B.AD_POS_HILO, B.AD_POS_SINGLE):
+        if ensemble:
+            out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=1))
+        else:
             out.append(dict(wg=256, wj=4, ipl=1, jchunk=256, posmode=posmode, fused=1))
     uniq = []
     for c in out:

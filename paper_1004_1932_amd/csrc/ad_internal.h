@@ -93,6 +93,8 @@ struct Dev {
     double2* pD2;
     double* part;       /* partial sums */
     double* H;          /* dense mode: per system the 3Nb x 3Nb pair tensor, column-major */
+    const Item* fitems; /* fused stages of an ensemble: (system, 16-target block) items */
+    int nfitems;        /* 0: one system, blocks in order */
     const long long* sys_hbase; /* [nsys] dense mode: first element of the system's tensor */
     const double* tab;  /* [ring][8] (sin, cos) of omega*t per epilogue stage */
     int ring;           /* entries in tab */
@@ -166,26 +168,27 @@ hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, h
  * the events, if given, bracket both launches */
 hipError_t launch_dense(const Dev& d, const Epi& e, int mode, int maxNb, hipStream_t s,
                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
-/* one system, FP32C, no steric forces: pair sum and epilogue of a stage in
- * one kernel with every source in LDS (at most FUSED_LDS_MAX bytes, i.e.
- * 6784 spheres with single-float, 4544 with hi/lo positions) */
+/* FP32C without steric forces: pair sum and epilogue of a stage in one
+ * kernel, every source of a work-group's system in LDS (at most
+ * FUSED_LDS_MAX bytes: 6784 spheres per system with single-float, 4544 with
+ * hi/lo positions); 16 waves per work-group for one system, 4 waves and the
+ * work list fitems for an ensemble */
 constexpr int FUSED_LDS_MAX = 160 * 1024; /* the kernel has no static LDS */
-/* LDS of the fused kernel after its pair sum: partial sums of 16 waves x 16
- * targets x 6 floats, 16 x 3 stage positions and 16 x 3 spring forces
- * (double) and a flag */
-constexpr int FUSED_RED_BYTES = 16 * 16 * 6 * 4 + 2 * 16 * 3 * 8 + 16;
-/* LDS bytes of the fused kernel for n sources (padded to 64): 36 B per
- * source with hi/lo positions, 24 B with single-float, and at least the
- * area its combination step reuses */
-__host__ __device__ inline int fused_lds_bytes(int n, int split) {
-    const int np = (n + 63) & ~63;
+/* LDS bytes of a fused work-group for a system of n spheres: the sources,
+ * padded to the 4 nw source splits (36 B each with hi/lo positions, 24 B
+ * with single-float), or the combination area it reuses (nw waves x 16
+ * targets x 6 floats, 16 x 3 positions and 16 x 3 forces, a flag) if larger */
+__host__ __device__ inline int fused_lds_bytes(int n, int split, int nw) {
+    const int js = 4 * nw;
+    const int np = (n + js - 1) / js * js;
     const int b = np * (split ? 36 : 24);
-    return b > FUSED_RED_BYTES ? b : FUSED_RED_BYTES;
+    const int red = nw * 16 * 6 * 4 + 2 * 16 * 3 * 8 + 16;
+    return b > red ? b : red;
 }
 /* allow the fused kernels FUSED_LDS_MAX bytes of dynamic LDS (host call,
  * outside any stream capture) */
 hipError_t prepare_fused();
-hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, hipStream_t s,
+hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, int maxNb, hipStream_t s,
                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_epilogue(const Dev& d, const Epi& e, hipStream_t s);
 /* steric forces at stage positions Y, then the next pack (steric path) */

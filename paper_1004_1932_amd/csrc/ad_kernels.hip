@@ -736,40 +736,56 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
     }
 }
 
-/* ------------------------------------------------ fused single-system stage */
+/* ------------------------------------------------------- fused stage */
 
-/* One stage of a single system in one kernel. A work-group of FS_T lanes
- * holds every source of the system in LDS and FS_I target spheres: lane
+/* One stage in one kernel. A work-group of NW waves owns FS_I = 16 target
+ * spheres of one system and holds all of that system's sources in LDS: lane
  * (wave w, quarter g, target t) sums target t over the sources
- * j = 4w + g + 64m, m = 0, 1, ..., in FP32 with a TwoSum into a (hi, lo)
- * pair every FS_M sources. The 64 pairs of a target are combined in a fixed
- * order (two shuffles inside the wave, then the 16 waves through LDS), and
- * the work-group then does its 8 dumbbells' stage update, next spring forces
- * and next pack, as the epilogue does, so a stage needs no partial sums in
- * HBM and no second launch. Only the 64-source block that holds the
- * work-group's own dumbbells needs the self/partner mask. */
-constexpr int FS_T = 1024;
+ * j = JS m + 4w + g (JS = 4 NW source splits, m = 0, 1, ...) in FP32, with a
+ * TwoSum into a (hi, lo) pair every FS_M sources. The JS partial sums of a
+ * target are combined in a fixed order (two shuffles inside the wave, then
+ * the NW waves through LDS, in wave order), and the work-group then does the
+ * stage update, next spring forces and next pack of its 8 dumbbells, as the
+ * epilogue does: a stage needs no partial sums in HBM and no second launch.
+ * Only the JS-source block that holds the work-group's own dumbbells needs
+ * the self/partner mask. A single system uses NW = 16 and target blocks in
+ * order; an ensemble NW = 4 and a work list of (system, target block),
+ * longest system first. */
 constexpr int FS_I = 16;
 constexpr int FS_M = 16;
 
-template <int SPLIT, int RPY>
-__global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
+template <int SPLIT, int RPY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
+    constexpr int T = 64 * NW; /* lanes */
+    constexpr int JS = 4 * NW; /* source splits per target */
     extern __shared__ float4 fs_lds[];
     const int N = d.Ntot;
-    const int np = (N + 63) & ~63;
+    const int tid = threadIdx.x;
+    advance_slots(d, e);
+
+    /* the work-group's targets [i0, i0 + ni) in the system [off, off + Nb) */
+    int i0, ni, off, Nb;
+    if (d.nfitems == 0) {
+        i0 = blockIdx.x * FS_I;
+        off = 0;
+        Nb = N;
+    } else {
+        const Item it = d.fitems[blockIdx.x];
+        i0 = it.i0;
+        off = it.ioff;
+        Nb = it.Nb;
+    }
+    ni = min(FS_I, off + Nb - i0);
+    const int np = (Nb + JS - 1) / JS * JS;
     /* sources: A = (x, y, z, Fx) [np]; with hi/lo B = (lo.x, lo.y, lo.z, Fy)
      * [np] and Fz [np], else (Fy, Fz) [np] */
     float4* sA = fs_lds;
     float4* sB = fs_lds + np;
     float* sC = reinterpret_cast<float*>(fs_lds + 2 * np);
     float2* sF = reinterpret_cast<float2*>(fs_lds + np);
-    const int tid = threadIdx.x;
-    advance_slots(d, e);
 
     /* inputs of the closing update, loaded first: lane 3t + a owns
      * component a of target i0 + t, lane q < ni/2 the forces of dumbbell q */
-    const int i0 = blockIdx.x * FS_I;
-    const int ni = min(FS_I, N - i0);
     const long long step = (e.stage == 0) ? d.ctl->slot[0] : d.ctl->slot[1];
     double st = 0.0, ct = 0.0, u0 = 0.0, xv = 0.0, rv = 0.0;
     double2 tp = make_double2(0.0, 0.0);
@@ -787,11 +803,11 @@ __global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
         tp = d.phitrig[(i0 >> 1) + tid];
     }
 
-    /* every source into LDS (padding far away and force-free) */
-    for (int j = tid; j < np; j += FS_T) {
+    /* the system's sources into LDS (padding far away and force-free) */
+    for (int j = tid; j < np; j += T) {
         float4 A, B;
         float C;
-        load_tile_entry(d, 0, N, j, A, B, C);
+        load_tile_entry(d, off, off + Nb, j, A, B, C);
         sA[j] = A;
         if (SPLIT) {
             sB[j] = B;
@@ -804,7 +820,7 @@ __global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
     const int js = 4 * w + g;
     const int i = i0 + t;
     float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
-    if (i < N) {
+    if (t < ni) {
         const float4 A = d.pA[i];
         hx = A.x; hy = A.y; hz = A.z;
         if (SPLIT) {
@@ -812,7 +828,7 @@ __global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
             lx = B.x; ly = B.y; lz = B.z;
         }
     }
-    const int di = i >> 1;
+    const int di = (i - off) >> 1; /* local dumbbell (off is even) */
     __syncthreads();
 
     const float crr = e.c.crr;
@@ -845,27 +861,27 @@ __global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
         if (masked && (j >> 1) == di) ir = 0.f;
         pair_term<RPY>(ir, rx, ry, rz, Aj.w, Fy, Fz, crr, px, py, pz);
     };
-    const int M = np >> 6;
-    const int ms = i0 >> 6; /* the source block holding this group's dumbbells */
+    const int M = np / JS;
+    const int ms = (i0 - off) / JS; /* the source block holding this group's dumbbells */
     for (int m0 = 0; m0 < M; m0 += FS_M) {
         const int m1 = min(M, m0 + FS_M);
         float px = 0.f, py = 0.f, pz = 0.f;
         if (ms >= m0 && ms < m1) {
-            for (int m = m0; m < m1; ++m) term(js + 64 * m, m == ms, px, py, pz);
+            for (int m = m0; m < m1; ++m) term(js + JS * m, m == ms, px, py, pz);
         } else if (m1 - m0 == FS_M) {
 #pragma unroll 4
-            for (int m = m0; m < m0 + FS_M; ++m) term(js + 64 * m, false, px, py, pz);
+            for (int m = m0; m < m0 + FS_M; ++m) term(js + JS * m, false, px, py, pz);
         } else {
-            for (int m = m0; m < m1; ++m) term(js + 64 * m, false, px, py, pz);
+            for (int m = m0; m < m1; ++m) term(js + JS * m, false, px, py, pz);
         }
         two_sum_acc(ax, bx, px);
         two_sum_acc(ay, by, py);
         two_sum_acc(az, bz, pz);
     }
 
-    /* combine the 64 partial sums of each target in a fixed order: the four
+    /* combine the JS partial sums of each target in a fixed order: the four
      * quarters of a wave by shuffles (both partners get the same sum), then
-     * the 16 waves through LDS, in wave order */
+     * the NW waves through LDS, in wave order */
     auto combine = [](float& hi, float& lo, float oh, float ol) {
         const float s = hi + oh;
         const float bb = s - hi;
@@ -883,8 +899,8 @@ __global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
         combine(az, bz, oaz, obz);
     }
     __syncthreads(); /* the sources are no longer read */
-    float* red = reinterpret_cast<float*>(fs_lds);                  /* [16 waves][FS_I][6] */
-    double* ys = reinterpret_cast<double*>(fs_lds) + 16 * FS_I * 3; /* [FS_I][3] stage positions */
+    float* red = reinterpret_cast<float*>(fs_lds);                  /* [NW waves][FS_I][6] */
+    double* ys = reinterpret_cast<double*>(fs_lds) + NW * FS_I * 3; /* [FS_I][3] stage positions */
     double* fsp = ys + FS_I * 3;                                    /* [FS_I][3] spring forces */
     int* badf = reinterpret_cast<int*>(fsp + FS_I * 3);
     if (g == 0) {
@@ -894,12 +910,12 @@ __global__ __launch_bounds__(FS_T) void k_stage_fused(Dev d, Epi e) {
     if (tid == 0) *badf = 0;
     __syncthreads();
     if (tid < 3 * ni) {
-        /* component a of target tt: the 16 waves' sums in wave order, then
-         * the stage update */
+        /* component a of target tt: the waves' sums in wave order, then the
+         * stage update */
         const int tt = tid / 3, a = tid - 3 * tt;
         const float* r0 = red + tt * 6 + 2 * a;
         float hi = r0[0], lo = r0[1];
-        for (int ww = 1; ww < 16; ++ww) {
+        for (int ww = 1; ww < NW; ++ww) {
             const float* r = red + (ww * FS_I + tt) * 6 + 2 * a;
             combine(hi, lo, r[0], r[1]);
         }
@@ -1247,23 +1263,27 @@ hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, h
     return hipErrorInvalidValue;
 }
 
-template <int SPLIT, int RPY>
-static hipError_t go_fused(const Dev& d, const Epi& e, hipStream_t s, const Timing& tm) {
-    const int lds = fused_lds_bytes(d.Ntot, SPLIT);
-    const dim3 grid((d.Ntot + FS_I - 1) / FS_I);
-    auto kern = k_stage_fused<SPLIT, RPY>;
+template <int SPLIT, int RPY, int NW>
+static hipError_t go_fused(const Dev& d, const Epi& e, int maxNb, hipStream_t s, const Timing& tm) {
+    const int lds = fused_lds_bytes(maxNb, SPLIT, NW);
+    const dim3 grid(d.nfitems ? d.nfitems : (d.Ntot + FS_I - 1) / FS_I);
+    auto kern = k_stage_fused<SPLIT, RPY, NW>;
     if (tm.start)
-        hipExtLaunchKernelGGL(kern, grid, dim3(FS_T), lds, s, tm.start, tm.stop, 0, d, e);
+        hipExtLaunchKernelGGL(kern, grid, dim3(64 * NW), lds, s, tm.start, tm.stop, 0, d, e);
     else
-        hipLaunchKernelGGL(kern, grid, dim3(FS_T), lds, s, d, e);
+        hipLaunchKernelGGL(kern, grid, dim3(64 * NW), lds, s, d, e);
     return hipGetLastError();
 }
 
 hipError_t prepare_fused() {
-    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_fused<0, 0>),
-                             reinterpret_cast<const void*>(&k_stage_fused<0, 1>),
-                             reinterpret_cast<const void*>(&k_stage_fused<1, 0>),
-                             reinterpret_cast<const void*>(&k_stage_fused<1, 1>)};
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_fused<0, 0, 16>),
+                             reinterpret_cast<const void*>(&k_stage_fused<0, 1, 16>),
+                             reinterpret_cast<const void*>(&k_stage_fused<1, 0, 16>),
+                             reinterpret_cast<const void*>(&k_stage_fused<1, 1, 16>),
+                             reinterpret_cast<const void*>(&k_stage_fused<0, 0, 4>),
+                             reinterpret_cast<const void*>(&k_stage_fused<0, 1, 4>),
+                             reinterpret_cast<const void*>(&k_stage_fused<1, 0, 4>),
+                             reinterpret_cast<const void*>(&k_stage_fused<1, 1, 4>)};
     for (const void* k : kernels) {
         hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, FUSED_LDS_MAX);
         if (err != hipSuccess) return err;
@@ -1271,13 +1291,19 @@ hipError_t prepare_fused() {
     return hipSuccess;
 }
 
-hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, hipStream_t s, hipEvent_t ev_start,
-                        hipEvent_t ev_stop) {
-    if (e.prec != PREC_FP32C || d.nsys != 1 || sh.steric || d.Ntot < 2) return hipErrorInvalidValue;
-    if (fused_lds_bytes(d.Ntot, sh.split) > FUSED_LDS_MAX) return hipErrorInvalidValue;
+hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, int maxNb, hipStream_t s,
+                        hipEvent_t ev_start, hipEvent_t ev_stop) {
+    if (e.prec != PREC_FP32C || sh.steric || maxNb < 2) return hipErrorInvalidValue;
+    if ((d.nsys > 1) != (d.nfitems > 0)) return hipErrorInvalidValue;
+    const int nw = d.nsys > 1 ? 4 : 16;
+    if (fused_lds_bytes(maxNb, sh.split, nw) > FUSED_LDS_MAX) return hipErrorInvalidValue;
     const Timing tm{ev_start, ev_stop};
-    if (sh.split) return sh.rpy ? go_fused<1, 1>(d, e, s, tm) : go_fused<1, 0>(d, e, s, tm);
-    return sh.rpy ? go_fused<0, 1>(d, e, s, tm) : go_fused<0, 0>(d, e, s, tm);
+    if (nw == 16) {
+        if (sh.split) return sh.rpy ? go_fused<1, 1, 16>(d, e, maxNb, s, tm) : go_fused<1, 0, 16>(d, e, maxNb, s, tm);
+        return sh.rpy ? go_fused<0, 1, 16>(d, e, maxNb, s, tm) : go_fused<0, 0, 16>(d, e, maxNb, s, tm);
+    }
+    if (sh.split) return sh.rpy ? go_fused<1, 1, 4>(d, e, maxNb, s, tm) : go_fused<1, 0, 4>(d, e, maxNb, s, tm);
+    return sh.rpy ? go_fused<0, 1, 4>(d, e, maxNb, s, tm) : go_fused<0, 0, 4>(d, e, maxNb, s, tm);
 }
 
 hipError_t launch_epilogue(const Dev& d, const Epi& e, hipStream_t s) {

@@ -48,6 +48,7 @@ struct ad_ctx {
     std::vector<long long> pbase;
     long long npart = 0;
     std::vector<long long> hbase; /* dense mode: first tensor element per system */
+    std::vector<Item> fitems;     /* fused stages of an ensemble: (system, target block) */
     bool fused_ready = false;     /* the fused kernels may use all of LDS */
     long long nH = 0;             /* dense mode: tensor elements over all systems */
     int maxNb = 0;
@@ -182,11 +183,11 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
     if (L.fused != 0 && L.fused != 1) return fail(c, AD_EINVAL, "launch.fused must be 0 or 1");
     if (L.fused) {
-        if (c->p.precision != AD_FP32C || c->nsys != 1 || c->p.steric_k != 0.0 || c->Ntot < 2)
-            return fail(c, AD_EINVAL, "launch.fused needs one system, AD_FP32C and no steric forces");
-        if (ad::fused_lds_bytes(c->Ntot, L.posmode == AD_POS_HILO) > ad::FUSED_LDS_MAX)
-            return fail(c, AD_EINVAL, "launch.fused: %d spheres do not fit in LDS with this position mode",
-                        c->Ntot);
+        if (c->p.precision != AD_FP32C || c->p.steric_k != 0.0)
+            return fail(c, AD_EINVAL, "launch.fused needs AD_FP32C and no steric forces");
+        if (ad::fused_lds_bytes(c->maxNb, L.posmode == AD_POS_HILO, c->nsys > 1 ? 4 : 16) > ad::FUSED_LDS_MAX)
+            return fail(c, AD_EINVAL, "launch.fused: a system of %d spheres does not fit in LDS with this "
+                        "position mode", c->maxNb);
     }
     return AD_OK;
 }
@@ -288,6 +289,25 @@ static void build_items(ad_ctx* c) {
         }
     }
     c->npart = pb;
+    /* fused stages of an ensemble: one item per 16-target block of a system,
+     * longest system first */
+    c->fitems.clear();
+    if (c->launch.fused && c->nsys > 1) {
+        for (int b = 0; b < c->nsys; ++b) {
+            const int Nb = 2 * c->S[b];
+            for (int i = 0; i < Nb; i += 16) {
+                Item it{};
+                it.sys = b;
+                it.i0 = c->off[b] + i;
+                it.ni = std::min(16, Nb - i);
+                it.ioff = c->off[b];
+                it.Nb = Nb;
+                c->fitems.push_back(it);
+            }
+        }
+        std::stable_sort(c->fitems.begin(), c->fitems.end(),
+                         [](const Item& a, const Item& b) { return a.Nb > b.Nb; });
+    }
     /* longest first: the hardware dispatcher then hands the cheap items to
      * whichever compute units free up last */
     std::stable_sort(c->items.begin(), c->items.end(), [](const Item& a, const Item& b) {
@@ -299,7 +319,7 @@ static void build_items(ad_ctx* c) {
 
 struct Layout {
     size_t ctl, X, R, U0, Y, Fs, nbr_cnt, nbr_idx, phitrig, dsys, sys_off, sys_P, sys_pbase, sys_hbase, items,
-        pA, pB, pC, pD, pA2, pB2, pC2, pD2, part, tab, H, total;
+        pA, pB, pC, pD, pA2, pB2, pC2, pD2, part, tab, H, fitems, total;
 };
 
 static Layout layout(const ad_ctx* c) {
@@ -339,6 +359,7 @@ static Layout layout(const ad_ctx* c) {
     L.part = take((size_t)c->npart * 8);
     L.tab = take((size_t)kRing * 8 * 8);
     L.H = take((size_t)c->nH * 8);
+    L.fitems = take(c->fitems.size() * sizeof(Item));
     L.total = o;
     return L;
 }
@@ -369,6 +390,8 @@ static void make_dev(ad_ctx* c) {
     d.sys_pbase = reinterpret_cast<const long long*>(b + L.sys_pbase);
     d.sys_hbase = reinterpret_cast<const long long*>(b + L.sys_hbase);
     d.H = c->nH ? reinterpret_cast<double*>(b + L.H) : nullptr;
+    d.fitems = reinterpret_cast<const Item*>(b + L.fitems);
+    d.nfitems = (int)c->fitems.size();
     d.items = reinterpret_cast<const Item*>(b + L.items);
     d.pA = reinterpret_cast<float4*>(b + L.pA);
     d.pB = reinterpret_cast<float4*>(b + L.pB);
@@ -416,6 +439,9 @@ static int upload_tables(ad_ctx* c) {
     HIPCHECK(c, hipMemcpy(b + L.sys_hbase, c->hbase.data(), c->nsys * 8, hipMemcpyHostToDevice));
     if (!c->items.empty())
         HIPCHECK(c, hipMemcpy(b + L.items, c->items.data(), c->items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    if (!c->fitems.empty())
+        HIPCHECK(c, hipMemcpy(b + L.fitems, c->fitems.data(), c->fitems.size() * sizeof(Item),
+                              hipMemcpyHostToDevice));
     return AD_OK;
 }
 
@@ -500,7 +526,7 @@ static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mod
     const bool fused = mode == 1 && c->launch.fused;
     if (!c->profile) {
         if (fused) {
-            HIPCHECK(c, ad::launch_fused(d, e, sh, st));
+            HIPCHECK(c, ad::launch_fused(d, e, sh, c->maxNb, st));
             return AD_OK;
         }
         if (is_dense(c))
@@ -518,7 +544,7 @@ static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mod
         if (rc != AD_OK) return rc;
     }
     if (fused)
-        HIPCHECK(c, ad::launch_fused(d, e, sh, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
+        HIPCHECK(c, ad::launch_fused(d, e, sh, c->maxNb, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
     else if (is_dense(c))
         HIPCHECK(c, ad::launch_dense(d, e, mode, c->maxNb, st, c->ev[2 * c->ev_used], c->ev[2 * c->ev_used + 1]));
     else

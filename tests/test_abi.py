@@ -146,8 +146,9 @@ def test_dense_mode_launch_rules_and_workspace():
 
 
 def test_fused_stage_launch_rules():
-    """launch.fused: one system, AD_FP32C, no steric forces, every source in
-    LDS (6784 spheres with single-float positions, 4544 with hi/lo)."""
+    """launch.fused: AD_FP32C, no steric forces, every source of a system in
+    LDS (6784 spheres with single-float positions, 4544 with hi/lo; ensembles
+    of systems up to those sizes)."""
     ctx = P.ad_create(P.make_params(Params(), "fp32c"), [2048])
     try:
         P.ad_set_launch(ctx, fused=1, posmode=2)
@@ -164,8 +165,14 @@ def test_fused_stage_launch_rules():
             P.ad_set_launch(ok, fused=1, posmode=1)                    # hi/lo: 4544 at most
     finally:
         P.ad_destroy(ok)
+    ens = P.ad_create(P.make_params(Params(), "fp32c"), [64, 32, 5])
+    try:
+        P.ad_set_launch(ens, fused=1, posmode=1)
+        assert P.ad_get_launch(ens)["fused"] == 1
+    finally:
+        P.ad_destroy(ens)
     for prec, sizes, params in (("fp64", [64], Params()), ("fp64_tiled", [64], Params()),
-                                ("fp32c", [64, 32], Params()), ("fp32c", [3400], Params()),
+                                ("fp32c", [3400], Params()), ("fp32c", [10, 3500], Params()),
                                 ("fp32c", [64], Params(steric_k=100.0, steric_r=2.0))):
         ctx = P.ad_create(P.make_params(params, prec), sizes)
         try:
