@@ -161,7 +161,8 @@ def main():
     value = pairs_per_step * args.steps / secs
     log(f"fp32c: {ms_per_step:.4f} ms/step, {value:.4e} pairs/s (wall {wall:.3f} s)")
 
-    # pair-kernel duration under HIP events on the launch stream
+    # pair-kernel duration under HIP events on the launch stream (with fused
+    # stages, the one kernel of a stage, which also does the stage update)
     P.ad_profile_pairs(sim.ctx, True)
     sim.step(args.profile_steps)
     kern_ms, launches = P.ad_profile_read(sim.ctx)
@@ -221,7 +222,8 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": counted_traffic(sim.launch) if args.workload == COUNTED["workload"] else None,
                      "traffic_unit": "B per launch",
-                     "kernel": "k_pairs_f32c", "avg_launch_us": avg_ms * 1e3,
+                     "kernel": "k_stage_fused (pair sum and stage update)" if sim.launch.get("fused") else "k_pairs_f32c",
+                     "avg_launch_us": avg_ms * 1e3,
                      "flops_per_launch": FLOPS_PER_PAIR * kernel_pairs},
     }
     if not args.no_cpu_baseline:
