@@ -32,10 +32,10 @@ FLOPS_PER_PAIR = 28           # algorithmic flops of one ordered pair term
 # Valid only for the kernel source and launch shape they were taken with.
 COUNTED = {
     "workload": "n4096",
-    "source_sha256": "131523fc33d0ca5aae4dc2ff368858a0c70cbcaf9fd6c3da72f85e160253ff60",
-    "launch": {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 2, "fused": 0},
-    "fetch_kib": 669.58, "fetch_scale": 262144.0 / 131092.56,
-    "write_kib": 1536.05, "write_scale": 262144.0 / 262144.0,
+    "source_sha256": "d1f3f3ab0605d5c4a8dc8e19f5f31ea22a22bcaef929574709e59a0e5e018494",
+    "launch": {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 2, "fused": 1},
+    "fetch_kib": 798.30, "fetch_scale": 262144.0 / 131093.0,
+    "write_kib": 336.05, "write_scale": 262144.0 / 262144.0,
 }
 
 
@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--unfused", action="store_true",
+                    help="tuned launch with pair kernel and epilogue as two kernels (for profiles of that path)")
     ap.add_argument("--counter-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a few steps plus one plain 256 MiB device copy")
     args = ap.parse_args()
@@ -137,6 +139,11 @@ def main():
     # the dumbbell partner is summed in FP64 outside the pair kernel
     kernel_pairs = float((Nb * (Nb - 2)).sum())
 
+    launch = "tuned"
+    if args.unfused:
+        from paper_1004_1932_amd.autotune import tuned_launch
+        launch = dict(tuned_launch(sizes) or {}, fused=0)
+
     if args.counter_probe:
         # a known-size copy calibrates FETCH_SIZE / WRITE_SIZE against bytes
         src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -144,7 +151,7 @@ def main():
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
-        sim = P.Simulator(w.params, sizes, precision="fp32c", launch="tuned")
+        sim = P.Simulator(w.params, sizes, precision="fp32c", launch=launch)
         sim.set_state(w.X, w.phi)
         sim.step(3)
         torch.cuda.synchronize()
@@ -152,7 +159,7 @@ def main():
         return
 
     # FP32-compensated path, graph-replayed steps
-    sim = P.Simulator(w.params, sizes, precision="fp32c", graph=not args.no_graph, launch="tuned")
+    sim = P.Simulator(w.params, sizes, precision="fp32c", graph=not args.no_graph, launch=launch)
     sim.set_state(w.X, w.phi)
     log(f"fp32c launch {sim.launch}")
     secs, wall = time_steps(sim, args.steps, args.warmup)
