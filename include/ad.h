@@ -183,9 +183,11 @@ int ad_check(ad_ctx* ctx, void* stream);
 int ad_use_graph(ad_ctx* ctx, int32_t enable);
 
 /* Measurement support. With enable != 0, ad_step/ad_run launch kernels
- * directly (no graph) and bracket every launch of the pair-sum kernel with
- * HIP events on the call's stream; ad_profile_read synchronises and returns
- * the summed duration (ms) and number of those launches since enabling. */
+ * directly (no graph) and bracket every launch of the pair-sum kernel (with
+ * launch.fused = 1, the stage kernel, which also does the stage update; with
+ * AD_FP64_DENSE, the assembly and product together) with HIP events on the
+ * call's stream; ad_profile_read synchronises and returns the summed duration
+ * (ms) and number of those launches since enabling. */
 int ad_profile_pairs(ad_ctx* ctx, int32_t enable);
 int ad_profile_read(ad_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -212,3 +212,16 @@ def test_oracle_keeps_sin_and_cos_separate():
     out = subprocess.run(["nm", "-D", str(adref.LIB)], capture_output=True, text=True, check=True).stdout
     undefined = {line.split()[-1].split("@")[0] for line in out.splitlines() if " U " in line}
     assert {"sin", "cos"} <= undefined and "sincos" not in undefined
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus N > 1 exits at once with a message."""
+    import json
+    import subprocess
+    import sys
+    from pathlib import Path
+    root = Path(__file__).resolve().parents[1]
+    res = subprocess.run([sys.executable, str(root / "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in json.loads(res.stdout.strip().splitlines()[-1])["error"]
