@@ -72,11 +72,37 @@ def cpu_baseline(w, sizes, budget_s):
     t = time.perf_counter()
     adref.run(p, X, w.phi, n, step0=1, S_per_sys=sizes)
     dt = time.perf_counter() - t
-    pairs = 4.0 * float((Nb * (Nb - 1)).sum()) * n
-    return {"value": pairs / dt, "unit": "pair interactions/s", "cores": adref.max_threads(),
-            "kind": "oracle",
-            "sample": f"{n} RK4 steps of the {N}-sphere workload ({dt:.1f} s), FP64, OpenMP over target spheres",
-            "sphere_steps_per_s": N * n / dt}
+    pairs_per_step = 4.0 * float((Nb * (Nb - 1)).sum())
+    cores = adref.max_threads()
+    out = {"value": pairs_per_step * n / dt, "unit": "pair interactions/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{n} RK4 steps of the {N}-sphere workload ({dt:.1f} s), FP64, OpenMP over target spheres",
+           "sphere_steps_per_s": N * n / dt, "cpu_model": cpu_model()}
+    # the same on one core, for a few seconds
+    adref.set_threads(1)
+    try:
+        t = time.perf_counter()
+        adref.run(p, X, w.phi, 1, step0=1, S_per_sys=sizes)
+        one = time.perf_counter() - t
+        n1 = max(1, int(0.2 * budget_s / max(one, 1e-6)))
+        t = time.perf_counter()
+        adref.run(p, X, w.phi, n1, step0=1, S_per_sys=sizes)
+        dt1 = time.perf_counter() - t
+    finally:
+        adref.set_threads(cores)
+    out["one_core"] = {"value": pairs_per_step * n1 / dt1, "sample": f"{n1} RK4 steps ({dt1:.1f} s)"}
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 DESCRIPTIONS = {

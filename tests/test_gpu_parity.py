@@ -644,6 +644,25 @@ def test_fused_stage_ensemble_matches_oracle(oracle, launch):
         assert e <= 1e-6, (b, e)
 
 
+@pytest.mark.parametrize("S,posmode", [(3392, 2), (2272, 1)])
+def test_fused_stage_at_the_lds_limit(oracle, S, posmode):
+    """The largest systems the fused stage takes (6784 spheres with
+    single-float positions, 4544 with hi/lo, every source in 160 KiB of LDS):
+    two steps against the oracle, relative to the displacement."""
+    _torch()
+    sus = make_single(S, 280.0, 41)
+    launch = dict(FUSED_SINGLE if posmode == 2 else FUSED_HILO)
+    say(f"fused at the LDS limit: N = {2 * S}, posmode {posmode}")
+    s = P.Simulator(sus.params, [S], precision="fp32c", launch=launch, graph=True)
+    s.set_state(sus.X, sus.phi)
+    _, _, code = s.run(2, 0)
+    assert code == 0
+    Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 2)
+    e = relerr(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X)
+    say(f"  displacement rel err {e:.2e}")
+    assert e <= 1e-6
+
+
 def test_fused_stage_deterministic_resumable_and_noise(oracle):
     """Fused stages: two runs give the same bits, split step calls equal one
     call, and the Heun noise follows the oracle's Brownian trajectory."""
