@@ -1,6 +1,7 @@
 """Pins of the oracle's Brownian option: additive noise with a constant C
 (Sec. V; Eq. e:langevin with Eq. e:cholesky on the diagonal of H), drawn from
-Philox4x32-10 and Box-Muller. Pinned to the statistics of the normals and to
+Philox4x32-10 and Box-Muller. Pinned to the generator's published
+known-answer vectors, to the statistics of the normals and to
 free diffusion of isolated dumbbells, whose centre moves only by the noise
 (the spring forces cancel in the centre velocity), so that its mean square
 displacement is 3 kT t/(6 pi eta a)."""
@@ -67,3 +68,14 @@ def test_noise_needs_heun(oracle):
     ens = make_ensemble(nsys=1, sizes=np.array([3], dtype=np.int32), params=p)
     with pytest.raises(OracleError):
         oracle.run(p, ens.X, ens.phi, 2, integrator=0, kT=0.1)
+
+
+def test_philox_known_answers(oracle, golden_dir):
+    """The oracle's Philox4x32-10 block against the generator's published
+    known-answer vectors (fixture tests/golden/philox4x32_10_kat.json)."""
+    import json
+    kat = json.loads((golden_dir / "philox4x32_10_kat.json").read_text())
+    for v in kat["vectors"]:
+        ctr = [int(x, 16) for x in v["counter"]]
+        key = [int(x, 16) for x in v["key"]]
+        assert oracle.philox(ctr, key) == [int(x, 16) for x in v["output"]]
