@@ -14,3 +14,11 @@ from .suspensions import (  # noqa: F401
     make_preset,
     place_dumbbells,
 )
+from .arrays import (  # noqa: F401
+    fig1_params,
+    lattice_array,
+    array_runs,
+    rotation_pair,
+    rotation_pairs,
+    checkerboard_phases,
+)
