@@ -742,26 +742,50 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
  * spheres of one system and holds all of that system's sources in LDS: lane
  * (wave w, quarter g, target t) sums target t over the sources
  * j = JS m + 4w + g (JS = 4 NW source splits, m = 0, 1, ...) in FP32, with a
- * TwoSum into a (hi, lo) pair every FS_M sources. The JS partial sums of a
- * target are combined in a fixed order (two shuffles inside the wave, then
- * the NW waves through LDS, in wave order), and the work-group then does the
- * stage update, next spring forces and next pack of its 8 dumbbells, as the
- * epilogue does: a stage needs no partial sums in HBM and no second launch.
- * Only the JS-source block that holds the work-group's own dumbbells needs
- * the self/partner mask. A single system uses NW = 16 and target blocks in
+ * TwoSum into a (hi, lo) pair every FS_M sources (32 for one system, 64 for
+ * an ensemble). The JS partial sums of a target are combined in a fixed order
+ * (two shuffles inside the wave, then the NW waves through LDS in a pairwise
+ * tree), and the work-group then does the stage update, next spring forces
+ * and next pack of its 8 dumbbells, as the epilogue does: a stage needs no
+ * partial sums in HBM and no second launch. Only the one term of the
+ * JS-source block that holds the work-group's own dumbbells needs the
+ * self/partner mask. A single system uses NW = 16 and target blocks in
  * order; an ensemble NW = 4 and a work list of (system, target block),
  * longest system first. */
 constexpr int FS_I = 16;
-constexpr int FS_M = 16;
+
+/* One source entry of the fused stage: sphere t0 + t of the pack, or
+ * padding (far away and force-free). With single-float positions only the
+ * forces' y and z are read beside (x, y, z, Fx). */
+template <int SPLIT>
+__device__ __forceinline__ void load_stage_entry(const Dev& d, int t0, int jend, int t, float4& A, float4& B,
+                                                 float& Fy, float& Fz) {
+    if (t0 + t < jend) {
+        A = d.pA[t0 + t];
+        if (SPLIT) {
+            B = d.pB[t0 + t];
+            Fy = B.w;
+        } else {
+            Fy = reinterpret_cast<const float*>(d.pB)[4 * (t0 + t) + 3];
+        }
+        Fz = d.pC[t0 + t];
+    } else {
+        A = make_float4(1.0e15f, 1.0e15f, 1.0e15f, 0.f);
+        B = make_float4(0.f, 0.f, 0.f, 0.f);
+        Fy = 0.f;
+        Fz = 0.f;
+    }
+}
 
 template <int SPLIT, int RPY, int NW>
 __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
     constexpr int T = 64 * NW; /* lanes */
     constexpr int JS = 4 * NW; /* source splits per target */
+    /* sources per FP32 partial sum before it is folded into (hi, lo) */
+    constexpr int FS_M = NW == 16 ? 32 : 64;
     extern __shared__ float4 fs_lds[];
     const int N = d.Ntot;
     const int tid = threadIdx.x;
-    advance_slots(d, e);
 
     /* the work-group's targets [i0, i0 + ni) in the system [off, off + Nb) */
     int i0, ni, off, Nb;
@@ -783,12 +807,10 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
     float4* sB = fs_lds + np;
     float* sC = reinterpret_cast<float*>(fs_lds + 2 * np);
     float2* sF = reinterpret_cast<float2*>(fs_lds + np);
-
-    /* inputs of the closing update, loaded first: lane 3t + a owns
-     * component a of target i0 + t, lane q < ni/2 the forces of dumbbell q */
     const long long step = (e.stage == 0) ? d.ctl->slot[0] : d.ctl->slot[1];
-    double st = 0.0, ct = 0.0, u0 = 0.0, xv = 0.0, rv = 0.0;
-    double2 tp = make_double2(0.0, 0.0);
+    /* inputs of the closing update, loaded first: lane 3t + a owns
+     * component a of target i0 + t */
+    double u0 = 0.0, xv = 0.0, rv = 0.0;
     if (tid < 3 * ni) {
         const int tt = tid / 3, a = tid - 3 * tt;
         const int o = a * N + i0 + tt;
@@ -796,29 +818,11 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
         xv = d.X[o];
         if (e.stage > 0) rv = d.R[o];
     }
-    if (tid < ni / 2) {
-        const long long row = step % d.ring;
-        st = d.tab[row * 8 + 2 * e.stage];
-        ct = d.tab[row * 8 + 2 * e.stage + 1];
-        tp = d.phitrig[(i0 >> 1) + tid];
-    }
 
-    /* the system's sources into LDS (padding far away and force-free) */
-    for (int j = tid; j < np; j += T) {
-        float4 A, B;
-        float C;
-        load_tile_entry(d, off, off + Nb, j, A, B, C);
-        sA[j] = A;
-        if (SPLIT) {
-            sB[j] = B;
-            sC[j] = C;
-        } else {
-            sF[j] = make_float2(B.w, C);
-        }
-    }
     const int w = tid >> 6, l = tid & 63, t = l & 15, g = l >> 4;
     const int js = 4 * w + g;
     const int i = i0 + t;
+    /* this lane's target position */
     float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
     if (t < ni) {
         const float4 A = d.pA[i];
@@ -828,8 +832,35 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
             lx = B.x; ly = B.y; lz = B.z;
         }
     }
+
+    /* the system's sources into LDS (padding far away and force-free) */
+    for (int j = tid; j < np; j += T) {
+        float4 A, B;
+        float Fy, Fz;
+        load_stage_entry<SPLIT>(d, off, off + Nb, j, A, B, Fy, Fz);
+        sA[j] = A;
+        if (SPLIT) {
+            sB[j] = B;
+            sC[j] = Fz;
+        } else {
+            sF[j] = make_float2(Fy, Fz);
+        }
+    }
     const int di = (i - off) >> 1; /* local dumbbell (off is even) */
     __syncthreads();
+    /* after the staging barrier, so that their dependent loads stall only
+     * wave 0, whose sums are not the last to finish: the step slots for the
+     * next kernel, and for lane q < ni the phase of dumbbell q/2 and the
+     * (sin, cos)(omega t) of this stage */
+    advance_slots(d, e);
+    double st = 0.0, ct = 0.0;
+    double2 tp = make_double2(0.0, 0.0);
+    if (tid < ni) {
+        const long long row = step % d.ring;
+        st = d.tab[row * 8 + 2 * e.stage];
+        ct = d.tab[row * 8 + 2 * e.stage + 1];
+        tp = d.phitrig[(i0 >> 1) + (tid >> 1)];
+    }
 
     const float crr = e.c.crr;
     float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
@@ -867,7 +898,11 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
         const int m1 = min(M, m0 + FS_M);
         float px = 0.f, py = 0.f, pz = 0.f;
         if (ms >= m0 && ms < m1) {
-            for (int m = m0; m < m1; ++m) term(js + JS * m, m == ms, px, py, pz);
+#pragma unroll 4
+            for (int m = m0; m < ms; ++m) term(js + JS * m, false, px, py, pz);
+            term(js + JS * ms, true, px, py, pz);
+#pragma unroll 4
+            for (int m = ms + 1; m < m1; ++m) term(js + JS * m, false, px, py, pz);
         } else if (m1 - m0 == FS_M) {
 #pragma unroll 4
             for (int m = m0; m < m0 + FS_M; ++m) term(js + JS * m, false, px, py, pz);
@@ -881,7 +916,7 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
 
     /* combine the JS partial sums of each target in a fixed order: the four
      * quarters of a wave by shuffles (both partners get the same sum), then
-     * the NW waves through LDS, in wave order */
+     * the NW waves through LDS in a pairwise tree */
     auto combine = [](float& hi, float& lo, float oh, float ol) {
         const float s = hi + oh;
         const float bb = s - hi;
@@ -901,8 +936,7 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
     __syncthreads(); /* the sources are no longer read */
     float* red = reinterpret_cast<float*>(fs_lds);                  /* [NW waves][FS_I][6] */
     double* ys = reinterpret_cast<double*>(fs_lds) + NW * FS_I * 3; /* [FS_I][3] stage positions */
-    double* fsp = ys + FS_I * 3;                                    /* [FS_I][3] spring forces */
-    int* badf = reinterpret_cast<int*>(fsp + FS_I * 3);
+    int* badf = reinterpret_cast<int*>(ys + FS_I * 3);
     if (g == 0) {
         float* r = red + (w * FS_I + t) * 6;
         r[0] = ax; r[1] = bx; r[2] = ay; r[3] = by; r[4] = az; r[5] = bz;
@@ -910,36 +944,36 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
     if (tid == 0) *badf = 0;
     __syncthreads();
     if (tid < 3 * ni) {
-        /* component a of target tt: the waves' sums in wave order, then the
+        /* component a of target tt: the waves' sums combined pairwise in a
+         * fixed tree (wave w with w + 1, then pairs of pairs, ...), then the
          * stage update */
         const int tt = tid / 3, a = tid - 3 * tt;
-        const float* r0 = red + tt * 6 + 2 * a;
-        float hi = r0[0], lo = r0[1];
-        for (int ww = 1; ww < NW; ++ww) {
+        float hs[NW], ls[NW];
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
             const float* r = red + (ww * FS_I + tt) * 6 + 2 * a;
-            combine(hi, lo, r[0], r[1]);
+            hs[ww] = r[0];
+            ls[ww] = r[1];
         }
+#pragma unroll
+        for (int sp = 1; sp < NW; sp *= 2)
+#pragma unroll
+            for (int ww = 0; ww < NW; ww += 2 * sp) combine(hs[ww], ls[ww], hs[ww + sp], ls[ww + sp]);
         const int ii = i0 + tt;
-        const double k = u0 + e.c.co * ((double)hi + (double)lo);
+        const double k = u0 + e.c.co * ((double)hs[0] + (double)ls[0]);
         if (!isfinite(k)) *badf = 1;
         ys[tt * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv, rv, step);
     }
     __syncthreads();
-    if (tid < ni / 2) {
-        /* spring forces of dumbbell tid at the stage positions */
-        double f0[3], f1[3];
-        spring_forces(e.c, ys + (2 * tid) * 3, ys + (2 * tid + 1) * 3, tp.x, tp.y, st, ct, f0, f1);
-        for (int a = 0; a < 3; ++a) {
-            fsp[(2 * tid) * 3 + a] = f0[a];
-            fsp[(2 * tid + 1) * 3 + a] = f1[a];
-        }
-    }
-    __syncthreads();
     if (tid == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
     if (tid < ni) {
-        /* one lane per sphere: partner term and the next pack */
-        const int p = tid ^ 1;
-        store_pack_sphere(d, e.c, i0 + tid, ys + tid * 3, ys + p * 3, fsp + tid * 3, fsp + p * 3, 1);
+        /* one lane per sphere: the spring forces of its dumbbell (both lanes
+         * of a dumbbell evaluate the same expression, so they agree bit for
+         * bit), then its partner term and its part of the next pack */
+        const int q = tid >> 1, h = tid & 1;
+        double f[2][3];
+        spring_forces(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
+        store_pack_sphere(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1], 1);
     }
 }
 

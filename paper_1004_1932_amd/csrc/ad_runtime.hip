@@ -577,7 +577,7 @@ static int ensure_graph(ad_ctx* c) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
     if (rc != AD_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g); /* the launch error is the one reported */
         return rc;
     }
     if (e != hipSuccess) return fail(c, AD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
