@@ -161,6 +161,22 @@ def store(S_per_sys, result: dict, path: Path = TABLE) -> None:
     path.write_text(json.dumps(table, indent=1, sort_keys=True) + "\n")
 
 
+def tuning_workload(name: str):
+    """A named workload to tune on: a preset (n512, n4096, ens512, ...),
+    "single:N" (one suspension of N spheres at the density of the 4096-sphere
+    preset, side 240 (N/4096)^(1/3)), or "arrays:x:W" (W checkerboard x^3
+    arrays at spacing 10 ell with the Fig. 1 parameters, one ensemble)."""
+    from workload import array_runs, fig1_params, make_preset, make_single
+    if name.startswith("single:"):
+        N = int(name.split(":")[1])
+        return make_single(N // 2, 240.0 * (N / 4096.0) ** (1.0 / 3.0), 0)
+    if name.startswith("arrays:"):
+        _, x, W = name.split(":")
+        p = fig1_params()
+        return array_runs(int(x), 10 * p.ell, int(W), "checkerboard", params=p)[0]
+    return make_preset(name)
+
+
 def main(argv=None):
     """Tune named synthetic workloads and write the table:
     python -m paper_1004_1932_amd.autotune --workload n4096 --out table.json"""
@@ -168,7 +184,6 @@ def main(argv=None):
     import sys
 
     sys.path.insert(0, str(Path(__file__).resolve().parents[1]))
-    from workload import make_preset
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", action="append", required=True)
@@ -177,7 +192,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=50)
     args = ap.parse_args(argv)
     for name in args.workload:
-        w = make_preset(name)
+        w = tuning_workload(name)
         sizes = getattr(w, "S_per_sys", None)
         sizes = [w.S] if sizes is None else sizes
         print(f"tuning {name}", flush=True)

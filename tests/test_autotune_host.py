@@ -1,0 +1,40 @@
+"""Host logic of the autotuner: size buckets, candidate shapes, the tuning
+workloads and the shipped table (no GPU needed)."""
+import json
+
+import numpy as np
+
+from paper_1004_1932_amd import autotune as A
+
+
+def test_bucket_keys():
+    assert A.bucket_key([2048]) == "single:N<=4096"
+    assert A.bucket_key([2049]) == "single:N<=8192"
+    assert A.bucket_key([256]) == "single:N<=512"
+    assert A.bucket_key([16, 400, 3]) == "ensemble:N<=1024"
+    assert A.bucket_key(np.array([27] * 64)) == "ensemble:N<=64"
+
+
+def test_tuning_workloads_land_in_their_buckets():
+    for name, key, nsys in (("single:1024", "single:N<=1024", 1), ("single:8192", "single:N<=8192", 1),
+                            ("arrays:3:4", "ensemble:N<=64", 4), ("arrays:5:2", "ensemble:N<=256", 2)):
+        w = A.tuning_workload(name)
+        S = getattr(w, "S_per_sys", None)
+        S = [w.S] if S is None else S
+        assert A.bucket_key(S) == key and len(S) == nsys, name
+
+
+def test_candidates_are_unique_and_include_the_fused_form():
+    for N, ens in ((512, False), (4096, False), (65536, False), (800, True)):
+        c = A.candidates(N, ens)
+        assert len(c) == len({json.dumps(x, sort_keys=True) for x in c})
+        assert any(x.get("fused") == 1 for x in c)
+
+
+def test_shipped_table_is_gated():
+    """Every stored shape passed the accuracy gate it was tuned under."""
+    table = A.load_table()
+    assert "single:N<=4096" in table
+    for key, rec in table.items():
+        assert rec["err"] <= rec["gate"] <= 5e-7, key
+        assert rec["ms_per_step"] > 0 and isinstance(rec["launch"], dict), key
