@@ -32,11 +32,16 @@ FLOPS_PER_PAIR = 28           # algorithmic flops of one ordered pair term
 # Valid only for the kernel source and launch shape they were taken with.
 COUNTED = {
     "workload": "n4096",
-    "source_sha256": "7a80ca97baed762d68b03f4191c1dc92fe8cc3396d1e08092d214afc6bd00660",
+    "source_sha256": "f4d218abfa2ba17e5ccb3e63621d5dcf10a0b1821e33ce5099dcbb0b84ef9996",
     "launch": {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 2, "fused": 1},
-    "fetch_kib": 814.80, "fetch_scale": 262144.0 / 131092.5,
+    "fetch_kib": 812.23, "fetch_scale": 262144.0 / 131087.9,
     "write_kib": 336.05, "write_scale": 262144.0 / 262144.0,
 }
+
+
+# the kernel that a launch of each form runs (the one bracketed by events)
+KERNEL_NAMES = {0: "k_pairs_f32c", 1: "k_stage_fused (pair sum and stage update)",
+                2: "k_stage_wide (pair sum and stage update, 64 targets per work-group)"}
 
 
 def log(msg):
@@ -145,6 +150,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--unfused", action="store_true",
                     help="tuned launch with pair kernel and epilogue as two kernels (for profiles of that path)")
+    ap.add_argument("--fused", type=int, choices=(0, 1, 2), default=None,
+                    help="tuned launch with this stage form (0: two kernels, 1: 16 targets per work-group, "
+                         "2: 64 targets per work-group), for profiles of the form the table did not choose")
     ap.add_argument("--counter-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a few steps plus one plain 256 MiB device copy")
     args = ap.parse_args()
@@ -166,9 +174,10 @@ def main():
     kernel_pairs = float((Nb * (Nb - 2)).sum())
 
     launch = "tuned"
-    if args.unfused:
+    form = 0 if args.unfused else args.fused
+    if form is not None:
         from paper_1004_1932_amd.autotune import tuned_launch
-        launch = dict(tuned_launch(sizes) or {}, fused=0)
+        launch = dict(tuned_launch(sizes) or {}, fused=form)
 
     if args.counter_probe:
         # a known-size copy calibrates FETCH_SIZE / WRITE_SIZE against bytes
@@ -255,7 +264,7 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": counted_traffic(sim.launch) if args.workload == COUNTED["workload"] else None,
                      "traffic_unit": "B per launch",
-                     "kernel": "k_stage_fused (pair sum and stage update)" if sim.launch.get("fused") else "k_pairs_f32c",
+                     "kernel": KERNEL_NAMES[sim.launch.get("fused", 0)],
                      "avg_launch_us": avg_ms * 1e3,
                      "flops_per_launch": FLOPS_PER_PAIR * kernel_pairs},
     }

@@ -109,10 +109,14 @@ typedef struct ad_launch {
     int32_t wj;       /* waves splitting each j-tile: 1, or 4 with wg = 256 (AD_FP32C) */
     int32_t posmode;  /* AD_FP32C positions: 1 = hi/lo float pair, 2 = single float */
     int32_t fused;    /* 1: each step stage is one kernel whose work-groups hold their
-                         system's sources in LDS and also do the stage update (AD_FP32C, no
-                         steric forces, at most 6784 spheres per system with single-float or
-                         4544 with hi/lo positions; ad_mobility_apply still uses the other
-                         fields); 0: pair kernel and epilogue as two kernels */
+                         system's sources in LDS and also do the stage update, 16 target
+                         spheres per work-group (AD_FP32C, no steric forces, at most 6784
+                         spheres per system with single-float or 4544 with hi/lo positions;
+                         ad_mobility_apply still uses the other fields);
+                         2: the same with 64 target spheres per 4-wave work-group, one per
+                         lane, for ensembles of small systems (at most 6824 single-float or
+                         4548 hi/lo spheres per system);
+                         0: pair kernel and epilogue as two kernels */
 } ad_launch;
 
 #define AD_POS_HILO 1
@@ -184,7 +188,7 @@ int ad_use_graph(ad_ctx* ctx, int32_t enable);
 
 /* Measurement support. With enable != 0, ad_step/ad_run launch kernels
  * directly (no graph) and bracket every launch of the pair-sum kernel (with
- * launch.fused = 1, the stage kernel, which also does the stage update; with
+ * launch.fused = 1 or 2, the stage kernel, which also does the stage update; with
  * AD_FP64_DENSE, the assembly and product together) with HIP events on the
  * call's stream; ad_profile_read synchronises and returns the summed duration
  * (ms) and number of those launches since enabling. */

@@ -65,6 +65,7 @@ def candidates(N: int, ensemble: bool):
     for posmode in (B.AD_POS_HILO, B.AD_POS_SINGLE):
         if ensemble:
             out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=1))
+            out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=2))
         else:
             out.append(dict(wg=256, wj=4, ipl=1, jchunk=256, posmode=posmode, fused=1))
     uniq = []

@@ -141,6 +141,8 @@ __device__ __forceinline__ void advance_slots(const Dev& d, const Epi& e) {
  * target spheres. */
 struct Shape {
     int wg, wj, ipl, split;
+    int fused;  /* 0: pair kernel + epilogue; 1: stage kernel, 16 targets per
+                   work-group; 2: stage kernel, 64 targets per work-group */
     int rpy;    /* pair tensor with the RPY-Mazur correction */
     int steric; /* FP32C: record steric candidates while summing */
 };
@@ -183,6 +185,16 @@ __host__ __device__ inline int fused_lds_bytes(int n, int split, int nw) {
     const int np = (n + js - 1) / js * js;
     const int b = np * (split ? 36 : 24);
     const int red = nw * 16 * 6 * 4 + 16 * 3 * 8 + 16;
+    return b > red ? b : red;
+}
+/* LDS bytes of a wide fused work-group (64 targets, 4 waves): the sources
+ * padded to 4, or the combination area (4 waves x 64 targets x 6 floats,
+ * 64 x 3 stage positions, a flag) if larger */
+constexpr int FW_I = 64;
+__host__ __device__ inline int fused_wide_lds_bytes(int n, int split) {
+    const int np = (n + 3) / 4 * 4;
+    const int b = np * (split ? 36 : 24);
+    const int red = 4 * FW_I * 6 * 4 + FW_I * 3 * 8 + 16;
     return b > red ? b : red;
 }
 /* allow the fused kernels FUSED_LDS_MAX bytes of dynamic LDS (host call,

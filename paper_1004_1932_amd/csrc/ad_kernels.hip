@@ -977,6 +977,177 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
     }
 }
 
+/* Wide form of the fused stage, for ensembles of small systems: a work-group
+ * of 4 waves owns FW_I = 64 target spheres of one system, one per lane, and
+ * holds all of the system's sources in LDS. Wave w sums, for every target,
+ * the sources of its quarter [w Q, (w + 1) Q) of the padded source list
+ * (Q = np / 4), each read as an LDS broadcast, in FP32 with a TwoSum into
+ * (hi, lo) every FW_M sources. Only the sources that are the work-group's own
+ * spheres need the self/partner test. The quarters' sums of a target are
+ * combined through LDS as (q0 + q1) + (q2 + q3), and the closing update is
+ * the one of k_stage_fused. Per work-group, staging and the closing update
+ * cost what they cost for 16 targets, over four times the pair work. */
+constexpr int FW_M = 32;
+
+template <int SPLIT, int RPY>
+__global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
+    extern __shared__ float4 fs_lds[];
+    const int N = d.Ntot;
+    const int tid = threadIdx.x;
+    const Item it = d.fitems[blockIdx.x];
+    const int i0 = it.i0, off = it.ioff, Nb = it.Nb;
+    const int ni = min(FW_I, off + Nb - i0);
+    const int np = (Nb + 3) / 4 * 4;
+    const int Q = np / 4;
+    float4* sA = fs_lds;
+    float4* sB = fs_lds + np;
+    float* sC = reinterpret_cast<float*>(fs_lds + 2 * np);
+    float2* sF = reinterpret_cast<float2*>(fs_lds + np);
+    const long long step = (e.stage == 0) ? d.ctl->slot[0] : d.ctl->slot[1];
+    /* inputs of the closing update, loaded first: lane 3t + a owns
+     * component a of target i0 + t */
+    double u0 = 0.0, xv = 0.0, rv = 0.0;
+    if (tid < 3 * ni) {
+        const int tt = tid / 3, a = tid - 3 * tt;
+        const int o = a * N + i0 + tt;
+        u0 = d.U0[o];
+        xv = d.X[o];
+        if (e.stage > 0) rv = d.R[o];
+    }
+    const int w = tid >> 6, l = tid & 63;
+    const int i = i0 + l;
+    /* this lane's target position (lanes past the block's end sum for
+     * position zero and are not used) */
+    float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
+    if (l < ni) {
+        const float4 A = d.pA[i];
+        hx = A.x; hy = A.y; hz = A.z;
+        if (SPLIT) {
+            const float4 B = d.pB[i];
+            lx = B.x; ly = B.y; lz = B.z;
+        }
+    }
+    /* the system's sources into LDS (padding far away and force-free) */
+    for (int j = tid; j < np; j += 256) {
+        float4 A, B;
+        float Fy, Fz;
+        load_stage_entry<SPLIT>(d, off, off + Nb, j, A, B, Fy, Fz);
+        sA[j] = A;
+        if (SPLIT) {
+            sB[j] = B;
+            sC[j] = Fz;
+        } else {
+            sF[j] = make_float2(Fy, Fz);
+        }
+    }
+    const int di = (i - off) >> 1; /* local dumbbell (off is even) */
+    __syncthreads();
+    /* as in k_stage_fused: after the staging barrier, for wave 0 only */
+    advance_slots(d, e);
+    double st = 0.0, ct = 0.0;
+    double2 tp = make_double2(0.0, 0.0);
+    if (tid < ni) {
+        const long long row = step % d.ring;
+        st = d.tab[row * 8 + 2 * e.stage];
+        ct = d.tab[row * 8 + 2 * e.stage + 1];
+        tp = d.phitrig[(i0 >> 1) + (tid >> 1)];
+    }
+
+    const float crr = e.c.crr;
+    float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+    auto term = [&](int j, bool masked, float& px, float& py, float& pz) {
+        const float4 Aj = sA[j];
+        float Fy, Fz, qx = 0.f, qy = 0.f, qz = 0.f;
+        if (SPLIT) {
+            const float4 Bj = sB[j];
+            qx = Bj.x; qy = Bj.y; qz = Bj.z;
+            Fy = Bj.w;
+            Fz = sC[j];
+        } else {
+            const float2 f = sF[j];
+            Fy = f.x;
+            Fz = f.y;
+        }
+        float rx, ry, rz;
+        if (SPLIT) {
+            rx = (hx - Aj.x) + (lx - qx);
+            ry = (hy - Aj.y) + (ly - qy);
+            rz = (hz - Aj.z) + (lz - qz);
+        } else {
+            rx = hx - Aj.x;
+            ry = hy - Aj.y;
+            rz = hz - Aj.z;
+        }
+        const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+        float ir = __builtin_amdgcn_rsqf(r2);
+        if (masked && (j >> 1) == di) ir = 0.f;
+        pair_term<RPY>(ir, rx, ry, rz, Aj.w, Fy, Fz, crr, px, py, pz);
+    };
+    /* this wave's quarter of the sources, and the part of it that holds the
+     * work-group's own spheres (local [i0 - off, i0 - off + ni)) */
+    const int j0 = w * Q, j1 = j0 + Q;
+    const int jm0 = max(j0, i0 - off), jm1 = min(j1, i0 - off + ni);
+    for (int c0 = j0; c0 < j1; c0 += FW_M) {
+        const int c1 = min(j1, c0 + FW_M);
+        float px = 0.f, py = 0.f, pz = 0.f;
+        if (c0 < jm1 && c1 > jm0) {
+            for (int j = c0; j < c1; ++j) term(j, true, px, py, pz);
+        } else if (c1 - c0 == FW_M) {
+#pragma unroll 4
+            for (int j = c0; j < c0 + FW_M; ++j) term(j, false, px, py, pz);
+        } else {
+            for (int j = c0; j < c1; ++j) term(j, false, px, py, pz);
+        }
+        two_sum_acc(ax, bx, px);
+        two_sum_acc(ay, by, py);
+        two_sum_acc(az, bz, pz);
+    }
+
+    auto combine = [](float& hi, float& lo, float oh, float ol) {
+        const float s = hi + oh;
+        const float bb = s - hi;
+        const float err = (hi - (s - bb)) + (oh - bb);
+        hi = s;
+        lo = (lo + ol) + err;
+    };
+    __syncthreads(); /* the sources are no longer read */
+    float* red = reinterpret_cast<float*>(fs_lds);                   /* [4 waves][FW_I][6] */
+    double* ys = reinterpret_cast<double*>(fs_lds) + 4 * FW_I * 3;   /* [FW_I][3] stage positions */
+    int* badf = reinterpret_cast<int*>(ys + FW_I * 3);
+    {
+        float* r = red + (w * FW_I + l) * 6;
+        r[0] = ax; r[1] = bx; r[2] = ay; r[3] = by; r[4] = az; r[5] = bz;
+    }
+    if (tid == 0) *badf = 0;
+    __syncthreads();
+    if (tid < 3 * ni) {
+        const int tt = tid / 3, a = tid - 3 * tt;
+        float hs[4], ls[4];
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+            const float* r = red + (ww * FW_I + tt) * 6 + 2 * a;
+            hs[ww] = r[0];
+            ls[ww] = r[1];
+        }
+        combine(hs[0], ls[0], hs[1], ls[1]);
+        combine(hs[2], ls[2], hs[3], ls[3]);
+        combine(hs[0], ls[0], hs[2], ls[2]);
+        const int ii = i0 + tt;
+        const double k = u0 + e.c.co * ((double)hs[0] + (double)ls[0]);
+        if (!isfinite(k)) *badf = 1;
+        ys[tt * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv, rv, step);
+    }
+    __syncthreads();
+    if (tid == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+    if (tid < ni) {
+        /* one lane per sphere, as in k_stage_fused */
+        const int q = tid >> 1, h = tid & 1;
+        double f[2][3];
+        spring_forces(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
+        store_pack_sphere(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1], 1);
+    }
+}
+
 /* FP64: the sum in ascending j with the plain operation order
  *   r2 = (rx*rx + ry*ry) + rz*rz; ir = 1/sqrt(r2); fr = (rx*Fx + ry*Fy) + rz*Fz;
  *   t = fr/r2; acc = acc + ir*(F + t*r)
@@ -1309,8 +1480,23 @@ static hipError_t go_fused(const Dev& d, const Epi& e, int maxNb, hipStream_t s,
     return hipGetLastError();
 }
 
+template <int SPLIT, int RPY>
+static hipError_t go_wide(const Dev& d, const Epi& e, int maxNb, hipStream_t s, const Timing& tm) {
+    const int lds = fused_wide_lds_bytes(maxNb, SPLIT);
+    auto kern = k_stage_wide<SPLIT, RPY>;
+    if (tm.start)
+        hipExtLaunchKernelGGL(kern, dim3(d.nfitems), dim3(256), lds, s, tm.start, tm.stop, 0, d, e);
+    else
+        hipLaunchKernelGGL(kern, dim3(d.nfitems), dim3(256), lds, s, d, e);
+    return hipGetLastError();
+}
+
 hipError_t prepare_fused() {
-    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_fused<0, 0, 16>),
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_wide<0, 0>),
+                             reinterpret_cast<const void*>(&k_stage_wide<0, 1>),
+                             reinterpret_cast<const void*>(&k_stage_wide<1, 0>),
+                             reinterpret_cast<const void*>(&k_stage_wide<1, 1>),
+                             reinterpret_cast<const void*>(&k_stage_fused<0, 0, 16>),
                              reinterpret_cast<const void*>(&k_stage_fused<0, 1, 16>),
                              reinterpret_cast<const void*>(&k_stage_fused<1, 0, 16>),
                              reinterpret_cast<const void*>(&k_stage_fused<1, 1, 16>),
@@ -1328,7 +1514,14 @@ hipError_t prepare_fused() {
 hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, int maxNb, hipStream_t s,
                         hipEvent_t ev_start, hipEvent_t ev_stop) {
     if (e.prec != PREC_FP32C || sh.steric || maxNb < 2) return hipErrorInvalidValue;
-    if ((d.nsys > 1) != (d.nfitems > 0)) return hipErrorInvalidValue;
+    const Timing tm0{ev_start, ev_stop};
+    if (sh.fused == 2) {
+        /* every work-group takes its (system, 64-target block) from the list */
+        if (d.nfitems <= 0 || fused_wide_lds_bytes(maxNb, sh.split) > FUSED_LDS_MAX) return hipErrorInvalidValue;
+        if (sh.split) return sh.rpy ? go_wide<1, 1>(d, e, maxNb, s, tm0) : go_wide<1, 0>(d, e, maxNb, s, tm0);
+        return sh.rpy ? go_wide<0, 1>(d, e, maxNb, s, tm0) : go_wide<0, 0>(d, e, maxNb, s, tm0);
+    }
+    if (sh.fused != 1 || (d.nsys > 1) != (d.nfitems > 0)) return hipErrorInvalidValue;
     const int nw = d.nsys > 1 ? 4 : 16;
     if (fused_lds_bytes(maxNb, sh.split, nw) > FUSED_LDS_MAX) return hipErrorInvalidValue;
     const Timing tm{ev_start, ev_stop};

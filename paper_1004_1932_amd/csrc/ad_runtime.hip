@@ -181,11 +181,14 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (c->p.precision == AD_FP32C && L.posmode != AD_POS_HILO && L.posmode != AD_POS_SINGLE)
         return fail(c, AD_EINVAL, "launch.posmode must be AD_POS_HILO or AD_POS_SINGLE");
     if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
-    if (L.fused != 0 && L.fused != 1) return fail(c, AD_EINVAL, "launch.fused must be 0 or 1");
+    if (L.fused < 0 || L.fused > 2) return fail(c, AD_EINVAL, "launch.fused must be 0, 1 or 2");
     if (L.fused) {
         if (c->p.precision != AD_FP32C || c->p.steric_k != 0.0)
             return fail(c, AD_EINVAL, "launch.fused needs AD_FP32C and no steric forces");
-        if (ad::fused_lds_bytes(c->maxNb, L.posmode == AD_POS_HILO, c->nsys > 1 ? 4 : 16) > ad::FUSED_LDS_MAX)
+        const int hilo = L.posmode == AD_POS_HILO;
+        const int lds = L.fused == 2 ? ad::fused_wide_lds_bytes(c->maxNb, hilo)
+                                     : ad::fused_lds_bytes(c->maxNb, hilo, c->nsys > 1 ? 4 : 16);
+        if (lds > ad::FUSED_LDS_MAX)
             return fail(c, AD_EINVAL, "launch.fused: a system of %d spheres does not fit in LDS with this "
                         "position mode", c->maxNb);
     }
@@ -201,6 +204,7 @@ static ad::Shape shape_of(const ad_ctx* c) {
     sh.wj = c->launch.wj;
     sh.ipl = c->launch.ipl;
     sh.split = c->launch.posmode == AD_POS_HILO ? 1 : 0;
+    sh.fused = c->launch.fused;
     sh.steric = uses_lists(c) ? 1 : 0;
     sh.rpy = c->p.tensor == AD_RPY ? 1 : 0;
     return sh;
@@ -289,17 +293,19 @@ static void build_items(ad_ctx* c) {
         }
     }
     c->npart = pb;
-    /* fused stages of an ensemble: one item per 16-target block of a system,
+    /* fused stages: one item per target block of a system (16 targets for an
+     * ensemble in the first form, 64 in the wide form, for one system too),
      * longest system first */
     c->fitems.clear();
-    if (c->launch.fused && c->nsys > 1) {
+    if ((c->launch.fused == 1 && c->nsys > 1) || c->launch.fused == 2) {
+        const int blk = c->launch.fused == 2 ? ad::FW_I : 16;
         for (int b = 0; b < c->nsys; ++b) {
             const int Nb = 2 * c->S[b];
-            for (int i = 0; i < Nb; i += 16) {
+            for (int i = 0; i < Nb; i += blk) {
                 Item it{};
                 it.sys = b;
                 it.i0 = c->off[b] + i;
-                it.ni = std::min(16, Nb - i);
+                it.ni = std::min(blk, Nb - i);
                 it.ioff = c->off[b];
                 it.Nb = Nb;
                 c->fitems.push_back(it);

@@ -155,7 +155,9 @@ def test_fused_stage_launch_rules():
         assert P.ad_get_launch(ctx)["fused"] == 1
         P.ad_set_launch(ctx, fused=1, posmode=1)
         with pytest.raises(P.ADError):
-            P.ad_set_launch(ctx, fused=2)
+            P.ad_set_launch(ctx, fused=3)
+        with pytest.raises(P.ADError):
+            P.ad_set_launch(ctx, fused=-1)
     finally:
         P.ad_destroy(ctx)
     ok = P.ad_create(P.make_params(Params(), "fp32c"), [3392])      # 6784 spheres
@@ -178,6 +180,47 @@ def test_fused_stage_launch_rules():
         try:
             with pytest.raises(P.ADError):
                 P.ad_set_launch(ctx, fused=1, posmode=2 if prec == "fp32c" else 0)
+        finally:
+            P.ad_destroy(ctx)
+
+
+def test_wide_fused_stage_launch_rules():
+    """launch.fused = 2 (64 targets per work-group): the same rules as the
+    first form, with sources padded to 4 instead of 4 x waves, so systems of
+    up to 6824 spheres single-float and 4548 hi/lo fit; one system or an
+    ensemble; the work list holds one item per 64-target block."""
+    for sizes in ([2048], [64, 32, 5], [16, 400, 3, 27]):
+        ctx = P.ad_create(P.make_params(Params(), "fp32c"), sizes)
+        try:
+            for posmode in (1, 2):
+                P.ad_set_launch(ctx, fused=2, posmode=posmode)
+                assert P.ad_get_launch(ctx)["fused"] == 2
+            P.ad_set_launch(ctx, fused=1, posmode=2)
+            P.ad_set_launch(ctx, fused=2, posmode=2)
+            P.ad_set_launch(ctx, fused=0)
+        finally:
+            P.ad_destroy(ctx)
+    ok = P.ad_create(P.make_params(Params(), "fp32c"), [3412])      # 6824 spheres
+    try:
+        P.ad_set_launch(ok, fused=2, posmode=2)
+        with pytest.raises(P.ADError):
+            P.ad_set_launch(ok, fused=1, posmode=2)                    # 16-wave form: 6784 at most
+        with pytest.raises(P.ADError):
+            P.ad_set_launch(ok, fused=2, posmode=1)
+    finally:
+        P.ad_destroy(ok)
+    hl = P.ad_create(P.make_params(Params(), "fp32c"), [2274])       # 4548 spheres
+    try:
+        P.ad_set_launch(hl, fused=2, posmode=1)
+    finally:
+        P.ad_destroy(hl)
+    for prec, sizes, params in (("fp64", [64], Params()), ("fp64_dense", [64], Params()),
+                                ("fp32c", [3414], Params()), ("fp32c", [10, 3414], Params()),
+                                ("fp32c", [64, 8], Params(steric_k=100.0, steric_r=2.0))):
+        ctx = P.ad_create(P.make_params(params, prec), sizes)
+        try:
+            with pytest.raises(P.ADError):
+                P.ad_set_launch(ctx, fused=2, posmode=2 if prec == "fp32c" else 0)
         finally:
             P.ad_destroy(ctx)
 

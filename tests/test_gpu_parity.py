@@ -688,6 +688,75 @@ def test_fused_stage_deterministic_resumable_and_noise(oracle):
     assert np.abs(s.get_state()[0].cpu().numpy() - Xo).max() <= 1e-7
 
 
+WIDE_SINGLE = {"ipl": 1, "jchunk": 128, "wg": 64, "wj": 1, "posmode": 2, "fused": 2}
+WIDE_HILO = dict(WIDE_SINGLE, posmode=1)
+
+
+@pytest.mark.parametrize("launch", [WIDE_SINGLE, WIDE_HILO])
+@pytest.mark.parametrize("integrator,tensor", [("rk4", "oseen"), ("heun", "oseen"), ("rk4", "rpy")])
+def test_wide_fused_stage_ensemble_matches_oracle(oracle, launch, integrator, tensor):
+    """The wide fused stage (64 targets per work-group, one per lane) over
+    uneven systems, from 1 dumbbell to blocks with a ragged last block, with a
+    system not a multiple of 4 spheres long in its sources: 300 steps within
+    1e-6 of the oracle per system, relative to the displacement, and within
+    1e-6 of the two-kernel path."""
+    _torch()
+    sizes = np.array([1, 16, 120, 3, 57, 64, 33, 90, 200], dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    say(f"wide fused ensemble posmode {launch['posmode']} {integrator} {tensor}")
+    out = {}
+    for name, L in (("wide", launch), ("two", dict(launch, fused=0))):
+        s = P.Simulator(ens.params, sizes, precision="fp32c", integrator=integrator, tensor=tensor, launch=L,
+                        graph=True)
+        assert s.launch["fused"] == L["fused"]
+        s.set_state(ens.X, ens.phi)
+        _, _, code = s.run(300, 0)
+        assert code == 0
+        out[name] = s.get_state()[0].cpu().numpy()
+    Xo, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 300, S_per_sys=sizes,
+                             integrator=1 if integrator == "heun" else 0, tensor=1 if tensor == "rpy" else 0)
+    off = ens.sphere_offsets
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        e = relerr(out["wide"][sl] - ens.X[sl], Xo[sl] - ens.X[sl])
+        e2 = relerr(out["wide"][sl] - ens.X[sl], out["two"][sl] - ens.X[sl])
+        assert e <= 1e-6 and e2 <= 1e-6, (b, e, e2)
+
+
+@pytest.mark.parametrize("S,posmode", [(300, 2), (3412, 2), (2274, 1)])
+def test_wide_fused_stage_single_system(oracle, S, posmode):
+    """The wide form on one system, up to the largest it takes (6824 spheres
+    single-float, 4548 hi/lo): two steps (ten for the small one) against the
+    oracle, relative to the displacement."""
+    _torch()
+    sus = make_single(S, 280.0 if S > 1000 else 120.0, 43)
+    n = 10 if S < 1000 else 2
+    say(f"wide fused single system N = {2 * S}, posmode {posmode}")
+    s = P.Simulator(sus.params, [S], precision="fp32c", launch=dict(WIDE_SINGLE, posmode=posmode), graph=True)
+    s.set_state(sus.X, sus.phi)
+    _, _, code = s.run(n, 0)
+    assert code == 0
+    Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, n)
+    e = relerr(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X)
+    say(f"  displacement rel err {e:.2e}")
+    assert e <= 1e-6
+
+
+def test_wide_fused_stage_deterministic_and_resumable():
+    """Two runs give the same bits; split step calls equal one call."""
+    _torch()
+    ens = make_ensemble(nsys=12, sizes=np.array([16, 400, 3, 27, 64, 5, 120, 33, 250, 8, 77, 190], dtype=np.int32))
+    out = []
+    for calls in ((200,), (200,), (70, 130)):
+        s = P.Simulator(ens.params, ens.S_per_sys, precision="fp32c", launch=WIDE_SINGLE, graph=True)
+        s.set_state(ens.X, ens.phi)
+        for n in calls:
+            _, _, code = s.run(n, 0)
+            assert code == 0
+        out.append(s.get_state()[0].cpu().numpy())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
 def test_heun_noise_deterministic_and_resumable():
     _torch()
     sus = make_single(50, 40.0, 5)
