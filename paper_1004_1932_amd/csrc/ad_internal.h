@@ -85,11 +85,11 @@ struct Dev {
     const Item* items;  /* [nitems] */
     float4* pA;         /* FP32C pack read by this stage: (hi.x, hi.y, hi.z, F.x) */
     float4* pB;         /* FP32C pack: (lo.x, lo.y, lo.z, F.y) */
-    float* pC;          /* FP32C pack: F.z */
+    float2* pC;         /* FP32C pack: (F.y, F.z) */
     double2* pD;        /* FP64 pack: 3 double2 per sphere (x,y)(z,Fx)(Fy,Fz) */
     float4* pA2;        /* the packs the epilogue writes for the next stage */
     float4* pB2;
-    float* pC2;
+    float2* pC2;
     double2* pD2;
     double* part;       /* partial sums */
     double* H;          /* dense mode: per system the 3Nb x 3Nb pair tensor, column-major */

@@ -158,7 +158,8 @@ __device__ double gauss_component(unsigned long long seed, int i, long long n, i
 /* FP32C pack of sphere i at stage position y with spring force f, its
  * dumbbell partner at yp with force fp: u0 = self term plus the partner's
  * term in FP64 (the pair kernels skip the partner), then the FP32 hi/lo
- * position and force. */
+ * position and force: A = (hi.xyz, Fx), B = (lo.xyz, Fy), C = (Fy, Fz), so
+ * that a reader of single-float positions needs A and C only. */
 __device__ __forceinline__ void store_pack_sphere(const Dev& d, const Coef& c, int i, const double y[3],
                                                   const double yp[3], const double f[3], const double fp[3],
                                                   int nxt) {
@@ -176,7 +177,7 @@ __device__ __forceinline__ void store_pack_sphere(const Dev& d, const Coef& c, i
     for (int a = 0; a < 3; ++a) split_f32(y[a], h[a], l[a]);
     (nxt ? d.pA2 : d.pA)[i] = make_float4(h[0], h[1], h[2], (float)f[0]);
     (nxt ? d.pB2 : d.pB)[i] = make_float4(l[0], l[1], l[2], (float)f[1]);
-    (nxt ? d.pC2 : d.pC)[i] = (float)f[2];
+    (nxt ? d.pC2 : d.pC)[i] = make_float2((float)f[1], (float)f[2]);
 }
 
 __device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const double y0[3],
@@ -525,7 +526,7 @@ __device__ __forceinline__ void load_tile_entry(const Dev& d, int t0, int jend, 
     if (t0 + t < jend) {
         A = d.pA[t0 + t];
         B = d.pB[t0 + t];
-        C = d.pC[t0 + t];
+        C = d.pC[t0 + t].y;
     } else {
         A = make_float4(1.0e15f, 1.0e15f, 1.0e15f, 0.f);
         B = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -755,8 +756,8 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
 constexpr int FS_I = 16;
 
 /* One source entry of the fused stage: sphere t0 + t of the pack, or
- * padding (far away and force-free). With single-float positions only the
- * forces' y and z are read beside (x, y, z, Fx). */
+ * padding (far away and force-free). With single-float positions only
+ * A = (x, y, z, Fx) and C = (Fy, Fz) are read, 24 B per source. */
 template <int SPLIT>
 __device__ __forceinline__ void load_stage_entry(const Dev& d, int t0, int jend, int t, float4& A, float4& B,
                                                  float& Fy, float& Fz) {
@@ -765,10 +766,12 @@ __device__ __forceinline__ void load_stage_entry(const Dev& d, int t0, int jend,
         if (SPLIT) {
             B = d.pB[t0 + t];
             Fy = B.w;
+            Fz = d.pC[t0 + t].y;
         } else {
-            Fy = reinterpret_cast<const float*>(d.pB)[4 * (t0 + t) + 3];
+            const float2 c = d.pC[t0 + t];
+            Fy = c.x;
+            Fz = c.y;
         }
-        Fz = d.pC[t0 + t];
     } else {
         A = make_float4(1.0e15f, 1.0e15f, 1.0e15f, 0.f);
         B = make_float4(0.f, 0.f, 0.f, 0.f);

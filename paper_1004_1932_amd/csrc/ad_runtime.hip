@@ -356,11 +356,11 @@ static Layout layout(const ad_ctx* c) {
     const bool f32 = c->p.precision == AD_FP32C;
     L.pA = take(f32 ? N * 16 : 0);
     L.pB = take(f32 ? N * 16 : 0);
-    L.pC = take(f32 ? N * 4 : 0);
+    L.pC = take(f32 ? N * 8 : 0);
     L.pD = take(f32 ? 0 : 3 * N * 16);
     L.pA2 = take(f32 ? N * 16 : 0);
     L.pB2 = take(f32 ? N * 16 : 0);
-    L.pC2 = take(f32 ? N * 4 : 0);
+    L.pC2 = take(f32 ? N * 8 : 0);
     L.pD2 = take(f32 ? 0 : 3 * N * 16);
     L.part = take((size_t)c->npart * 8);
     L.tab = take((size_t)kRing * 8 * 8);
@@ -401,11 +401,11 @@ static void make_dev(ad_ctx* c) {
     d.items = reinterpret_cast<const Item*>(b + L.items);
     d.pA = reinterpret_cast<float4*>(b + L.pA);
     d.pB = reinterpret_cast<float4*>(b + L.pB);
-    d.pC = reinterpret_cast<float*>(b + L.pC);
+    d.pC = reinterpret_cast<float2*>(b + L.pC);
     d.pD = reinterpret_cast<double2*>(b + L.pD);
     d.pA2 = reinterpret_cast<float4*>(b + L.pA2);
     d.pB2 = reinterpret_cast<float4*>(b + L.pB2);
-    d.pC2 = reinterpret_cast<float*>(b + L.pC2);
+    d.pC2 = reinterpret_cast<float2*>(b + L.pC2);
     d.pD2 = reinterpret_cast<double2*>(b + L.pD2);
     d.part = reinterpret_cast<double*>(b + L.part);
     d.tab = reinterpret_cast<const double*>(b + L.tab);
