@@ -25,6 +25,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kTabSteps = 4096;          /* steps per table chunk */
+constexpr int kGraphSteps = 16;          /* steps per graph launch in runs of steps */
 constexpr int kRing = 2 * kTabSteps;     /* table entries (two chunks) */
 
 thread_local std::string g_create_error;
@@ -73,10 +74,13 @@ struct ad_ctx {
     hipEvent_t tab_event = nullptr;
     bool tab_event_live = false;
 
-    /* graph of one step */
+    /* graphs of one step and of kGraphSteps steps: one graph launch costs
+     * several microseconds, so runs of steps replay the longer graph */
     bool use_graph = false;
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_run_exec = nullptr;
+    hipGraph_t graph_run = nullptr;
     hipStream_t capture_stream = nullptr;
 
     /* pair-kernel timing */
@@ -430,8 +434,12 @@ static void make_dev(ad_ctx* c) {
 static void drop_graph(ad_ctx* c) {
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->graph_run_exec) (void)hipGraphExecDestroy(c->graph_run_exec);
+    if (c->graph_run) (void)hipGraphDestroy(c->graph_run);
     c->graph_exec = nullptr;
     c->graph = nullptr;
+    c->graph_run_exec = nullptr;
+    c->graph_run = nullptr;
 }
 
 /* upload the work list and the per-system tables (synchronous) */
@@ -575,11 +583,11 @@ static int launch_step_kernels(ad_ctx* c, hipStream_t st) {
     return AD_OK;
 }
 
-static int ensure_graph(ad_ctx* c) {
-    if (c->graph_exec) return AD_OK;
-    if (!c->capture_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+/* capture nsteps consecutive steps into *graph / *exec */
+static int capture_steps(ad_ctx* c, int nsteps, hipGraph_t* graph, hipGraphExec_t* exec) {
     HIPCHECK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-    int rc = launch_step_kernels(c, c->capture_stream);
+    int rc = AD_OK;
+    for (int k = 0; k < nsteps && rc == AD_OK; ++k) rc = launch_step_kernels(c, c->capture_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
     if (rc != AD_OK) {
@@ -587,9 +595,19 @@ static int ensure_graph(ad_ctx* c) {
         return rc;
     }
     if (e != hipSuccess) return fail(c, AD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    c->graph = g;
-    HIPCHECK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    *graph = g;
+    HIPCHECK(c, hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
     return AD_OK;
+}
+
+static int ensure_graph(ad_ctx* c) {
+    if (c->graph_exec && c->graph_run_exec) return AD_OK;
+    drop_graph(c);
+    if (!c->capture_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    int rc = capture_steps(c, 1, &c->graph, &c->graph_exec);
+    if (rc == AD_OK) rc = capture_steps(c, kGraphSteps, &c->graph_run, &c->graph_run_exec);
+    if (rc != AD_OK) drop_graph(c);
+    return rc;
 }
 
 static int advance(ad_ctx* c, long long nsteps, int record_every, double* centres, double* com, hipStream_t st) {
@@ -620,14 +638,23 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
         const int chunk = (int)std::min<long long>(nsteps - done, kTabSteps);
         int rc = fill_table(c, c->step + done, chunk, st);
         if (rc != AD_OK) return rc;
-        for (int q = 0; q < chunk; ++q) {
-            if (graph) {
-                HIPCHECK(c, hipGraphLaunch(c->graph_exec, st));
+        for (int q = 0; q < chunk;) {
+            /* steps left before the next record point or the chunk's end */
+            long long room = chunk - q;
+            if (record_every > 0) room = std::min<long long>(room, record_every - (done + q) % record_every);
+            if (graph && room >= kGraphSteps) {
+                HIPCHECK(c, hipGraphLaunch(c->graph_run_exec, st));
+                q += kGraphSteps;
             } else {
-                rc = launch_step_kernels(c, st);
-                if (rc != AD_OK) return rc;
+                if (graph) {
+                    HIPCHECK(c, hipGraphLaunch(c->graph_exec, st));
+                } else {
+                    rc = launch_step_kernels(c, st);
+                    if (rc != AD_OK) return rc;
+                }
+                q += 1;
             }
-            const long long n = done + q + 1;
+            const long long n = done + q;
             if (record_every > 0 && n % record_every == 0) {
                 double* cp = centres ? centres + rec * 3LL * c->Stot : nullptr;
                 double* mp = com ? com + rec * 3LL * c->nsys : nullptr;

@@ -261,6 +261,36 @@ def test_graph_equals_direct_launches(oracle):
     assert np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("launch", [dict(wg=256, wj=4, ipl=1, jchunk=256), FUSED_SINGLE,
+                                    {"ipl": 1, "jchunk": 128, "wg": 64, "wj": 1, "posmode": 2, "fused": 2}])
+def test_graph_runs_equal_direct_launches_with_records(launch):
+    """Runs of steps replay a 16-step graph, single steps the one-step graph,
+    and neither crosses a record point: for step counts and record intervals
+    that are not multiples of 16, records and final state equal those of
+    direct launches bit for bit."""
+    _torch()
+    sizes = [3, 120, 64, 17] if launch.get("fused") == 2 else [150]
+    ens = make_ensemble(nsys=len(sizes), sizes=np.array(sizes, dtype=np.int32))
+    out = []
+    for graph in (False, True):
+        s = P.Simulator(ens.params, sizes, precision="fp32c", graph=graph, launch=launch)
+        s.set_state(ens.X, ens.phi)
+        recs = []
+        for nsteps, every in ((100, 7), (37, 0), (64, 16), (90, 23), (5, 5)):
+            cen, com, code = s.run(nsteps, every)
+            assert code == 0
+            if every:
+                recs.append((cen.cpu().numpy(), com.cpu().numpy()))
+        X, t0, step = s.get_state()
+        assert step == 296
+        out.append((recs, X.cpu().numpy()))
+    (r0, x0), (r1, x1) = out
+    assert np.array_equal(x0, x1)
+    for (c0, m0), (c1, m1) in zip(r0, r1):
+        assert np.array_equal(c0, c1) and np.array_equal(m0, m1)
+    assert [len(c) for c, _ in r0] == [14, 4, 3, 1]
+
+
 @pytest.mark.parametrize("launch", [dict(wg=256, wj=4, ipl=1, jchunk=256), dict(wg=256, wj=1, ipl=2, jchunk=512),
                                     dict(wg=64, wj=1, ipl=4, jchunk=128, posmode=2),
                                     dict(wg=256, wj=4, ipl=4, jchunk=1000, posmode=2)])
