@@ -116,6 +116,9 @@ typedef struct ad_launch {
                          2: the same with 64 target spheres per 4-wave work-group, one per
                          lane, for ensembles of small systems (at most 6824 single-float or
                          4548 hi/lo spheres per system);
+                         3: 16 target spheres per work-group whose waves stream their share of
+                         the sources through a small LDS slot each (AD_FP32C, no steric
+                         forces, any system size; sources are padded to a multiple of 1024);
                          0: pair kernel and epilogue as two kernels */
 } ad_launch;
 

@@ -68,6 +68,8 @@ def candidates(N: int, ensemble: bool):
             out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=2))
         else:
             out.append(dict(wg=256, wj=4, ipl=1, jchunk=256, posmode=posmode, fused=1))
+            if N >= 1024:  # the streamed form pads every system to 1024 sources
+                out.append(dict(wg=256, wj=4, ipl=1, jchunk=256, posmode=posmode, fused=3))
     uniq = []
     for c in out:
         if c not in uniq:

@@ -142,7 +142,8 @@ __device__ __forceinline__ void advance_slots(const Dev& d, const Epi& e) {
 struct Shape {
     int wg, wj, ipl, split;
     int fused;  /* 0: pair kernel + epilogue; 1: stage kernel, 16 targets per
-                   work-group; 2: stage kernel, 64 targets per work-group */
+                   work-group; 2: stage kernel, 64 targets per work-group; 3:
+                   stage kernel, 16 targets, sources streamed per wave */
     int rpy;    /* pair tensor with the RPY-Mazur correction */
     int steric; /* FP32C: record steric candidates while summing */
 };
@@ -195,6 +196,15 @@ __host__ __device__ inline int fused_wide_lds_bytes(int n, int split) {
     const int np = (n + 3) / 4 * 4;
     const int b = np * (split ? 36 : 24);
     const int red = 4 * FW_I * 6 * 4 + FW_I * 3 * 8 + 16;
+    return b > red ? b : red;
+}
+/* target spheres per work-group of the streamed fused stage */
+constexpr int FT_I = 16;
+/* LDS bytes of a streamed fused work-group: 16 waves x 2 slots x 64 source
+ * entries, or the combination area if larger */
+__host__ __device__ inline int fused_stream_lds_bytes(int split) {
+    const int b = 16 * 2 * 64 * (split ? 36 : 24);
+    const int red = 16 * 16 * 6 * 4 + 16 * 3 * 8 + 16;
     return b > red ? b : red;
 }
 /* allow the fused kernels FUSED_LDS_MAX bytes of dynamic LDS (host call,

@@ -1151,6 +1151,212 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
     }
 }
 
+/* Streamed form of the fused stage (ad_launch.fused = 3). The work-group of
+ * 16 waves owns TI = FT_I = 16 target spheres, like k_stage_fused (TI = 8,
+ * which lets two work-groups share a compute unit, measured slower at
+ * N = 4096: every work-group reads every source). Each of its source splits
+ * (wave w, lane group g of TI lanes) owns a contiguous range of Q sources
+ * (Q a multiple of TI). A wave streams its ranges through a double-buffered LDS
+ * slot of its own, TI sources per split at a time, one entry per lane: the
+ * next chunk's loads are in flight while the current chunk is summed, no
+ * work-group barrier separates loading from summing, and no system is too
+ * large for LDS. Lane (w, g, t) sums target t over its split's range in
+ * ascending order, folding into (hi, lo) every 32 sources; the combination
+ * and the closing update are those of k_stage_fused. LDS ops of one wave
+ * complete in order, so the slot needs no barrier: a chunk is written after
+ * the wave's reads of the chunk it replaces and read after its own writes.
+ * (Interleaving the groups' entries within a slot measured slower.) */
+template <int SPLIT, int RPY, int TI>
+__global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
+    constexpr int NW = 16;
+    constexpr int G = 64 / TI;    /* lane groups (splits) per wave */
+    constexpr int JS = NW * G;    /* source splits */
+    constexpr int FOLD = 32 / TI; /* chunks per (hi, lo) fold */
+    extern __shared__ float4 fs_lds[];
+    const int N = d.Ntot;
+    const int tid = threadIdx.x;
+    int i0, off, Nb;
+    if (d.nfitems == 0) {
+        i0 = blockIdx.x * TI;
+        off = 0;
+        Nb = N;
+    } else {
+        const Item it = d.fitems[blockIdx.x];
+        i0 = it.i0;
+        off = it.ioff;
+        Nb = it.Nb;
+    }
+    const int ni = min(TI, off + Nb - i0);
+    const int Q = (Nb + JS * TI - 1) / (JS * TI) * TI; /* sources per split */
+    const int K = Q / TI;                              /* chunks per split */
+    /* per wave and buffer 64 entries: A = (x, y, z, Fx); with hi/lo
+     * B = (lo.xyz, Fy) and Fz, else (Fy, Fz) */
+    float4* sA = fs_lds;
+    float4* sB = fs_lds + NW * 128;
+    float* sC = reinterpret_cast<float*>(fs_lds + 2 * NW * 128);
+    float2* sF = reinterpret_cast<float2*>(fs_lds + NW * 128);
+    const long long step = (e.stage == 0) ? d.ctl->slot[0] : d.ctl->slot[1];
+    /* inputs of the closing update, loaded first */
+    double u0 = 0.0, xv = 0.0, rv = 0.0;
+    if (tid < 3 * ni) {
+        const int tt = tid / 3, a = tid - 3 * tt;
+        const int o = a * N + i0 + tt;
+        u0 = d.U0[o];
+        xv = d.X[o];
+        if (e.stage > 0) rv = d.R[o];
+    }
+    const int w = tid >> 6, l = tid & 63, t = l % TI, g = l / TI;
+    const int sp = G * w + g; /* this lane's source split */
+    const int i = i0 + t;
+    float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
+    if (t < ni) {
+        const float4 A = d.pA[i];
+        hx = A.x; hy = A.y; hz = A.z;
+        if (SPLIT) {
+            const float4 B = d.pB[i];
+            lx = B.x; ly = B.y; lz = B.z;
+        }
+    }
+    const int di = (i - off) >> 1;
+    /* the chunk holding the work-group's own spheres: split so, chunk ko */
+    const int so = (i0 - off) / Q, ko = ((i0 - off) - so * Q) / TI;
+    const bool own_wave = so / G == w;
+
+    float4 eA, eB;
+    float eFy, eFz;
+    auto fetch = [&](int k) { load_stage_entry<SPLIT>(d, off, off + Nb, sp * Q + k * TI + t, eA, eB, eFy, eFz); };
+    auto put = [&](int buf) {
+        const int x = (w * 2 + buf) * 64 + g * TI + t;
+        sA[x] = eA;
+        if (SPLIT) {
+            sB[x] = eB;
+            sC[x] = eFz;
+        } else {
+            sF[x] = make_float2(eFy, eFz);
+        }
+    };
+    fetch(0);
+    put(0);
+    /* wave 0 only: the step slots and this stage's (sin, cos)(omega t) and
+     * phases, whose dependent loads then stall a wave that is not the last
+     * to finish its sums */
+    advance_slots(d, e);
+    double st = 0.0, ct = 0.0;
+    double2 tp = make_double2(0.0, 0.0);
+    if (tid < ni) {
+        const long long row = step % d.ring;
+        st = d.tab[row * 8 + 2 * e.stage];
+        ct = d.tab[row * 8 + 2 * e.stage + 1];
+        tp = d.phitrig[(i0 >> 1) + (tid >> 1)];
+    }
+
+    const float crr = e.c.crr;
+    float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+    auto term = [&](int x, int j, bool masked, float& px, float& py, float& pz) {
+        const float4 Aj = sA[x];
+        float Fy, Fz, qx = 0.f, qy = 0.f, qz = 0.f;
+        if (SPLIT) {
+            const float4 Bj = sB[x];
+            qx = Bj.x; qy = Bj.y; qz = Bj.z;
+            Fy = Bj.w;
+            Fz = sC[x];
+        } else {
+            const float2 f = sF[x];
+            Fy = f.x;
+            Fz = f.y;
+        }
+        float rx, ry, rz;
+        if (SPLIT) {
+            rx = (hx - Aj.x) + (lx - qx);
+            ry = (hy - Aj.y) + (ly - qy);
+            rz = (hz - Aj.z) + (lz - qz);
+        } else {
+            rx = hx - Aj.x;
+            ry = hy - Aj.y;
+            rz = hz - Aj.z;
+        }
+        const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+        float ir = __builtin_amdgcn_rsqf(r2);
+        if (masked && (j >> 1) == di) ir = 0.f;
+        pair_term<RPY>(ir, rx, ry, rz, Aj.w, Fy, Fz, crr, px, py, pz);
+    };
+    float px = 0.f, py = 0.f, pz = 0.f;
+    for (int k = 0; k < K; ++k) {
+        const int buf = k & 1;
+        if (k + 1 < K) fetch(k + 1);
+        const int x0 = (w * 2 + buf) * 64 + g * TI;
+        const int j0 = sp * Q + k * TI;
+        if (own_wave && k == ko) {
+            for (int v = 0; v < TI; ++v) term(x0 + v, j0 + v, true, px, py, pz);
+        } else {
+#pragma unroll 4
+            for (int v = 0; v < TI; ++v) term(x0 + v, j0 + v, false, px, py, pz);
+        }
+        if ((k + 1) % FOLD == 0 || k + 1 == K) {
+            two_sum_acc(ax, bx, px);
+            two_sum_acc(ay, by, py);
+            two_sum_acc(az, bz, pz);
+            px = py = pz = 0.f;
+        }
+        if (k + 1 < K) put(buf ^ 1);
+    }
+
+    /* combine the partial sums of each target as k_stage_fused does: the G
+     * groups of a wave by shuffles, then the waves through LDS in a tree */
+    auto combine = [](float& hi, float& lo, float oh, float ol) {
+        const float s = hi + oh;
+        const float bb = s - hi;
+        const float err = (hi - (s - bb)) + (oh - bb);
+        hi = s;
+        lo = (lo + ol) + err;
+    };
+#pragma unroll
+    for (int sh = TI; sh < 64; sh *= 2) {
+        const float oax = __shfl_xor(ax, sh), obx = __shfl_xor(bx, sh);
+        const float oay = __shfl_xor(ay, sh), oby = __shfl_xor(by, sh);
+        const float oaz = __shfl_xor(az, sh), obz = __shfl_xor(bz, sh);
+        combine(ax, bx, oax, obx);
+        combine(ay, by, oay, oby);
+        combine(az, bz, oaz, obz);
+    }
+    __syncthreads(); /* the source slots are no longer read */
+    float* red = reinterpret_cast<float*>(fs_lds);                /* [NW waves][TI][6] */
+    double* ys = reinterpret_cast<double*>(fs_lds) + NW * TI * 3; /* [TI][3] stage positions */
+    int* badf = reinterpret_cast<int*>(ys + TI * 3);
+    if (g == 0) {
+        float* r = red + (w * TI + t) * 6;
+        r[0] = ax; r[1] = bx; r[2] = ay; r[3] = by; r[4] = az; r[5] = bz;
+    }
+    if (tid == 0) *badf = 0;
+    __syncthreads();
+    if (tid < 3 * ni) {
+        const int tt = tid / 3, a = tid - 3 * tt;
+        float hs[NW], ls[NW];
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            const float* r = red + (ww * TI + tt) * 6 + 2 * a;
+            hs[ww] = r[0];
+            ls[ww] = r[1];
+        }
+#pragma unroll
+        for (int st2 = 1; st2 < NW; st2 *= 2)
+#pragma unroll
+            for (int ww = 0; ww < NW; ww += 2 * st2) combine(hs[ww], ls[ww], hs[ww + st2], ls[ww + st2]);
+        const int ii = i0 + tt;
+        const double k = u0 + e.c.co * ((double)hs[0] + (double)ls[0]);
+        if (!isfinite(k)) *badf = 1;
+        ys[tt * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv, rv, step);
+    }
+    __syncthreads();
+    if (tid == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+    if (tid < ni) {
+        const int q = tid >> 1, h = tid & 1;
+        double f[2][3];
+        spring_forces(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
+        store_pack_sphere(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1], 1);
+    }
+}
+
 /* FP64: the sum in ascending j with the plain operation order
  *   r2 = (rx*rx + ry*ry) + rz*rz; ir = 1/sqrt(r2); fr = (rx*Fx + ry*Fy) + rz*Fz;
  *   t = fr/r2; acc = acc + ir*(F + t*r)
@@ -1494,8 +1700,24 @@ static hipError_t go_wide(const Dev& d, const Epi& e, int maxNb, hipStream_t s, 
     return hipGetLastError();
 }
 
+template <int SPLIT, int RPY>
+static hipError_t go_stream(const Dev& d, const Epi& e, hipStream_t s, const Timing& tm) {
+    const int lds = fused_stream_lds_bytes(SPLIT);
+    const dim3 grid(d.nfitems ? d.nfitems : (d.Ntot + FT_I - 1) / FT_I);
+    auto kern = k_stage_stream<SPLIT, RPY, FT_I>;
+    if (tm.start)
+        hipExtLaunchKernelGGL(kern, grid, dim3(1024), lds, s, tm.start, tm.stop, 0, d, e);
+    else
+        hipLaunchKernelGGL(kern, grid, dim3(1024), lds, s, d, e);
+    return hipGetLastError();
+}
+
 hipError_t prepare_fused() {
-    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_wide<0, 0>),
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_stream<0, 0, FT_I>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, FT_I>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, FT_I>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, FT_I>),
+                             reinterpret_cast<const void*>(&k_stage_wide<0, 0>),
                              reinterpret_cast<const void*>(&k_stage_wide<0, 1>),
                              reinterpret_cast<const void*>(&k_stage_wide<1, 0>),
                              reinterpret_cast<const void*>(&k_stage_wide<1, 1>),
@@ -1524,7 +1746,12 @@ hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, int maxNb, 
         if (sh.split) return sh.rpy ? go_wide<1, 1>(d, e, maxNb, s, tm0) : go_wide<1, 0>(d, e, maxNb, s, tm0);
         return sh.rpy ? go_wide<0, 1>(d, e, maxNb, s, tm0) : go_wide<0, 0>(d, e, maxNb, s, tm0);
     }
-    if (sh.fused != 1 || (d.nsys > 1) != (d.nfitems > 0)) return hipErrorInvalidValue;
+    if ((d.nsys > 1) != (d.nfitems > 0)) return hipErrorInvalidValue;
+    if (sh.fused == 3) {
+        if (sh.split) return sh.rpy ? go_stream<1, 1>(d, e, s, tm0) : go_stream<1, 0>(d, e, s, tm0);
+        return sh.rpy ? go_stream<0, 1>(d, e, s, tm0) : go_stream<0, 0>(d, e, s, tm0);
+    }
+    if (sh.fused != 1) return hipErrorInvalidValue;
     const int nw = d.nsys > 1 ? 4 : 16;
     if (fused_lds_bytes(maxNb, sh.split, nw) > FUSED_LDS_MAX) return hipErrorInvalidValue;
     const Timing tm{ev_start, ev_stop};

@@ -185,13 +185,14 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (c->p.precision == AD_FP32C && L.posmode != AD_POS_HILO && L.posmode != AD_POS_SINGLE)
         return fail(c, AD_EINVAL, "launch.posmode must be AD_POS_HILO or AD_POS_SINGLE");
     if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
-    if (L.fused < 0 || L.fused > 2) return fail(c, AD_EINVAL, "launch.fused must be 0, 1 or 2");
+    if (L.fused < 0 || L.fused > 3) return fail(c, AD_EINVAL, "launch.fused must be 0, 1, 2 or 3");
     if (L.fused) {
         if (c->p.precision != AD_FP32C || c->p.steric_k != 0.0)
             return fail(c, AD_EINVAL, "launch.fused needs AD_FP32C and no steric forces");
         const int hilo = L.posmode == AD_POS_HILO;
-        const int lds = L.fused == 2 ? ad::fused_wide_lds_bytes(c->maxNb, hilo)
-                                     : ad::fused_lds_bytes(c->maxNb, hilo, c->nsys > 1 ? 4 : 16);
+        const int lds = L.fused == 3   ? ad::fused_stream_lds_bytes(hilo)
+                        : L.fused == 2 ? ad::fused_wide_lds_bytes(c->maxNb, hilo)
+                                       : ad::fused_lds_bytes(c->maxNb, hilo, c->nsys > 1 ? 4 : 16);
         if (lds > ad::FUSED_LDS_MAX)
             return fail(c, AD_EINVAL, "launch.fused: a system of %d spheres does not fit in LDS with this "
                         "position mode", c->maxNb);
@@ -298,11 +299,11 @@ static void build_items(ad_ctx* c) {
     }
     c->npart = pb;
     /* fused stages: one item per target block of a system (16 targets for an
-     * ensemble in the first form, 64 in the wide form, for one system too),
-     * longest system first */
+     * ensemble in the first and the streamed form, 64 in the wide form, for
+     * one system too), longest system first */
     c->fitems.clear();
-    if ((c->launch.fused == 1 && c->nsys > 1) || c->launch.fused == 2) {
-        const int blk = c->launch.fused == 2 ? ad::FW_I : 16;
+    if (((c->launch.fused == 1 || c->launch.fused == 3) && c->nsys > 1) || c->launch.fused == 2) {
+        const int blk = c->launch.fused == 2 ? ad::FW_I : c->launch.fused == 3 ? ad::FT_I : 16;
         for (int b = 0; b < c->nsys; ++b) {
             const int Nb = 2 * c->S[b];
             for (int i = 0; i < Nb; i += blk) {

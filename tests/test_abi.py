@@ -155,7 +155,7 @@ def test_fused_stage_launch_rules():
         assert P.ad_get_launch(ctx)["fused"] == 1
         P.ad_set_launch(ctx, fused=1, posmode=1)
         with pytest.raises(P.ADError):
-            P.ad_set_launch(ctx, fused=3)
+            P.ad_set_launch(ctx, fused=4)
         with pytest.raises(P.ADError):
             P.ad_set_launch(ctx, fused=-1)
     finally:
@@ -221,6 +221,27 @@ def test_wide_fused_stage_launch_rules():
         try:
             with pytest.raises(P.ADError):
                 P.ad_set_launch(ctx, fused=2, posmode=2 if prec == "fp32c" else 0)
+        finally:
+            P.ad_destroy(ctx)
+
+
+def test_streamed_fused_stage_launch_rules():
+    """launch.fused = 3 (sources streamed per wave): AD_FP32C without steric
+    forces, any system size (no LDS limit), one system or an ensemble."""
+    for sizes in ([2048], [3414], [20000], [64, 32, 5]):
+        ctx = P.ad_create(P.make_params(Params(), "fp32c"), sizes)
+        try:
+            for posmode in (1, 2):
+                P.ad_set_launch(ctx, fused=3, posmode=posmode)
+                assert P.ad_get_launch(ctx)["fused"] == 3
+        finally:
+            P.ad_destroy(ctx)
+    for prec, sizes, params in (("fp64", [64], Params()), ("fp64_tiled", [64], Params()),
+                                ("fp32c", [64, 8], Params(steric_k=100.0, steric_r=2.0))):
+        ctx = P.ad_create(P.make_params(params, prec), sizes)
+        try:
+            with pytest.raises(P.ADError):
+                P.ad_set_launch(ctx, fused=3, posmode=2 if prec == "fp32c" else 0)
         finally:
             P.ad_destroy(ctx)
 

@@ -787,6 +787,77 @@ def test_wide_fused_stage_deterministic_and_resumable():
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
 
 
+STREAM_SINGLE = {"ipl": 1, "jchunk": 256, "wg": 256, "wj": 4, "posmode": 2, "fused": 3}
+STREAM_HILO = dict(STREAM_SINGLE, posmode=1)
+
+
+@pytest.mark.parametrize("launch", [STREAM_SINGLE, STREAM_HILO])
+@pytest.mark.parametrize("integrator,tensor", [("rk4", "oseen"), ("heun", "oseen"), ("rk4", "rpy")])
+def test_streamed_fused_stage_matches_oracle(oracle, launch, integrator, tensor):
+    """The streamed fused stage on single systems from 1 dumbbell to a size
+    that is neither a multiple of the 1024-source padding nor of the 16-target
+    block (its own spheres then fall in different splits and chunks), 200
+    steps: within 1e-6 of the oracle, relative to the displacement, and
+    within 1e-6 of the two-kernel path."""
+    _torch()
+    for S, side in ((1, 10.0), (5, 20.0), (300, 120.0), (1100, 180.0)):
+        sus = make_single(S, side, 51)
+        say(f"streamed {launch['posmode']} {integrator} {tensor} S={S}")
+        out = {}
+        for name, L in (("stream", launch), ("two", dict(launch, fused=0))):
+            s = P.Simulator(sus.params, [S], precision="fp32c", integrator=integrator, tensor=tensor, launch=L,
+                            graph=True)
+            s.set_state(sus.X, sus.phi)
+            _, _, code = s.run(200, 0)
+            assert code == 0
+            out[name] = s.get_state()[0].cpu().numpy()
+        Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 200, integrator=1 if integrator == "heun" else 0,
+                                 tensor=1 if tensor == "rpy" else 0)
+        e = relerr(out["stream"] - sus.X, Xo - sus.X)
+        e2 = relerr(out["stream"] - sus.X, out["two"] - sus.X)
+        say(f"  vs oracle {e:.2e}, vs two-kernel path {e2:.2e}")
+        assert e <= 1e-6 and e2 <= 1e-6
+
+
+@pytest.mark.parametrize("S,posmode", [(2048, 2), (4100, 2), (4100, 1)])
+def test_streamed_fused_stage_large_systems(oracle, S, posmode):
+    """Systems at and beyond the size where every source fits one
+    work-group's LDS (8200 spheres): two steps against the oracle."""
+    _torch()
+    sus = make_single(S, 240.0 * (2 * S / 4096.0) ** (1.0 / 3.0), 53)
+    say(f"streamed N = {2 * S}, posmode {posmode}")
+    s = P.Simulator(sus.params, [S], precision="fp32c", launch=dict(STREAM_SINGLE, posmode=posmode), graph=True)
+    s.set_state(sus.X, sus.phi)
+    _, _, code = s.run(2, 0)
+    assert code == 0
+    Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 2)
+    e = relerr(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X)
+    say(f"  displacement rel err {e:.2e}")
+    assert e <= 1e-6
+
+
+def test_streamed_fused_stage_ensemble_and_determinism(oracle):
+    """An ensemble of uneven systems (16-target work list), 200 steps against
+    the oracle; two runs give the same bits and split calls equal one call."""
+    _torch()
+    sizes = np.array([1, 16, 120, 3, 57, 64, 33, 90, 200], dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    out = []
+    for calls in ((200,), (200,), (70, 130)):
+        s = P.Simulator(ens.params, sizes, precision="fp32c", launch=STREAM_SINGLE, graph=True)
+        s.set_state(ens.X, ens.phi)
+        for n in calls:
+            _, _, code = s.run(n, 0)
+            assert code == 0
+        out.append(s.get_state()[0].cpu().numpy())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    Xo, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 200, S_per_sys=sizes)
+    off = ens.sphere_offsets
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        assert relerr(out[0][sl] - ens.X[sl], Xo[sl] - ens.X[sl]) <= 1e-6, b
+
+
 def test_heun_noise_deterministic_and_resumable():
     _torch()
     sus = make_single(50, 40.0, 5)
