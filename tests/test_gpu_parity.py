@@ -858,6 +858,23 @@ def test_streamed_fused_stage_ensemble_and_determinism(oracle):
         assert relerr(out[0][sl] - ens.X[sl], Xo[sl] - ens.X[sl]) <= 1e-6, b
 
 
+def test_streamed_fused_stage_noise(oracle):
+    """Heun with additive noise through the streamed stage: the GPU follows
+    the oracle's Brownian trajectory (same Philox numbers)."""
+    _torch()
+    sus = make_single(600, 120.0, 57)
+    kT, seed = 0.01, 91
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c", integrator="heun", kT=kT, seed=seed,
+                    launch=STREAM_HILO, graph=True)
+    s.set_state(sus.X, sus.phi)
+    _, _, code = s.run(100, 0)
+    assert code == 0
+    Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 100, integrator=1, kT=kT, seed=seed)
+    Xd, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 100, integrator=1)
+    assert np.abs(Xo - Xd).max() > 1e-3  # the noise matters
+    assert np.abs(s.get_state()[0].cpu().numpy() - Xo).max() <= 1e-7
+
+
 def test_heun_noise_deterministic_and_resumable():
     _torch()
     sus = make_single(50, 40.0, 5)
