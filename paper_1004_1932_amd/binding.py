@@ -152,6 +152,9 @@ def ad_bind_workspace(ctx, ws) -> None:
 
 
 def ad_set_launch(ctx, ipl=0, jchunk=0, wg=0, wj=0, posmode=0, fused=0) -> None:
+    """Launch shape (ad_launch in include/ad.h). fused: 0 pair kernel and
+    epilogue; 1 one stage kernel, every source in LDS; 2 the same with 64
+    targets per work-group; 3 one stage kernel streaming the sources."""
     L = ad_launch(int(ipl), int(jchunk), int(wg), int(wj), int(posmode), int(fused))
     _check(lib().ad_set_launch(ctx, C.byref(L)), ctx)
 
