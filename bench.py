@@ -151,9 +151,10 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--unfused", action="store_true",
                     help="tuned launch with pair kernel and epilogue as two kernels (for profiles of that path)")
-    ap.add_argument("--fused", type=int, choices=(0, 1, 2), default=None,
+    ap.add_argument("--fused", type=int, choices=(0, 1, 2, 3), default=None,
                     help="tuned launch with this stage form (0: two kernels, 1: 16 targets per work-group, "
-                         "2: 64 targets per work-group), for profiles of the form the table did not choose")
+                         "2: 64 targets per work-group, 3: 16 targets per work-group with streamed "
+                         "sources), for profiles of the form the table did not choose")
     ap.add_argument("--counter-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a few steps plus one plain 256 MiB device copy")
     args = ap.parse_args()
