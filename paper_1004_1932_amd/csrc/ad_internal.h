@@ -180,12 +180,12 @@ constexpr int FUSED_LDS_MAX = 160 * 1024; /* the kernel has no static LDS */
 /* LDS bytes of a fused work-group for a system of n spheres: the sources,
  * padded to the 4 nw source splits (36 B each with hi/lo positions, 24 B
  * with single-float), or the combination area it reuses (nw waves x 16
- * targets x 6 floats, 16 x 3 stage positions, a flag) if larger */
+ * targets x 6 floats, 16 x 3 stage positions) if larger */
 __host__ __device__ inline int fused_lds_bytes(int n, int split, int nw) {
     const int js = 4 * nw;
     const int np = (n + js - 1) / js * js;
     const int b = np * (split ? 36 : 24);
-    const int red = nw * 16 * 6 * 4 + 16 * 3 * 8 + 16;
+    const int red = nw * 16 * 6 * 4 + 16 * 3 * 8;
     return b > red ? b : red;
 }
 /* LDS bytes of a wide fused work-group (64 targets, 4 waves): the sources
@@ -201,11 +201,12 @@ __host__ __device__ inline int fused_wide_lds_bytes(int n, int split) {
 /* target spheres per work-group of the streamed fused stage */
 constexpr int FT_I = 16;
 /* LDS bytes of a streamed fused work-group: 16 waves x 2 slots x 64 source
- * entries, or the combination area if larger */
+ * entries, followed by the combination area (16 waves x 16 targets x 6
+ * floats, 16 x 3 stage positions) */
 __host__ __device__ inline int fused_stream_lds_bytes(int split) {
     const int b = 16 * 2 * 64 * (split ? 36 : 24);
-    const int red = 16 * 16 * 6 * 4 + 16 * 3 * 8 + 16;
-    return b > red ? b : red;
+    const int red = 16 * 16 * 6 * 4 + 16 * 3 * 8;
+    return b + red;
 }
 /* allow the fused kernels FUSED_LDS_MAX bytes of dynamic LDS (host call,
  * outside any stream capture) */

@@ -180,6 +180,50 @@ __device__ __forceinline__ void store_pack_sphere(const Dev& d, const Coef& c, i
     (nxt ? d.pC2 : d.pC)[i] = make_float2((float)f[1], (float)f[2]);
 }
 
+/* The closing update of the FP32C stage kernels uses these two forms of
+ * spring_forces and store_pack_sphere: one rsqrt (a few ulp) in place of
+ * each IEEE sqrt and division. In the FP32C path the state stays FP64 and
+ * only the pair sums are FP32, so a relative error near 1e-16 here is far
+ * below theirs (about 1e-7); the FP64 paths keep the IEEE forms, whose
+ * operation order the bitwise parity with the plain sum depends on. With
+ * single-float positions (SPLIT = 0) no stage kernel reads the lo parts, so
+ * B is not written. */
+__device__ __forceinline__ void spring_forces_rs(const Coef& c, const double y0[3], const double y1[3],
+                                                 double sphi, double cphi, double st, double ct,
+                                                 double f0[3], double f1[3]) {
+    /* -k (d - L) n / d = k (L / d - 1) n */
+    const double nx = y1[0] - y0[0], ny = y1[1] - y0[1], nz = y1[2] - y0[2];
+    const double id = rsqrt((nx * nx + ny * ny) + nz * nz);
+    const double L = c.ell + c.lam * (st * cphi + ct * sphi);
+    const double cc = c.k * (L * id - 1.0);
+    f1[0] = cc * nx;
+    f1[1] = cc * ny;
+    f1[2] = cc * nz;
+    f0[0] = -f1[0];
+    f0[1] = -f1[1];
+    f0[2] = -f1[2];
+}
+
+template <int SPLIT>
+__device__ __forceinline__ void store_pack_sphere_rs(const Dev& d, const Coef& c, int i, const double y[3],
+                                                     const double yp[3], const double f[3], const double fp[3]) {
+    const int N = d.Ntot;
+    const double r[3] = {y[0] - yp[0], y[1] - yp[1], y[2] - yp[2]};
+    const double ir = rsqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+    const double ir2 = ir * ir;
+    const double t = ((r[0] * fp[0] + r[1] * fp[1]) + r[2] * fp[2]) * ir2;
+    for (int a = 0; a < 3; ++a) {
+        double u = c.cs * f[a] + c.co * (ir * (fp[a] + t * r[a]));
+        if (c.rpy) u = u + c.cr * ((ir * ir2) * (fp[a] - (3.0 * t) * r[a]));
+        d.U0[a * N + i] = u;
+    }
+    float h[3], l[3];
+    for (int a = 0; a < 3; ++a) split_f32(y[a], h[a], l[a]);
+    d.pA2[i] = make_float4(h[0], h[1], h[2], (float)f[0]);
+    if (SPLIT) d.pB2[i] = make_float4(l[0], l[1], l[2], (float)f[1]);
+    d.pC2[i] = make_float2((float)f[1], (float)f[2]);
+}
+
 __device__ void store_pack(const Dev& d, const Coef& c, int prec, int i0, const double y0[3],
                            const double y1[3], const double f0[3], const double f1[3], int nxt) {
     const int N = d.Ntot;
@@ -746,9 +790,10 @@ __global__ __launch_bounds__(WG) void k_pairs_f32c(Dev d, Epi e, int mode) {
  * TwoSum into a (hi, lo) pair every FS_M sources (32 for one system, 64 for
  * an ensemble). The JS partial sums of a target are combined in a fixed order
  * (two shuffles inside the wave, then the NW waves through LDS in a pairwise
- * tree), and the work-group then does the stage update, next spring forces
- * and next pack of its 8 dumbbells, as the epilogue does: a stage needs no
- * partial sums in HBM and no second launch. Only the one term of the
+ * tree), and wave 0 then does the stage update, next spring forces and next
+ * pack of the 8 dumbbells (as the epilogue does, in the rsqrt forms) with no
+ * further barrier: a stage needs no partial sums in HBM and no second
+ * launch. Only the one term of the
  * JS-source block that holds the work-group's own dumbbells needs the
  * self/partner mask. A single system uses NW = 16 and target blocks in
  * order; an ensemble NW = 4 and a work list of (system, target block),
@@ -939,13 +984,14 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
     __syncthreads(); /* the sources are no longer read */
     float* red = reinterpret_cast<float*>(fs_lds);                  /* [NW waves][FS_I][6] */
     double* ys = reinterpret_cast<double*>(fs_lds) + NW * FS_I * 3; /* [FS_I][3] stage positions */
-    int* badf = reinterpret_cast<int*>(ys + FS_I * 3);
     if (g == 0) {
         float* r = red + (w * FS_I + t) * 6;
         r[0] = ax; r[1] = bx; r[2] = ay; r[3] = by; r[4] = az; r[5] = bz;
     }
-    if (tid == 0) *badf = 0;
     __syncthreads();
+    /* wave 0 closes the stage alone */
+    if (w != 0) return;
+    int bad = 0;
     if (tid < 3 * ni) {
         /* component a of target tt: the waves' sums combined pairwise in a
          * fixed tree (wave w with w + 1, then pairs of pairs, ...), then the
@@ -964,19 +1010,23 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
             for (int ww = 0; ww < NW; ww += 2 * sp) combine(hs[ww], ls[ww], hs[ww + sp], ls[ww + sp]);
         const int ii = i0 + tt;
         const double k = u0 + e.c.co * ((double)hs[0] + (double)ls[0]);
-        if (!isfinite(k)) *badf = 1;
+        bad = !isfinite(k);
         ys[tt * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv, rv, step);
     }
-    __syncthreads();
-    if (tid == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+    /* LDS operations of one wave complete in order: the fences only keep
+     * the compiler from moving the reads of ys above its writes */
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (__any(bad) && tid == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
     if (tid < ni) {
         /* one lane per sphere: the spring forces of its dumbbell (both lanes
          * of a dumbbell evaluate the same expression, so they agree bit for
          * bit), then its partner term and its part of the next pack */
         const int q = tid >> 1, h = tid & 1;
         double f[2][3];
-        spring_forces(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
-        store_pack_sphere(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1], 1);
+        spring_forces_rs(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
+        store_pack_sphere_rs<SPLIT>(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1]);
     }
 }
 
@@ -1146,8 +1196,8 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
         /* one lane per sphere, as in k_stage_fused */
         const int q = tid >> 1, h = tid & 1;
         double f[2][3];
-        spring_forces(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
-        store_pack_sphere(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1], 1);
+        spring_forces_rs(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
+        store_pack_sphere_rs<SPLIT>(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1]);
     }
 }
 
@@ -1161,11 +1211,14 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
  * next chunk's loads are in flight while the current chunk is summed, no
  * work-group barrier separates loading from summing, and no system is too
  * large for LDS. Lane (w, g, t) sums target t over its split's range in
- * ascending order, folding into (hi, lo) every 32 sources; the combination
- * and the closing update are those of k_stage_fused. LDS ops of one wave
- * complete in order, so the slot needs no barrier: a chunk is written after
- * the wave's reads of the chunk it replaces and read after its own writes.
- * (Interleaving the groups' entries within a slot measured slower.) */
+ * ascending order, folding into (hi, lo) every 32 sources. LDS ops of one
+ * wave complete in order, so the slot needs no barrier: a chunk is written
+ * after the wave's reads of the chunk it replaces and read after its own
+ * writes. (Interleaving the groups' entries within a slot measured slower.)
+ * The partial sums are combined in k_stage_fused's order, through an LDS
+ * area beside the slots, so one work-group barrier precedes the closing
+ * update; wave 0 then does it alone (stage update, spring forces and pack,
+ * in the rsqrt forms) with no further barrier. */
 template <int SPLIT, int RPY, int TI>
 __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
     constexpr int NW = 16;
@@ -1289,7 +1342,7 @@ __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
         if (own_wave && k == ko) {
             for (int v = 0; v < TI; ++v) term(x0 + v, j0 + v, true, px, py, pz);
         } else {
-#pragma unroll 4
+#pragma unroll
             for (int v = 0; v < TI; ++v) term(x0 + v, j0 + v, false, px, py, pz);
         }
         if ((k + 1) % FOLD == 0 || k + 1 == K) {
@@ -1319,16 +1372,18 @@ __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
         combine(ay, by, oay, oby);
         combine(az, bz, oaz, obz);
     }
-    __syncthreads(); /* the source slots are no longer read */
-    float* red = reinterpret_cast<float*>(fs_lds);                /* [NW waves][TI][6] */
-    double* ys = reinterpret_cast<double*>(fs_lds) + NW * TI * 3; /* [TI][3] stage positions */
-    int* badf = reinterpret_cast<int*>(ys + TI * 3);
+    /* the combination area lies beside the source slots, so no barrier
+     * waits for the slowest wave's last reads before it is written */
+    float* red = reinterpret_cast<float*>(reinterpret_cast<char*>(fs_lds) + NW * 128 * (SPLIT ? 36 : 24));
+    double* ys = reinterpret_cast<double*>(red + NW * TI * 6); /* [TI][3] stage positions */
     if (g == 0) {
         float* r = red + (w * TI + t) * 6;
         r[0] = ax; r[1] = bx; r[2] = ay; r[3] = by; r[4] = az; r[5] = bz;
     }
-    if (tid == 0) *badf = 0;
     __syncthreads();
+    /* wave 0 closes the stage alone */
+    if (w != 0) return;
+    int bad = 0;
     if (tid < 3 * ni) {
         const int tt = tid / 3, a = tid - 3 * tt;
         float hs[NW], ls[NW];
@@ -1344,16 +1399,20 @@ __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
             for (int ww = 0; ww < NW; ww += 2 * st2) combine(hs[ww], ls[ww], hs[ww + st2], ls[ww + st2]);
         const int ii = i0 + tt;
         const double k = u0 + e.c.co * ((double)hs[0] + (double)ls[0]);
-        if (!isfinite(k)) *badf = 1;
+        bad = !isfinite(k);
         ys[tt * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv, rv, step);
     }
-    __syncthreads();
-    if (tid == 0 && *badf) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+    /* LDS operations of one wave complete in order: the fences only keep
+     * the compiler from moving the reads of ys above its writes */
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (__any(bad) && tid == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
     if (tid < ni) {
         const int q = tid >> 1, h = tid & 1;
         double f[2][3];
-        spring_forces(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
-        store_pack_sphere(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1], 1);
+        spring_forces_rs(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
+        store_pack_sphere_rs<SPLIT>(d, e.c, i0 + tid, ys + tid * 3, ys + (tid ^ 1) * 3, f[h], f[h ^ 1]);
     }
 }
 
