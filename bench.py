@@ -112,6 +112,8 @@ def cpu_model():
 
 
 DESCRIPTIONS = {
+    "n16": "suspension of S=8 active dumbbells (N=16 spheres), cube side 40, RK4 dt=0.01, Oseen, "
+           "FP32-compensated pair sum, FP64 state",
     "n4096": "suspension of S=2048 active dumbbells (N=4096 spheres), cube side 240, RK4 dt=0.01, Oseen, "
              "FP32-compensated pair sum, FP64 state",
     "n512": "suspension of S=256 active dumbbells (N=512 spheres), cube side 120, RK4 dt=0.01, Oseen, "
