@@ -36,7 +36,19 @@ def load_table(path: Path = TABLE) -> dict:
 
 
 def tuned_launch(S_per_sys, path: Path = TABLE):
-    return load_table(path).get(bucket_key(S_per_sys), {}).get("launch")
+    """The table's launch for the workload's size bucket. A workload smaller
+    than the smallest tuned bucket of its kind (single or ensemble) takes that
+    bucket's launch, which holds for any smaller size; any other bucket the
+    table lacks gets None (the library default, two kernels per stage)."""
+    table = load_table(path)
+    key = bucket_key(S_per_sys)
+    if key in table:
+        return table[key].get("launch")
+    kind, n = key.split(":N<=")
+    tuned = sorted(int(k.split(":N<=")[1]) for k in table if k.startswith(kind + ":N<="))
+    if tuned and int(n) < tuned[0]:
+        return table[f"{kind}:N<={tuned[0]}"].get("launch")
+    return None
 
 
 def candidates(N: int, ensemble: bool):
