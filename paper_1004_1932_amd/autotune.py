@@ -20,13 +20,21 @@ from . import binding as B
 TABLE = Path(__file__).resolve().parent / "tuning_gfx950.json"
 
 
+# an ensemble of fewer systems than this is tuned apart: its wide work list
+# (64 targets per work-group) can hold fewer work-groups than there are CUs
+FEW_SYSTEMS = 32
+
+
 def bucket_key(S_per_sys) -> str:
     """Size bucket of a workload: one system by N rounded to a power of two,
-    an ensemble by the power-of-two bucket of its largest system."""
+    an ensemble by the power-of-two bucket of its largest system, with
+    ":few" appended for fewer than FEW_SYSTEMS systems."""
     S = np.asarray(S_per_sys).reshape(-1)
     n = int(2 * S.max())
     p2 = 1 << max(0, math.ceil(math.log2(max(n, 1))))
-    return f"{'single' if len(S) == 1 else 'ensemble'}:N<={p2}"
+    if len(S) == 1:
+        return f"single:N<={p2}"
+    return f"ensemble:N<={p2}" + (":few" if len(S) < FEW_SYSTEMS else "")
 
 
 def load_table(path: Path = TABLE) -> dict:
@@ -36,16 +44,20 @@ def load_table(path: Path = TABLE) -> dict:
 
 
 def tuned_launch(S_per_sys, path: Path = TABLE):
-    """The table's launch for the workload's size bucket. A workload smaller
-    than the smallest tuned bucket of its kind (single or ensemble) takes that
-    bucket's launch, which holds for any smaller size; any other bucket the
-    table lacks gets None (the library default, two kernels per stage)."""
+    """The table's launch for the workload's size bucket. A few-system
+    ensemble whose ":few" bucket is not tuned takes its size bucket's entry.
+    A workload smaller than the smallest tuned bucket of its kind (single or
+    ensemble) takes that bucket's launch, which holds for any smaller size;
+    any other bucket the table lacks gets None (the library default, two
+    kernels per stage)."""
     table = load_table(path)
     key = bucket_key(S_per_sys)
-    if key in table:
-        return table[key].get("launch")
-    kind, n = key.split(":N<=")
-    tuned = sorted(int(k.split(":N<=")[1]) for k in table if k.startswith(kind + ":N<="))
+    plain = key.removesuffix(":few")
+    for k in (key, plain):
+        if k in table:
+            return table[k].get("launch")
+    kind, n = plain.split(":N<=")
+    tuned = sorted(int(k.split(":N<=")[1]) for k in table if k.startswith(kind + ":N<=") and not k.endswith(":few"))
     if tuned and int(n) < tuned[0]:
         return table[f"{kind}:N<={tuned[0]}"].get("launch")
     return None
@@ -78,6 +90,8 @@ def candidates(N: int, ensemble: bool):
         if ensemble:
             out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=1))
             out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=2))
+            if N >= 1024:
+                out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=3))
         else:
             out.append(dict(wg=256, wj=4, ipl=1, jchunk=256, posmode=posmode, fused=1))
             if N >= 1024:  # the streamed form pads every system to 1024 sources
