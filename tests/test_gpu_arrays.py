@@ -176,3 +176,27 @@ def test_array_msd_against_number():
     for x in (3, 5, 7, 9):
         for model in (0, 1):
             assert out["checkerboard", x][model] > 1.3 * out["random", x][model]
+
+
+def test_tuned_launch_on_lattice_ensembles(oracle):
+    """The tuned launch of few-system lattice ensembles (their ":few" bucket
+    or its size bucket) against the oracle: 3^3 and 7^3 lattices, W = 3,
+    100 steps from rest, displacement within 1e-6."""
+    _torch()
+    from paper_1004_1932_amd.autotune import bucket_key, tuned_launch
+    p = fig1_params(0.2, SPP)
+    for x in (3, 7):
+        ens, _, _, _ = array_runs(x, 10 * p.ell, 3, "checkerboard", seed=5, params=p)
+        launch = tuned_launch(ens.S_per_sys)
+        say(f"tuned {bucket_key(ens.S_per_sys)}: {launch}")
+        assert launch is not None and launch.get("fused") in (1, 2)
+        s = P.Simulator(p, ens.S_per_sys, precision="fp32c", launch="tuned", graph=True)
+        s.set_state(ens.X, ens.phi)
+        _, _, code = s.run(100, 0)
+        assert code == 0
+        Xg = s.get_state()[0].cpu().numpy()
+        s.close()
+        Xo, _, _, _ = oracle.run(p, ens.X, ens.phi, 100, S_per_sys=ens.S_per_sys)
+        err = relerr(Xg - ens.X, Xo - ens.X)
+        say(f"  {x}^3 x 3: displacement rel err {err:.2e}")
+        assert err <= 1e-6
