@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -138,10 +139,25 @@ def counted_traffic(launch):
     return kib * 1024.0
 
 
+def workload_name(name: str) -> str:
+    """A preset name, or arrays:x:W (W checkerboard x^3 lattices, one ensemble)."""
+    if name in DESCRIPTIONS or re.fullmatch(r"arrays:[1-9][0-9]*:[1-9][0-9]*", name):
+        return name
+    raise argparse.ArgumentTypeError(f"{name!r}: one of {sorted(DESCRIPTIONS)} or arrays:x:W")
+
+
+def describe(name: str) -> str:
+    if name in DESCRIPTIONS:
+        return DESCRIPTIONS[name]
+    _, x, W = name.split(":")
+    return (f"ensemble of {W} lattices of {x}^3 active dumbbells, spacing 10 ell, checkerboard phases, "
+            f"a = 0.2 ell, lambda = 0.1 ell, RK4, Oseen, FP32-compensated pair sum, FP64 state")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="n4096", choices=sorted(DESCRIPTIONS),
+    ap.add_argument("--workload", default="n4096", type=workload_name,
                     help="the N = 4096 suspension is the measured configuration; the others are for profiles")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
@@ -169,7 +185,11 @@ def main():
     from workload import make_preset
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    w = make_preset(args.workload)
+    if args.workload.startswith("arrays:"):
+        from paper_1004_1932_amd.autotune import tuning_workload
+        w = tuning_workload(args.workload)
+    else:
+        w = make_preset(args.workload)
     sizes = [int(v) for v in w.S_per_sys] if hasattr(w, "S_per_sys") else [w.S]
     Nb = 2.0 * np.asarray(sizes, dtype=np.float64)
     N, S = w.X.shape[0], int(sum(sizes))
@@ -256,7 +276,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": DESCRIPTIONS[args.workload], "name": args.workload,
+        "config": {"workload": describe(args.workload), "name": args.workload,
                    "N": N, "S": S, "systems": len(sizes), "launch": sim.launch, "graph": not args.no_graph},
         "sphere_steps_per_s": N * args.steps / secs,
         "fp64_tiled": {"value": v64, "unit": "pair interactions/s", "ms_per_step": secs64 / fp64_steps * 1e3,
