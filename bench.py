@@ -25,7 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
-FLOPS_PER_PAIR = 28           # algorithmic flops of one ordered pair term
+FLOPS_PER_PAIR = 28           # algorithmic flops of one ordered pair term (Oseen)
+FLOPS_PER_PAIR_RPY = 34       # with the Rotne-Prager-Yamakawa-Mazur correction
 
 # HBM bytes per pair-kernel launch from two rocprofv3 --pmc runs of
 # `bench.py --counter-probe` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
@@ -173,9 +174,16 @@ def main():
                     help="tuned launch with this stage form (0: two kernels, 1: 16 targets per work-group, "
                          "2: 64 targets per work-group, 3: 16 targets per work-group with streamed "
                          "sources), for profiles of the form the table did not choose")
+    ap.add_argument("--tensor", choices=("oseen", "rpy"), default="oseen",
+                    help="measurement runs of the RPY tensor (the measured configuration is Oseen)")
+    ap.add_argument("--integrator", choices=("rk4", "heun"), default="rk4",
+                    help="measurement runs of Heun steps (two stages; the measured configuration is RK4)")
+    ap.add_argument("--kT", type=float, default=0.0, help="Brownian noise (Heun only)")
     ap.add_argument("--counter-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a few steps plus one plain 256 MiB device copy")
     args = ap.parse_args()
+    if args.kT != 0.0 and args.integrator != "heun":
+        ap.error("--kT needs --integrator heun")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
@@ -193,7 +201,11 @@ def main():
     sizes = [int(v) for v in w.S_per_sys] if hasattr(w, "S_per_sys") else [w.S]
     Nb = 2.0 * np.asarray(sizes, dtype=np.float64)
     N, S = w.X.shape[0], int(sum(sizes))
-    pairs_per_step = 4.0 * float((Nb * (Nb - 1)).sum())
+    variant = args.tensor != "oseen" or args.integrator != "rk4" or args.kT != 0.0
+    stages = 4 if args.integrator == "rk4" else 2
+    flops_per_pair = FLOPS_PER_PAIR_RPY if args.tensor == "rpy" else FLOPS_PER_PAIR
+    model = dict(tensor=args.tensor, integrator=args.integrator, kT=args.kT)
+    pairs_per_step = stages * float((Nb * (Nb - 1)).sum())
     # the dumbbell partner is summed in FP64 outside the pair kernel
     kernel_pairs = float((Nb * (Nb - 2)).sum())
 
@@ -218,7 +230,7 @@ def main():
         return
 
     # FP32-compensated path, graph-replayed steps
-    sim = P.Simulator(w.params, sizes, precision="fp32c", graph=not args.no_graph, launch=launch)
+    sim = P.Simulator(w.params, sizes, precision="fp32c", graph=not args.no_graph, launch=launch, **model)
     sim.set_state(w.X, w.phi)
     log(f"fp32c launch {sim.launch}")
     secs, wall = time_steps(sim, args.steps, args.warmup)
@@ -234,12 +246,12 @@ def main():
     kern_ms, launches = P.ad_profile_read(sim.ctx)
     P.ad_profile_pairs(sim.ctx, False)
     avg_ms = kern_ms / launches
-    achieved = FLOPS_PER_PAIR * kernel_pairs / (avg_ms * 1e-3) / 1e12
+    achieved = flops_per_pair * kernel_pairs / (avg_ms * 1e-3) / 1e12
     log(f"pair kernel: {avg_ms * 1e3:.2f} us avg over {launches} launches, {achieved:.2f} TFLOP/s")
 
     # plain FP64 form (tiled) timed beside it, on about 2e11 pair terms at most
     fp64_steps = max(2, min(args.fp64_steps, int(2e11 / pairs_per_step)))
-    sim64 = P.Simulator(w.params, sizes, precision="fp64_tiled", graph=not args.no_graph)
+    sim64 = P.Simulator(w.params, sizes, precision="fp64_tiled", graph=not args.no_graph, **model)
     sim64.set_state(w.X, w.phi)
     secs64, _ = time_steps(sim64, fp64_steps, max(1, fp64_steps // 10))
     v64 = pairs_per_step * fp64_steps / secs64
@@ -251,7 +263,7 @@ def main():
     # per step 4 stages, each tensor written once and read once
     dense_bytes = 4 * 2 * 72.0 * float((Nb * Nb).sum())
     dense = None
-    if dense_bytes / 8 <= 8e9:
+    if dense_bytes / 8 <= 8e9 and not variant:
         simd = P.Simulator(w.params, sizes, precision="fp64_dense", graph=not args.no_graph)
         simd.set_state(w.X, w.phi)
         secsd, _ = time_steps(simd, args.dense_steps, max(1, args.dense_steps // 10))
@@ -286,13 +298,16 @@ def main():
         "speedup_vs_dense": value / dense["value"] if dense else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": counted_traffic(sim.launch) if args.workload == COUNTED["workload"] else None,
+                     "traffic": (counted_traffic(sim.launch)
+                                 if args.workload == COUNTED["workload"] and not variant else None),
                      "traffic_unit": "B per launch",
                      "kernel": KERNEL_NAMES[sim.launch.get("fused", 0)],
                      "avg_launch_us": avg_ms * 1e3,
-                     "flops_per_launch": FLOPS_PER_PAIR * kernel_pairs},
+                     "flops_per_launch": flops_per_pair * kernel_pairs},
     }
-    if not args.no_cpu_baseline:
+    if variant:
+        out["config"].update(model)
+    if not args.no_cpu_baseline and not variant:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, sizes, args.cpu_seconds)
     print(json.dumps(out), flush=True)
