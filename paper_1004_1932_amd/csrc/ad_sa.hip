@@ -8,8 +8,11 @@
  *   K^{sr} = w sin(phi_s - phi_r) (15/64) (a/ell) (lam/ell)^2 (ell/D)^5 Dhat
  *            (3s + 6rq + 6 s q^2 - 7 s^3 - 21 s r^2 - 42 q s^2 r + 63 s^3 r^2),
  *   D = R_s - R_r, s = Dhat.N_s, r = Dhat.N_r, q = N_s.N_r.
- * One thread per dumbbell sums over all others in ascending order, with the
- * sources staged through LDS in tiles. FP64 throughout, no FMA contraction.
+ * One wave per dumbbell: lane l sums over the others j = l, l + 64, ... in
+ * ascending order, and a fixed butterfly of shuffles adds the 64 partial
+ * sums (every lane ends with the same bits). FP64 throughout, no FMA
+ * contraction. (One thread per dumbbell left the paper's arrays of 125-729
+ * dumbbells with one to six work-groups on the whole chip.)
  * A step is four launches of k_sa_stage (RK4); each also applies its stage's
  * update to its own dumbbell, and the last one scales the axes back to unit
  * length.
@@ -25,74 +28,67 @@
 namespace ad_sa {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int SA_WG = 128;
+constexpr int SA_WG = 64; /* one wave, one dumbbell */
 
 struct SaCoef {
     double ell, cj, ck; /* cj = a w (9/64)(lam/ell)^2, ck = w (15/64)(a/ell)(lam/ell)^2 */
     double h2, dt, dt6;
 };
 
-/* rates of dumbbell i against all S, reading positions Rs and axes Ns */
+/* rates of dumbbell i against all S, reading positions Rs and axes Ns; called
+ * by all 64 lanes of the wave that owns i, which all return the rates */
 __device__ void sa_rates(const SaCoef& k, int S, int i, const double* __restrict__ Rs,
                          const double* __restrict__ Ns, const double* __restrict__ phi, double dR[3], double dN[3],
                          int* bad) {
-    __shared__ double tR[SA_WG][3];
-    __shared__ double tN[SA_WG][3];
-    __shared__ double tp[SA_WG];
-    const int t = threadIdx.x;
-    double ri[3] = {0.0, 0.0, 0.0}, ni[3] = {1.0, 0.0, 0.0}, pi_ = 0.0;
-    if (i < S) {
-        for (int a = 0; a < 3; ++a) {
-            ri[a] = Rs[3 * i + a];
-            ni[a] = Ns[3 * i + a];
-        }
-        pi_ = phi[i];
+    const int l = threadIdx.x & 63;
+    double ri[3], ni[3];
+    for (int a = 0; a < 3; ++a) {
+        ri[a] = Rs[3 * i + a];
+        ni[a] = Ns[3 * i + a];
     }
+    const double pi_ = phi[i];
     double jx = 0.0, jy = 0.0, jz = 0.0, kx = 0.0, ky = 0.0, kz = 0.0;
-    for (int t0 = 0; t0 < S; t0 += SA_WG) {
-        const int n = min(SA_WG, S - t0);
-        __syncthreads();
-        if (t < n) {
-            for (int a = 0; a < 3; ++a) {
-                tR[t][a] = Rs[3 * (t0 + t) + a];
-                tN[t][a] = Ns[3 * (t0 + t) + a];
-            }
-            tp[t] = phi[t0 + t];
+    for (int j = l; j < S; j += 64) {
+        if (j == i) continue;
+        const double rj[3] = {Rs[3 * j], Rs[3 * j + 1], Rs[3 * j + 2]};
+        const double nj[3] = {Ns[3 * j], Ns[3 * j + 1], Ns[3 * j + 2]};
+        const double Dx = ri[0] - rj[0];
+        const double Dy = ri[1] - rj[1];
+        const double Dz = ri[2] - rj[2];
+        const double D = sqrt((Dx * Dx + Dy * Dy) + Dz * Dz);
+        if (D == 0.0) {
+            *bad = 1;
+            continue;
         }
-        __syncthreads();
-        if (i >= S) continue;
-        for (int jj = 0; jj < n; ++jj) {
-            const int j = t0 + jj;
-            if (j == i) continue;
-            const double Dx = ri[0] - tR[jj][0];
-            const double Dy = ri[1] - tR[jj][1];
-            const double Dz = ri[2] - tR[jj][2];
-            const double D = sqrt((Dx * Dx + Dy * Dy) + Dz * Dz);
-            if (D == 0.0) {
-                *bad = 1;
-                continue;
-            }
-            const double ux = Dx / D, uy = Dy / D, uz = Dz / D;
-            const double s = (ux * ni[0] + uy * ni[1]) + uz * ni[2];
-            const double r = (ux * tN[jj][0] + uy * tN[jj][1]) + uz * tN[jj][2];
-            const double q = (ni[0] * tN[jj][0] + ni[1] * tN[jj][1]) + ni[2] * tN[jj][2];
-            const double sn = sin(pi_ - tp[jj]);
-            const double x = k.ell / D;
-            const double x4 = (x * x) * (x * x);
-            const double aN = 2.0 * s + 4.0 * q * r - 10.0 * s * r * r;
-            const double aD =
-                1.0 + 2.0 * q * q - 5.0 * s * s - 5.0 * r * r - 20.0 * q * s * r + 35.0 * s * s * r * r;
-            const double fj = k.cj * sn * x4;
-            jx = jx + fj * (ni[0] * aN + ux * aD);
-            jy = jy + fj * (ni[1] * aN + uy * aD);
-            jz = jz + fj * (ni[2] * aN + uz * aD);
-            const double bK = 3.0 * s + 6.0 * r * q + 6.0 * s * q * q - 7.0 * s * s * s - 21.0 * s * r * r -
-                              42.0 * q * s * s * r + 63.0 * s * s * s * r * r;
-            const double fk = k.ck * sn * (x4 * x) * bK;
-            kx = kx + fk * ux;
-            ky = ky + fk * uy;
-            kz = kz + fk * uz;
-        }
+        const double ux = Dx / D, uy = Dy / D, uz = Dz / D;
+        const double s = (ux * ni[0] + uy * ni[1]) + uz * ni[2];
+        const double r = (ux * nj[0] + uy * nj[1]) + uz * nj[2];
+        const double q = (ni[0] * nj[0] + ni[1] * nj[1]) + ni[2] * nj[2];
+        const double sn = sin(pi_ - phi[j]);
+        const double x = k.ell / D;
+        const double x4 = (x * x) * (x * x);
+        const double aN = 2.0 * s + 4.0 * q * r - 10.0 * s * r * r;
+        const double aD =
+            1.0 + 2.0 * q * q - 5.0 * s * s - 5.0 * r * r - 20.0 * q * s * r + 35.0 * s * s * r * r;
+        const double fj = k.cj * sn * x4;
+        jx = jx + fj * (ni[0] * aN + ux * aD);
+        jy = jy + fj * (ni[1] * aN + uy * aD);
+        jz = jz + fj * (ni[2] * aN + uz * aD);
+        const double bK = 3.0 * s + 6.0 * r * q + 6.0 * s * q * q - 7.0 * s * s * s - 21.0 * s * r * r -
+                          42.0 * q * s * s * r + 63.0 * s * s * s * r * r;
+        const double fk = k.ck * sn * (x4 * x) * bK;
+        kx = kx + fk * ux;
+        ky = ky + fk * uy;
+        kz = kz + fk * uz;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        jx = jx + __shfl_xor(jx, o);
+        jy = jy + __shfl_xor(jy, o);
+        jz = jz + __shfl_xor(jz, o);
+        kx = kx + __shfl_xor(kx, o);
+        ky = ky + __shfl_xor(ky, o);
+        kz = kz + __shfl_xor(kz, o);
     }
     dR[0] = jx;
     dR[1] = jy;
@@ -106,16 +102,17 @@ __device__ void sa_rates(const SaCoef& k, int S, int i, const double* __restrict
 __global__ __launch_bounds__(SA_WG) void k_sa_rhs(SaCoef k, int S, const double* __restrict__ R,
                                                   const double* __restrict__ N, const double* __restrict__ phi,
                                                   double* __restrict__ dR, double* __restrict__ dN, int* flag) {
-    const int i = blockIdx.x * SA_WG + threadIdx.x;
+    const int i = blockIdx.x; /* the grid has exactly S work-groups */
     double r[3], n[3];
     int bad = 0;
     sa_rates(k, S, i, R, N, phi, r, n, &bad);
-    if (i >= S) return;
+    const int any = __any(bad);
+    if (threadIdx.x != 0) return;
     for (int a = 0; a < 3; ++a) {
         dR[3 * i + a] = r[a];
         dN[3 * i + a] = n[a];
     }
-    if (bad && flag) atomicOr(flag, 1);
+    if (any && flag) atomicOr(flag, 1);
 }
 
 /* One RK4 stage: rates at the stage positions (YR, YN), accumulate, and write
@@ -125,12 +122,13 @@ __global__ __launch_bounds__(SA_WG) void k_sa_stage(SaCoef k, int S, int stage, 
                                                     const double* __restrict__ YR, const double* __restrict__ YN,
                                                     double* __restrict__ ZR, double* __restrict__ ZN,
                                                     double* __restrict__ AR, double* __restrict__ AN, int* flag) {
-    const int i = blockIdx.x * SA_WG + threadIdx.x;
+    const int i = blockIdx.x; /* the grid has exactly S work-groups */
     double kr[3], kn[3];
     int bad = 0;
     sa_rates(k, S, i, YR, YN, phi, kr, kn, &bad);
-    if (i >= S) return;
-    if (bad) atomicOr(flag, 1);
+    const int any = __any(bad);
+    if (threadIdx.x != 0) return;
+    if (any) atomicOr(flag, 1);
     double nv[3];
     for (int a = 0; a < 3; ++a) {
         const int o = 3 * i + a;
@@ -203,7 +201,7 @@ int ad_sa_rhs(const ad_params* p, int32_t S, const double* R, const double* N, c
               double* dN, void* stream) {
     if (!sa_params_ok(p) || S < 1 || !R || !N || !phi || !dR || !dN) return AD_EINVAL;
     const SaCoef k = sa_coef(p, 1.0);
-    hipLaunchKernelGGL(k_sa_rhs, dim3((S + SA_WG - 1) / SA_WG), dim3(SA_WG), 0, (hipStream_t)stream, k, S, R, N,
+    hipLaunchKernelGGL(k_sa_rhs, dim3(S), dim3(SA_WG), 0, (hipStream_t)stream, k, S, R, N,
                        phi, dR, dN, (int*)nullptr);
     return hipGetLastError() == hipSuccess ? AD_OK : AD_EDEVICE;
 }
@@ -226,7 +224,7 @@ int ad_sa_run(const ad_params* p, int32_t S, double* R, double* N, const double*
     double* AR = reinterpret_cast<double*>(b + 256 + 4 * blk);
     double* AN = reinterpret_cast<double*>(b + 256 + 5 * blk);
     const SaCoef k = sa_coef(p, dt);
-    const dim3 grid((S + SA_WG - 1) / SA_WG), block(SA_WG);
+    const dim3 grid(S), block(SA_WG); /* one work-group (one wave) per dumbbell */
     hipLaunchKernelGGL(k_sa_clear, dim3(1), dim3(1), 0, st, flag);
     for (int64_t n = 0; n < nsteps; ++n) {
         /* stage inputs: state, YA, YB, YA; outputs: YA, YB, YA, state */
