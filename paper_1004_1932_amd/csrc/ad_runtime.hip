@@ -15,6 +15,7 @@
 
 #include "../../include/ad.h"
 #include "ad_internal.h"
+#include "ad_order.h"
 
 using ad::Coef;
 using ad::Ctl;
@@ -259,55 +260,6 @@ static void build_dense_items(ad_ctx* c) {
     });
 }
 
-/* XCD-aware order of a fused work list of many systems. Work-groups go to
- * the 8 XCDs round-robin (work-group i to XCD i mod 8), and each XCD has an
- * L2 of its own. Each system gets one XCD (largest first, to the XCD with the
- * least pair work so far) and its items take positions congruent to that XCD
- * mod 8, so that all of a system's work-groups read its sources through one
- * L2. Each XCD keeps its items longest first; a position whose XCD has run
- * out takes the next item of the XCD with the most left. With few systems
- * the XCDs could not be balanced, so their list keeps the plain order. */
-static void xcd_order(std::vector<Item>& v) {
-    constexpr int X = 8;
-    std::vector<std::vector<Item>> q(X);
-    long long load[X] = {};
-    int nsys = 0;
-    for (size_t k = 0; k < v.size();) {
-        size_t e = k;
-        while (e < v.size() && v[e].sys == v[k].sys) ++e;
-        ++nsys;
-        k = e;
-    }
-    if (nsys < 8 * X) return;
-    for (size_t k = 0; k < v.size();) {
-        size_t e = k;
-        while (e < v.size() && v[e].sys == v[k].sys) ++e;
-        const int x = (int)(std::min_element(load, load + X) - load);
-        for (size_t j = k; j < e; ++j) {
-            q[x].push_back(v[j]);
-            load[x] += (long long)v[j].ni * v[j].Nb;
-        }
-        k = e;
-    }
-    std::vector<size_t> head(X, 0);
-    std::vector<Item> out;
-    out.reserve(v.size());
-    while (out.size() < v.size()) {
-        const int x = (int)(out.size() % X);
-        int from = x;
-        if (head[x] == q[x].size()) {
-            size_t best = 0;
-            for (int y = 0; y < X; ++y)
-                if (q[y].size() - head[y] > best) {
-                    best = q[y].size() - head[y];
-                    from = y;
-                }
-        }
-        out.push_back(q[from][head[from]++]);
-    }
-    v.swap(out);
-}
-
 static void build_items(ad_ctx* c) {
     const ad_launch& L = c->launch;
     const int NC = ncomp_of(c);
@@ -367,7 +319,7 @@ static void build_items(ad_ctx* c) {
         }
         std::stable_sort(c->fitems.begin(), c->fitems.end(),
                          [](const Item& a, const Item& b) { return a.Nb > b.Nb; });
-        xcd_order(c->fitems);
+        ad::xcd_order(c->fitems);
     }
     /* longest first: the hardware dispatcher then hands the cheap items to
      * whichever compute units free up last */

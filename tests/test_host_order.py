@@ -1,0 +1,85 @@
+"""The XCD-aware order of the fused stages' work lists (host logic of the
+runtime, paper_1004_1932_amd/csrc/ad_order.h), compiled with g++ on its own:
+a permutation of the input; with many systems every system on one XCD
+(position mod 8) and the XCDs' pair work balanced; with few systems the
+input order."""
+import json
+import shutil
+import subprocess
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+
+PROGRAM = r"""
+#include <cstdio>
+#include <random>
+#include <set>
+#include "ad_order.h"
+struct Item { int sys, i0, ni, Nb; };
+int main() {
+  std::mt19937 rng(1);
+  for (int nsys : {512, 64, 63, 10, 300}) {
+    std::vector<Item> v;
+    int off = 0;
+    std::vector<int> Nb(nsys);
+    for (int b = 0; b < nsys; ++b) Nb[b] = 2 * (16 + (int)(rng() % 385));
+    std::vector<int> order(nsys);
+    for (int b = 0; b < nsys; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Nb[a] > Nb[b]; });
+    for (int b : order) {
+      for (int i = 0; i < Nb[b]; i += 64) v.push_back(Item{b, off + i, std::min(64, Nb[b] - i), Nb[b]});
+      off += Nb[b];
+    }
+    std::vector<Item> w = v;
+    ad::xcd_order(w);
+    std::multiset<int> a, c;
+    for (auto& t : v) a.insert(t.i0);
+    for (auto& t : w) c.insert(t.i0);
+    std::vector<std::set<int>> xcds(nsys);
+    long long load[8] = {0};
+    for (size_t k = 0; k < w.size(); ++k) {
+      xcds[w[k].sys].insert((int)(k % 8));
+      load[k % 8] += (long long)w[k].ni * w[k].Nb;
+    }
+    int worst = 0;
+    for (auto& s : xcds) worst = std::max(worst, (int)s.size());
+    long long mx = *std::max_element(load, load + 8), mn = *std::min_element(load, load + 8);
+    bool same = true;
+    for (size_t k = 0; k < v.size(); ++k) same = same && v[k].i0 == w[k].i0;
+    std::printf("{\"nsys\": %d, \"perm\": %s, \"same\": %s, \"worst_xcds\": %d, \"balance\": %.6f}\n", nsys,
+                a == c ? "true" : "false", same ? "true" : "false", worst, (double)mx / (double)mn);
+  }
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def results(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ is not available")
+    d = tmp_path_factory.mktemp("order")
+    (d / "t.cpp").write_text(PROGRAM)
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", str(ROOT / "paper_1004_1932_amd" / "csrc"), str(d / "t.cpp"),
+                    "-o", str(d / "t")], check=True)
+    out = subprocess.run([str(d / "t")], check=True, capture_output=True, text=True).stdout
+    return {r["nsys"]: r for r in map(json.loads, out.splitlines())}
+
+
+def test_order_is_a_permutation(results):
+    assert all(r["perm"] for r in results.values())
+
+
+def test_many_systems_one_xcd_each_and_balanced(results):
+    for nsys in (512, 64, 300):
+        r = results[nsys]
+        assert not r["same"]
+        assert r["worst_xcds"] <= 2, r          # a system spills only where an XCD ran dry
+        assert r["balance"] < 1.05, r
+
+
+def test_few_systems_keep_their_order(results):
+    for nsys in (63, 10):
+        assert results[nsys]["same"]
