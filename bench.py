@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6       # MI355X published FP64 vector peak
 FLOPS_PER_PAIR = 28           # algorithmic flops of one ordered pair term (Oseen)
 FLOPS_PER_PAIR_RPY = 34       # with the Rotne-Prager-Yamakawa-Mazur correction
 
@@ -44,7 +45,8 @@ COUNTED = {
 # the kernel that a launch of each form runs (the one bracketed by events)
 KERNEL_NAMES = {0: "k_pairs_f32c", 1: "k_stage_fused (pair sum and stage update)",
                 2: "k_stage_wide (pair sum and stage update, 64 targets per work-group)",
-                3: "k_stage_stream (pair sum and stage update, sources streamed per wave)"}
+                3: "k_stage_stream (pair sum and stage update, sources streamed per wave)",
+                4: "k_resident (every stage of a run of steps, one work-group per system)"}
 
 
 def log(msg):
@@ -100,6 +102,90 @@ def cpu_baseline(w, sizes, budget_s):
         adref.set_threads(cores)
     out["one_core"] = {"value": pairs_per_step * n1 / dt1, "sample": f"{n1} RK4 steps ({dt1:.1f} s)"}
     return out
+
+
+# VALU instructions per loop trip of 8 terms in the issue-rate probe, from the
+# gfx950 assembly of k_valu_rate (8 terms plus the target's step; with hi/lo
+# positions the lo differences and the lo step as well; 8 FMAs for kind 1)
+PROBE_VALU_PER_TRIP = {0: 147, 1: 8, 2: 189}
+PROBE_KINDS = {0: "Oseen pair term, single-float positions", 1: "independent FMA chains",
+               2: "Oseen pair term, hi/lo positions"}
+
+
+def calibrate(iters: int = 4096):
+    """Issue rate of the pair term's own instruction mix (operands in
+    registers, no memory traffic) at 1, 2, 4 and 8 waves per SIMD, and the
+    shader clock under the load, one JSON line per case."""
+    import torch
+    import paper_1004_1932_amd as P
+    props = torch.cuda.get_device_properties(0)
+    cus = props.multi_processor_count
+    import ctypes
+    # rate of the constant-rate counter: hipDeviceGetAttribute with
+    # hipDeviceAttributeWallClockRate (value 10019 in hip_runtime_api.h), kHz
+    rate = ctypes.c_int(0)
+    rc = ctypes.CDLL("libamdhip64.so").hipDeviceGetAttribute(ctypes.byref(rate), 10019, 0)
+    if rc != 0 or rate.value <= 0:
+        raise RuntimeError(f"hipDeviceGetAttribute(WallClockRate) failed: {rc}")
+    wall_hz = rate.value * 1e3
+    out = []
+    for kind in (0, 2, 1):
+        for wps in (1, 2, 4, 8):
+            blocks = cus * wps  # 256-thread groups: one wave per SIMD each
+            sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+            clk = torch.zeros(2, dtype=torch.int64, device="cuda")
+            P.ad_valu_probe(kind, blocks, 64, sink, clk)  # warm-up
+            times = []
+            for _ in range(5):
+                clk.zero_()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                P.ad_valu_probe(kind, blocks, iters, sink, clk)
+                b.record()
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b) * 1e-3)
+            t = sorted(times)[len(times) // 2]
+            cyc, ticks = (int(v) for v in clk.cpu())
+            ghz = cyc / (ticks / wall_hz) / 1e9 if ticks else float("nan")
+            trips = blocks * 256.0 * iters
+            lane_instr = trips * PROBE_VALU_PER_TRIP[kind] / t
+            line = {"calibrate": PROBE_KINDS[kind], "kind": kind, "waves_per_simd": wps, "blocks": blocks,
+                    "seconds": t, "shader_clock_GHz": ghz, "valu_lane_instr_per_s": lane_instr,
+                    "valu_instr_per_cu_per_clock": lane_instr / 64.0 / cus / (ghz * 1e9),
+                    "cus": cus}
+            if kind != 1:
+                line["pair_terms_per_s"] = trips * 8 / t
+                line["tflops_at_28_per_term"] = trips * 8 * 28 / t / 1e12
+            else:
+                line["fma_tflops"] = trips * 8 * 2 / t / 1e12
+            print(json.dumps(line), flush=True)
+            out.append(line)
+    return out
+
+
+def stroke_averaged_timing(steps: int = 2000):
+    """The stroke-averaged equations (Sec. III) on the GPU: one checkerboard
+    lattice of x^3 dumbbells at spacing 10 ell with the Fig. 1 parameters,
+    RK4 steps of T/20, for x = 5, 7, 9 (the paper's arrays) and 16 (4096
+    dumbbells); one JSON line per size (microseconds per RK4 step, pair
+    evaluations 4 S (S - 1) per step per second)."""
+    import torch
+    import paper_1004_1932_amd as P
+    from workload import fig1_params, lattice_array
+    p = fig1_params(0.2, 5000)
+    for x in (5, 7, 9, 16):
+        R, N, phi = lattice_array(x, 10 * p.ell, 3, "checkerboard")
+        sa = P.StrokeAveraged(p, R, N, phi)
+        assert sa.run(p.T / 20, 20) == 0  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        assert sa.run(p.T / 20, steps) == 0
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        S = len(R)
+        print(json.dumps({"stroke_averaged": True, "dumbbells": S, "us_per_step": dt / steps * 1e6,
+                          "pair_evaluations_per_s": 4 * S * (S - 1) * steps / dt}), flush=True)
 
 
 def cpu_model():
@@ -170,15 +256,24 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--unfused", action="store_true",
                     help="tuned launch with pair kernel and epilogue as two kernels (for profiles of that path)")
-    ap.add_argument("--fused", type=int, choices=(0, 1, 2, 3), default=None,
+    ap.add_argument("--fused", type=int, choices=(0, 1, 2, 3, 4), default=None,
                     help="tuned launch with this stage form (0: two kernels, 1: 16 targets per work-group, "
                          "2: 64 targets per work-group, 3: 16 targets per work-group with streamed "
-                         "sources), for profiles of the form the table did not choose")
+                         "sources, 4: resident, one work-group per system for a run of steps), for profiles "
+                         "of the form the table did not choose")
+    ap.add_argument("--precision", choices=("fp32c", "fp64"), default="fp32c",
+                    help="arithmetic of the measured leg (the measured configuration is fp32c; fp64 for "
+                         "the plain-FP64 workloads)")
     ap.add_argument("--tensor", choices=("oseen", "rpy"), default="oseen",
                     help="measurement runs of the RPY tensor (the measured configuration is Oseen)")
     ap.add_argument("--integrator", choices=("rk4", "heun"), default="rk4",
                     help="measurement runs of Heun steps (two stages; the measured configuration is RK4)")
     ap.add_argument("--kT", type=float, default=0.0, help="Brownian noise (Heun only)")
+    ap.add_argument("--stroke-averaged", action="store_true",
+                    help="time the stroke-averaged far-field equations on lattices of 5^3 to 16^3 dumbbells")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="issue rate of the pair term's instruction mix and of FMA chains, and the shader clock")
+    ap.add_argument("--calibrate-iters", type=int, default=4096)
     ap.add_argument("--counter-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a few steps plus one plain 256 MiB device copy")
     args = ap.parse_args()
@@ -193,6 +288,12 @@ def main():
     from workload import make_preset
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.calibrate:
+        calibrate(args.calibrate_iters)
+        return
+    if args.stroke_averaged:
+        stroke_averaged_timing()
+        return
     if args.workload.startswith("arrays:"):
         from paper_1004_1932_amd.autotune import tuning_workload
         w = tuning_workload(args.workload)
@@ -206,12 +307,15 @@ def main():
     flops_per_pair = FLOPS_PER_PAIR_RPY if args.tensor == "rpy" else FLOPS_PER_PAIR
     model = dict(tensor=args.tensor, integrator=args.integrator, kT=args.kT)
     pairs_per_step = stages * float((Nb * (Nb - 1)).sum())
-    # the dumbbell partner is summed in FP64 outside the pair kernel
-    kernel_pairs = float((Nb * (Nb - 2)).sum())
+    # FP32C: the dumbbell partner is summed in FP64 outside the pair kernel
+    kernel_pairs = float((Nb * (Nb - 2)).sum()) if args.precision == "fp32c" else float((Nb * (Nb - 1)).sum())
+    peak = PEAK_FP32_TFLOPS if args.precision == "fp32c" else PEAK_FP64_TFLOPS
 
     launch = "tuned"
     form = 0 if args.unfused else args.fused
-    if form is not None:
+    if form is not None and args.precision == "fp64":
+        launch = dict(ipl=1, jchunk=0, wg=64, wj=1, posmode=0, fused=form)
+    elif form is not None:
         from paper_1004_1932_amd.autotune import tuned_launch
         launch = dict(tuned_launch(sizes) or {}, fused=form)
 
@@ -229,27 +333,11 @@ def main():
         print(json.dumps({"counter_probe": True, "copy_bytes": src.numel() * 8, "launch": sim.launch}), flush=True)
         return
 
-    # FP32-compensated path, graph-replayed steps
-    sim = P.Simulator(w.params, sizes, precision="fp32c", graph=not args.no_graph, launch=launch, **model)
-    sim.set_state(w.X, w.phi)
-    log(f"fp32c launch {sim.launch}")
-    secs, wall = time_steps(sim, args.steps, args.warmup)
-    assert sim.check() == 0
-    ms_per_step = secs / args.steps * 1e3
-    value = pairs_per_step * args.steps / secs
-    log(f"fp32c: {ms_per_step:.4f} ms/step, {value:.4e} pairs/s (wall {wall:.3f} s)")
-
-    # pair-kernel duration under HIP events on the launch stream (with fused
-    # stages, the one kernel of a stage, which also does the stage update)
-    P.ad_profile_pairs(sim.ctx, True)
-    sim.step(args.profile_steps)
-    kern_ms, launches = P.ad_profile_read(sim.ctx)
-    P.ad_profile_pairs(sim.ctx, False)
-    avg_ms = kern_ms / launches
-    achieved = flops_per_pair * kernel_pairs / (avg_ms * 1e-3) / 1e12
-    log(f"pair kernel: {avg_ms * 1e3:.2f} us avg over {launches} launches, {achieved:.2f} TFLOP/s")
-
-    # plain FP64 form (tiled) timed beside it, on about 2e11 pair terms at most
+    # The plain FP64 form (tiled) and the paper's dense-tensor design are timed
+    # first, each with its own warm-up: the FP32C steps are then measured on a
+    # device that has been busy for a while (at N = 4096 a few dozen steps are
+    # about a millisecond of work, too short for the clocks to settle from idle).
+    # plain FP64 form (tiled), on about 2e11 pair terms at most
     fp64_steps = max(2, min(args.fp64_steps, int(2e11 / pairs_per_step)))
     sim64 = P.Simulator(w.params, sizes, precision="fp64_tiled", graph=not args.no_graph, **model)
     sim64.set_state(w.X, w.phi)
@@ -275,6 +363,30 @@ def main():
         simd.close()
         del simd
 
+    # FP32-compensated path, graph-replayed steps
+    sim = P.Simulator(w.params, sizes, precision=args.precision, graph=not args.no_graph,
+                      launch=launch if args.precision == "fp32c" or form is not None else None, **model)
+    sim.set_state(w.X, w.phi)
+    log(f"fp32c launch {sim.launch}")
+    secs, wall = time_steps(sim, args.steps, args.warmup)
+    assert sim.check() == 0
+    ms_per_step = secs / args.steps * 1e3
+    value = pairs_per_step * args.steps / secs
+    log(f"fp32c: {ms_per_step:.4f} ms/step, {value:.4e} pairs/s (wall {wall:.3f} s)")
+
+    # pair-kernel duration under HIP events on the launch stream (with fused
+    # stages, the one kernel of a stage, which also does the stage update)
+    P.ad_profile_pairs(sim.ctx, True)
+    sim.step(args.profile_steps)
+    kern_ms, launches = P.ad_profile_read(sim.ctx)
+    P.ad_profile_pairs(sim.ctx, False)
+    avg_ms = kern_ms / launches
+    # stage-equivalents the timed launches covered: one per launch, or with
+    # the resident form every stage of every step
+    stage_units = args.profile_steps * stages if sim.launch.get("fused") == 4 else launches
+    achieved = flops_per_pair * kernel_pairs * stage_units / (kern_ms * 1e-3) / 1e12
+    log(f"pair kernel: {avg_ms * 1e3:.2f} us avg over {launches} launches, {achieved:.2f} TFLOP/s")
+
     out = {
         "metric": "Oseen pair interactions/s and sphere-steps/s at N=4096, FP32-comp vs FP64",
         "value": value,
@@ -286,7 +398,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32c" else "f64",
         "data": "synthetic",
         "config": {"workload": describe(args.workload), "name": args.workload,
                    "N": N, "S": S, "systems": len(sizes), "launch": sim.launch, "graph": not args.no_graph},
@@ -296,14 +408,14 @@ def main():
         "speedup_vs_fp64": value / v64,
         "fp64_dense": dense,
         "speedup_vs_dense": value / dense["value"] if dense else None,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak,
                      "traffic": (counted_traffic(sim.launch)
                                  if args.workload == COUNTED["workload"] and not variant else None),
                      "traffic_unit": "B per launch",
                      "kernel": KERNEL_NAMES[sim.launch.get("fused", 0)],
                      "avg_launch_us": avg_ms * 1e3,
-                     "flops_per_launch": flops_per_pair * kernel_pairs},
+                     "flops_per_launch": flops_per_pair * kernel_pairs * stage_units / launches},
     }
     if variant:
         out["config"].update(model)

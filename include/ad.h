@@ -119,6 +119,11 @@ typedef struct ad_launch {
                          3: 16 target spheres per work-group whose waves stream their share of
                          the sources through a small LDS slot each (AD_FP32C, no steric
                          forces, any system size; sources are padded to a multiple of 1024);
+                         4: resident: one work-group per system holds the whole system in
+                         LDS and runs every stage of a run of steps (up to the next record
+                         point) in one launch (AD_FP64 and AD_FP64_TILED: the sequential
+                         FP64 sum, systems of at most 128 spheres; AD_FP32C: at most 256;
+                         no steric forces; for ensembles of small systems);
                          0: pair kernel and epilogue as two kernels */
 } ad_launch;
 
@@ -149,9 +154,11 @@ int ad_bind_workspace(ad_ctx* ctx, void* dev_ptr, uint64_t bytes);
 int ad_set_launch(ad_ctx* ctx, const ad_launch* launch);
 int ad_get_launch(const ad_ctx* ctx, ad_launch* launch);
 
-/* Load a state: X (device, [N_total][3] f64), phases phi (HOST, [S_total]
+/* Load a state: X (device, [N_total][3] f64), phases phi (device, [S_total]
  * f64), and the clock: step n starts at time t0 + n*dt, the state is at step
- * step0. Clears the non-finite flag. */
+ * step0. The phases are copied to the host once, where (sin phi, cos phi)
+ * are taken with libm (Eq. e:swimmer_potential by the addition theorem).
+ * Clears the non-finite flag. Synchronises the stream. */
 int ad_set_state(ad_ctx* ctx, const double* X, const double* phi, double t0, int64_t step0,
                  void* stream);
 
@@ -185,8 +192,10 @@ int ad_run(ad_ctx* ctx, int64_t nsteps, int32_t record_every, double* centres, d
 /* Synchronise the stream and report the flags (AD_OK, AD_ENONFINITE or AD_ERANGE). */
 int ad_check(ad_ctx* ctx, void* stream);
 
-/* Capture one step into a HIP graph and replay it for ad_step/ad_run
- * (enable != 0), or launch kernels directly (enable == 0, the default). */
+/* Capture runs of 16, 4 and 1 steps into HIP graphs (at the first
+ * ad_step/ad_run after enabling, uploaded to the device on that call's
+ * stream) and replay them, longest first, for ad_step/ad_run (enable != 0),
+ * or launch kernels directly (enable == 0, the default). */
 int ad_use_graph(ad_ctx* ctx, int32_t enable);
 
 /* Measurement support. With enable != 0, ad_step/ad_run launch kernels
@@ -197,6 +206,17 @@ int ad_use_graph(ad_ctx* ctx, int32_t enable);
  * (ms) and number of those launches since enabling. */
 int ad_profile_pairs(ad_ctx* ctx, int32_t enable);
 int ad_profile_read(ad_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Measurement support: the issue rate of the FP32 pair term's instruction
+ * mix with operands in registers (kind 0: single-float positions, 2: hi/lo
+ * positions) or of independent FMA chains (kind 1), in `blocks` work-groups
+ * of 256 threads, `iters` trips of 8 terms per thread. sink: device
+ * [blocks*256] f32 (results, kept from being optimised away); clk: device [2]
+ * i64, zeroed by the caller, receives the sums over work-groups of their
+ * shader cycles and of their constant-rate counter ticks (rate:
+ * hipDeviceAttributeWallClockRate), whose ratio is the shader clock under
+ * the load. Asynchronous on stream. */
+int ad_valu_probe(int32_t kind, int32_t blocks, int32_t iters, float* sink, long long* clk, void* stream);
 
 /* ---- Stroke-averaged far-field equations (Sec. III, Eqs. e:eom, J, K) ----
  * For S dumbbells with centres R, unit axes N and phases phi:

@@ -26,7 +26,7 @@ INTEGRATORS = {"rk4": AD_RK4, "heun": AD_HEUN}
 EXPORTS = ("ad_create", "ad_destroy", "ad_workspace_size", "ad_bind_workspace", "ad_set_launch",
            "ad_get_launch", "ad_set_state", "ad_get_state", "ad_forces", "ad_mobility_apply",
            "ad_step", "ad_run", "ad_check", "ad_use_graph", "ad_profile_pairs", "ad_profile_read",
-           "ad_sa_rhs", "ad_sa_workspace_size", "ad_sa_run", "ad_last_error")
+           "ad_valu_probe", "ad_sa_rhs", "ad_sa_workspace_size", "ad_sa_run", "ad_last_error")
 
 
 class ad_params(C.Structure):
@@ -68,7 +68,7 @@ def lib():
         L.ad_bind_workspace.argtypes = [vp, vp, C.c_uint64]
         L.ad_set_launch.argtypes = [vp, C.POINTER(ad_launch)]
         L.ad_get_launch.argtypes = [vp, C.POINTER(ad_launch)]
-        L.ad_set_state.argtypes = [vp, vp, dp, C.c_double, i64, vp]
+        L.ad_set_state.argtypes = [vp, vp, vp, C.c_double, i64, vp]
         L.ad_get_state.argtypes = [vp, vp, dp, C.POINTER(C.c_int64), vp]
         L.ad_forces.argtypes = [vp, vp, C.c_double, vp, vp]
         L.ad_mobility_apply.argtypes = [vp, vp, vp, vp, vp]
@@ -81,6 +81,7 @@ def lib():
         L.ad_sa_rhs.argtypes = [C.POINTER(ad_params), i32, vp, vp, vp, vp, vp, vp]
         L.ad_sa_workspace_size.argtypes = [i32, C.POINTER(C.c_uint64)]
         L.ad_sa_run.argtypes = [C.POINTER(ad_params), i32, vp, vp, vp, C.c_double, i64, vp, C.c_uint64, vp]
+        L.ad_valu_probe.argtypes = [i32, i32, i32, vp, vp, vp]
         L.ad_last_error.argtypes = [vp]
         L.ad_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -166,9 +167,8 @@ def ad_get_launch(ctx) -> dict:
 
 
 def ad_set_state(ctx, X, phi, t0=0.0, step0=0, stream=None) -> None:
-    phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float64))
-    _check(lib().ad_set_state(ctx, _dev(X, "X"), phi.ctypes.data_as(C.POINTER(C.c_double)), float(t0),
-                              int(step0), _stream(stream)), ctx)
+    """X: device (N, 3) float64; phi: device (S,) float64."""
+    _check(lib().ad_set_state(ctx, _dev(X, "X"), _dev(phi, "phi"), float(t0), int(step0), _stream(stream)), ctx)
 
 
 def ad_get_state(ctx, X_out, stream=None):
@@ -222,6 +222,16 @@ def ad_profile_read(ctx):
     n = C.c_int64()
     _check(lib().ad_profile_read(ctx, C.byref(ms), C.byref(n)), ctx)
     return float(ms.value), int(n.value)
+
+
+def ad_valu_probe(kind: int, blocks: int, iters: int, sink, clk, stream=None) -> None:
+    """Issue-rate probe (include/ad.h): sink float32 [blocks*256], clk int64 [2]
+    zeroed, both device tensors."""
+    import torch
+    if sink.dtype != torch.float32 or sink.numel() < blocks * 256 or clk.dtype != torch.int64 or clk.numel() < 2:
+        raise ValueError("sink: float32 [blocks*256], clk: int64 [2]")
+    _check(lib().ad_valu_probe(int(kind), int(blocks), int(iters), C.c_void_p(sink.data_ptr()),
+                               C.c_void_p(clk.data_ptr()), _stream(stream)), None)
 
 
 def _sa_check(code: int, what: str) -> None:
@@ -333,6 +343,10 @@ class Simulator:
     def set_state(self, X, phi, t0=0.0, step0=0):
         import torch
         X = torch.as_tensor(X, dtype=torch.float64).to(self.device).contiguous()
+        if isinstance(phi, torch.Tensor):
+            phi = phi.to(self.device, torch.float64).contiguous()
+        else:
+            phi = torch.as_tensor(np.asarray(phi, dtype=np.float64)).to(self.device).contiguous()
         ad_set_state(self.ctx, X, phi, t0, step0)
 
     def get_state(self):

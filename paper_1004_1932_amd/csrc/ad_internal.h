@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/ad.h"
+
 namespace ad {
 
 /* One work-group's share of a pair sum: target spheres [i0, i0+ni) against
@@ -143,10 +145,44 @@ struct Shape {
     int wg, wj, ipl, split;
     int fused;  /* 0: pair kernel + epilogue; 1: stage kernel, 16 targets per
                    work-group; 2: stage kernel, 64 targets per work-group; 3:
-                   stage kernel, 16 targets, sources streamed per wave */
+                   stage kernel, 16 targets, sources streamed per wave; 4:
+                   resident, one work-group per system for a run of steps */
     int rpy;    /* pair tensor with the RPY-Mazur correction */
     int steric; /* FP32C: record steric candidates while summing */
 };
+
+/* Default launch shape of the pair kernel (not the dense mode) for nsys
+ * systems of at most maxN spheres: FP64 one system-long j-chunk per target
+ * block of 64; small or many systems 64-thread groups over 256-source
+ * chunks; large single systems 256-thread groups (4 waves splitting every
+ * tile in FP32C) and j-chunks that make about 1024 work-groups. */
+struct PairShape {
+    int ipl, wg, wj, jchunk;
+};
+__host__ __device__ inline PairShape default_pair_shape(int prec, int nsys, int maxN) {
+    PairShape L{1, 64, 1, 256};
+    if (prec == PREC_FP64) {
+        L.jchunk = maxN;
+        return L;
+    }
+    if (nsys > 1 || maxN < 1024) return L;
+    L.wg = 256;
+    if (prec == PREC_FP32C) L.wj = 4;
+    const int IB = L.ipl * L.wg / L.wj;
+    const int blocks = (maxN + IB - 1) / IB;
+    const int P = blocks >= 1024 ? 1 : 1024 / blocks;
+    int jc = (maxN + P - 1) / P;
+    jc = (jc + L.wg - 1) / L.wg * L.wg;
+    L.jchunk = jc > L.wg ? jc : L.wg;
+    return L;
+}
+
+/* host helpers (ad_runtime.hip): the model constants of a parameter set,
+ * and the thread's error message of the context-free calls (a fixed
+ * buffer; printf-style, returns code) */
+Coef make_coef(const ad_params* p);
+int thread_fail(int code, const char* fmt, ...);
+void thread_clear_error();
 
 /* kernel launchers (ad_kernels.hip) */
 hipError_t launch_set_step(const Dev& d, long long step, hipStream_t s);
@@ -208,6 +244,47 @@ __host__ __device__ inline int fused_stream_lds_bytes(int split) {
     const int red = 16 * 16 * 6 * 4 + 16 * 3 * 8;
     return b + red;
 }
+/* Resident form (launch.fused = 4): one work-group of RES_T threads per
+ * system holds the whole system in LDS and runs every stage of a run of
+ * steps in one launch. Systems of at most RES_MAX64 spheres with FP64 pair
+ * sums, RES_MAX32 with FP32C. */
+constexpr int RES_T = 256;
+constexpr int RES_MAX64 = 128;
+constexpr int RES_MAX32 = 256;
+/* FP64 term-matrix budget per column chunk */
+constexpr int RES_TERM_BYTES = 64 * 1024;
+/* dynamic LDS a resident work-group may use (the largest need is 81 KiB:
+ * 128 FP64 spheres with RPY); the kernels also hold a little static LDS */
+constexpr int RES_LDS_MAX = 96 * 1024;
+/* source columns of one FP64 term-matrix chunk for a system of n spheres */
+__host__ __device__ inline int resident_cols(int n, int rpy) {
+    const int per = n * 24 * (rpy ? 2 : 1);
+    int cc = RES_TERM_BYTES / (per > 0 ? per : 1);
+    if (cc < 1) cc = 1;
+    return cc < n ? cc : n;
+}
+/* LDS bytes of a resident work-group for a system of n spheres: X, R, Y and
+ * F (FP64, 3n each) and the pair sums (3n, twice with FP64 RPY), then with
+ * FP64 the term-matrix chunk, with FP32C the self-and-partner velocities
+ * (3n doubles) and the float pack A, B (16 B each) and Fz (4 B) */
+__host__ __device__ inline int resident_lds_bytes(int n, int p64, int rpy) {
+    const int dbl = 3 * n * (4 + ((p64 && rpy) ? 2 : 1) + (p64 ? 0 : 1));
+    int b = dbl * 8;
+    b = (b + 15) / 16 * 16;
+    if (p64) return b + resident_cols(n, rpy) * n * 24 * (rpy ? 2 : 1);
+    return b + n * 36;
+}
+/* target lanes per system sphere in the FP32C resident pair sum: the
+ * largest power of two s <= 64 with s n <= RES_T */
+__host__ __device__ inline int resident_split(int n) {
+    int s = 1;
+    while (s < 64 && 2 * s * n <= RES_T) s *= 2;
+    return s;
+}
+hipError_t launch_resident(const Dev& d, const Epi& e, int hilo, int maxNb, long long step0, int nsteps,
+                           double st0, double ct0, hipStream_t s, hipEvent_t ev_start = nullptr,
+                           hipEvent_t ev_stop = nullptr);
+
 /* allow the fused kernels FUSED_LDS_MAX bytes of dynamic LDS (host call,
  * outside any stream capture) */
 hipError_t prepare_fused();

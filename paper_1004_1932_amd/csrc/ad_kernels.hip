@@ -1626,6 +1626,274 @@ __global__ void k_record(Dev d, double* __restrict__ centres, double* __restrict
     }
 }
 
+/* ------------------------------------------------------- resident small systems */
+
+/* Stage update of one component, in the operation order of stage_update,
+ * with the RK accumulator r and the state x held by the caller. */
+__device__ __forceinline__ double res_update(const Coef& c, int integ, int stage, int nst, double k, double& x,
+                                             double& r, double nz) {
+    double y;
+    if (integ == 0) {
+        if (stage == 0) {
+            r = k;
+            y = x + c.h2 * k;
+        } else if (stage == 1) {
+            r = r + 2.0 * k;
+            y = x + c.h2 * k;
+        } else if (stage == 2) {
+            r = r + 2.0 * k;
+            y = x + c.dt * k;
+        } else {
+            y = x + c.dt6 * (r + k);
+        }
+    } else {
+        if (stage == 0) {
+            r = k;
+            y = x + c.dt * k;
+        } else {
+            y = x + c.h2 * (r + k);
+        }
+        if (c.noise) y = y + nz;
+    }
+    if (stage == nst - 1) x = y;
+    return y;
+}
+
+/* Resident form (ad_launch.fused = 4): one work-group per system, the whole
+ * system in LDS, every stage of nsteps steps in one launch with work-group
+ * barriers between the phases of a stage:
+ *   pair sums at the stage positions Y and forces F;
+ *   closing: velocity, stage update (state X and RK accumulator R stay in
+ *   LDS), next stage positions;
+ *   forces of the next stage at the table's (sin, cos)(omega t), one thread
+ *   per dumbbell.
+ * P64 = 1: the plain FP64 sum, bitwise that of the sequential oracle: the
+ *   terms of a chunk of source columns are evaluated in parallel into LDS,
+ *   then every (target, component) adds its row of the chunk in ascending j.
+ * P64 = 0: FP32C. Each target has `split` adjacent lanes that take every
+ *   split-th source in ascending order (self and partner skipped: they are in
+ *   the FP64 self-and-partner velocity U0), fold their FP32 sum into a
+ *   (hi, lo) pair with TwoSum every 32 sources, and are combined by shuffles
+ *   in a fixed tree.
+ * The state comes from and returns to d.X; the first stage's forces are
+ * formed at (st0, ct0) = (sin, cos)(omega t) of step step0. */
+template <int P64, int SPLIT, int RPY>
+__global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step0, int nsteps, double st0,
+                                                    double ct0) {
+    extern __shared__ double res_lds[];
+    const Item it = d.fitems[blockIdx.x];
+    const int n = it.Nb, ioff = it.ioff, S = n / 2;
+    const int N = d.Ntot;
+    const int tid = threadIdx.x;
+    const Coef& c = e.c;
+    double* X = res_lds;
+    double* R = X + 3 * n;
+    double* Y = R + 3 * n;
+    double* F = Y + 3 * n;
+    double* Acc = F + 3 * n; /* pair sums [3n] (FP64 RPY: [6n]) */
+    double* U0 = Acc + 3 * n;
+    double* Bcc = Acc + 3 * n;
+    char* tail = reinterpret_cast<char*>(res_lds) +
+                 ((3 * n * (4 + ((P64 && RPY) ? 2 : 1) + (P64 ? 0 : 1))) * 8 + 15) / 16 * 16;
+    double* T = reinterpret_cast<double*>(tail); /* FP64 term chunk [n][cc][3] (RPY: then [n][cc][3]) */
+    float4* pA = reinterpret_cast<float4*>(tail);
+    float4* pB = pA + n;
+    float* pz = reinterpret_cast<float*>(pB + n);
+    const int cc = P64 ? resident_cols(n, RPY) : 0;
+    double* Tb = T + 3 * n * cc;
+    const int split = P64 ? 1 : resident_split(n);
+
+    /* state in, phases of this thread's dumbbell */
+    for (int q = tid; q < 3 * n; q += RES_T) {
+        const int a = q / n, i = q - a * n;
+        const double v = d.X[a * N + ioff + i];
+        X[q] = v;
+        Y[q] = v;
+    }
+    double2 tp = make_double2(0.0, 0.0);
+    if (tid < S) tp = d.phitrig[(ioff >> 1) + tid];
+    int bad = 0;
+    __syncthreads();
+
+    /* forces (and for FP32C the pack and U0) at the positions Y */
+    auto forces = [&](double st, double ct) {
+        if (tid < S) {
+            const int i0 = 2 * tid;
+            double y0[3], y1[3], f0[3], f1[3];
+            for (int a = 0; a < 3; ++a) {
+                y0[a] = Y[a * n + i0];
+                y1[a] = Y[a * n + i0 + 1];
+            }
+            if (P64) {
+                spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+            } else {
+                spring_forces_rs(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+            }
+            for (int a = 0; a < 3; ++a) {
+                F[a * n + i0] = f0[a];
+                F[a * n + i0 + 1] = f1[a];
+            }
+            if (!P64) {
+                for (int h = 0; h < 2; ++h) {
+                    const double* y = h ? y1 : y0;
+                    const double* yp = h ? y0 : y1;
+                    const double* f = h ? f1 : f0;
+                    const double* fp = h ? f0 : f1;
+                    const double r[3] = {y[0] - yp[0], y[1] - yp[1], y[2] - yp[2]};
+                    const double ir = rsqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+                    const double ir2 = ir * ir;
+                    const double tt = ((r[0] * fp[0] + r[1] * fp[1]) + r[2] * fp[2]) * ir2;
+                    for (int a = 0; a < 3; ++a) {
+                        double u = c.cs * f[a] + c.co * (ir * (fp[a] + tt * r[a]));
+                        if (RPY) u = u + c.cr * ((ir * ir2) * (fp[a] - (3.0 * tt) * r[a]));
+                        U0[a * n + i0 + h] = u;
+                    }
+                    float hi[3], lo[3];
+                    for (int a = 0; a < 3; ++a) split_f32(y[a], hi[a], lo[a]);
+                    pA[i0 + h] = make_float4(hi[0], hi[1], hi[2], (float)f[0]);
+                    pB[i0 + h] = make_float4(lo[0], lo[1], lo[2], (float)f[1]);
+                    pz[i0 + h] = (float)f[2];
+                }
+            }
+        }
+        __syncthreads();
+    };
+    forces(st0, ct0);
+
+    const float crr = c.crr;
+    for (int sn = 0; sn < nsteps; ++sn) {
+        const long long step = step0 + sn;
+        const long long row = step % d.ring;
+        for (int stage = 0; stage < e.nst; ++stage) {
+            /* ---- pair sums */
+            if (P64) {
+                for (int j0 = 0; j0 < n; j0 += cc) {
+                    const int nc = min(cc, n - j0);
+                    for (int p = tid; p < n * nc; p += RES_T) {
+                        const int i = p / nc, jj = p - i * nc, j = j0 + jj;
+                        double* t = T + (i * cc + jj) * 3;
+                        double* tb = Tb + (i * cc + jj) * 3;
+                        const double r[3] = {Y[i] - Y[j], Y[n + i] - Y[n + j], Y[2 * n + i] - Y[2 * n + j]};
+                        const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+                        if (j == i || r2 == 0.0) {
+                            if (j != i) bad = 1;
+                            t[0] = t[1] = t[2] = 0.0;
+                            if (RPY) tb[0] = tb[1] = tb[2] = 0.0;
+                            continue;
+                        }
+                        const double Fj[3] = {F[j], F[n + j], F[2 * n + j]};
+                        oseen_term64(r, Fj, t);
+                        if (RPY) rpy_term64(r, Fj, tb);
+                    }
+                    __syncthreads();
+                    for (int q = tid; q < 3 * n; q += RES_T) {
+                        const int i = q / 3, a = q - 3 * i;
+                        double acc = (j0 == 0) ? 0.0 : Acc[q];
+                        double bcc = (RPY && j0 > 0) ? Bcc[q] : 0.0;
+                        for (int jj = 0; jj < nc; ++jj) {
+                            if (j0 + jj == i) continue;
+                            acc = acc + T[(i * cc + jj) * 3 + a];
+                            if (RPY) bcc = bcc + Tb[(i * cc + jj) * 3 + a];
+                        }
+                        Acc[q] = acc;
+                        if (RPY) Bcc[q] = bcc;
+                    }
+                    __syncthreads();
+                }
+            } else {
+                const int t = tid / split, sub = tid - t * split;
+                float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+                if (t < n) {
+                    const float4 Ai = pA[t];
+                    const float4 Bi = pB[t];
+                    const int dt = t >> 1;
+                    float px = 0.f, py = 0.f, pzz = 0.f;
+                    int cnt = 0;
+                    for (int j = sub; j < n; j += split) {
+                        if ((j >> 1) == dt) continue;
+                        const float4 Aj = pA[j];
+                        const float4 Bj = pB[j];
+                        float rx, ry, rz;
+                        if (SPLIT) {
+                            rx = (Ai.x - Aj.x) + (Bi.x - Bj.x);
+                            ry = (Ai.y - Aj.y) + (Bi.y - Bj.y);
+                            rz = (Ai.z - Aj.z) + (Bi.z - Bj.z);
+                        } else {
+                            rx = Ai.x - Aj.x;
+                            ry = Ai.y - Aj.y;
+                            rz = Ai.z - Aj.z;
+                        }
+                        const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                        const float ir = __builtin_amdgcn_rsqf(r2);
+                        pair_term<RPY>(ir, rx, ry, rz, Aj.w, Bj.w, pz[j], crr, px, py, pzz);
+                        if (++cnt == 32) {
+                            two_sum_acc(ax, bx, px);
+                            two_sum_acc(ay, by, py);
+                            two_sum_acc(az, bz, pzz);
+                            px = py = pzz = 0.f;
+                            cnt = 0;
+                        }
+                    }
+                    two_sum_acc(ax, bx, px);
+                    two_sum_acc(ay, by, py);
+                    two_sum_acc(az, bz, pzz);
+                }
+                auto combine = [](float& hi, float& lo, float oh, float ol) {
+                    const float s = hi + oh;
+                    const float bb = s - hi;
+                    const float err = (hi - (s - bb)) + (oh - bb);
+                    hi = s;
+                    lo = (lo + ol) + err;
+                };
+                for (int sh = 1; sh < split; sh *= 2) {
+                    const float oax = __shfl_xor(ax, sh), obx = __shfl_xor(bx, sh);
+                    const float oay = __shfl_xor(ay, sh), oby = __shfl_xor(by, sh);
+                    const float oaz = __shfl_xor(az, sh), obz = __shfl_xor(bz, sh);
+                    combine(ax, bx, oax, obx);
+                    combine(ay, by, oay, oby);
+                    combine(az, bz, oaz, obz);
+                }
+                if (t < n && sub == 0) {
+                    Acc[t] = (double)ax + (double)bx;
+                    Acc[n + t] = (double)ay + (double)by;
+                    Acc[2 * n + t] = (double)az + (double)bz;
+                }
+                __syncthreads();
+            }
+            /* ---- closing: velocity, stage update, next stage positions */
+            for (int q = tid; q < 3 * n; q += RES_T) {
+                int i, a, o;
+                double k;
+                if (P64) {
+                    i = q / 3;
+                    a = q - 3 * i;
+                    o = a * n + i;
+                    k = c.cs * F[o] + c.co * Acc[q];
+                    if (RPY) k = k + c.cr * Bcc[q];
+                } else {
+                    a = q / n;
+                    i = q - a * n;
+                    o = q;
+                    k = U0[o] + c.co * Acc[o];
+                }
+                if (!isfinite(k)) bad = 1;
+                const double nz = (e.integ == 1 && c.noise) ? c.g * gauss_component(c.seed, ioff + i, step, a) : 0.0;
+                double x = X[o], r = R[o];
+                Y[o] = res_update(c, e.integ, stage, e.nst, k, x, r, nz);
+                X[o] = x;
+                R[o] = r;
+            }
+            __syncthreads();
+            forces(d.tab[row * 8 + 2 * stage], d.tab[row * 8 + 2 * stage + 1]);
+        }
+    }
+    for (int q = tid; q < 3 * n; q += RES_T) {
+        const int a = q / n, i = q - a * n;
+        d.X[a * N + ioff + i] = X[q];
+    }
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+}
+
 /* ------------------------------------------------------------ launchers */
 
 static inline dim3 blocks_for(int n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
@@ -1790,9 +2058,48 @@ hipError_t prepare_fused() {
                              reinterpret_cast<const void*>(&k_stage_fused<1, 1, 4>)};
     for (const void* k : kernels) {
         hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, FUSED_LDS_MAX);
-        if (err != hipSuccess) return err;
+        if (err != hipSuccess) {
+            (void)hipGetLastError(); /* a later launch check must not report it again */
+            return err;
+        }
+    }
+    const void* resident[] = {reinterpret_cast<const void*>(&k_resident<1, 0, 0>),
+                              reinterpret_cast<const void*>(&k_resident<1, 0, 1>),
+                              reinterpret_cast<const void*>(&k_resident<0, 0, 0>),
+                              reinterpret_cast<const void*>(&k_resident<0, 0, 1>),
+                              reinterpret_cast<const void*>(&k_resident<0, 1, 0>),
+                              reinterpret_cast<const void*>(&k_resident<0, 1, 1>)};
+    for (const void* k : resident) {
+        hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, RES_LDS_MAX);
+        if (err != hipSuccess) {
+            (void)hipGetLastError();
+            return err;
+        }
     }
     return hipSuccess;
+}
+
+hipError_t launch_resident(const Dev& d, const Epi& e, int hilo, int maxNb, long long step0, int nsteps,
+                           double st0, double ct0, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+    if (d.nfitems <= 0 || nsteps <= 0) return hipErrorInvalidValue;
+    const int p64 = e.prec != PREC_FP32C;
+    const int rpy = e.c.rpy;
+    if (maxNb > (p64 ? RES_MAX64 : RES_MAX32)) return hipErrorInvalidValue;
+    const size_t lds = (size_t)resident_lds_bytes(maxNb, p64, rpy);
+    if (lds > (size_t)RES_LDS_MAX) return hipErrorInvalidValue;
+    void (*kern)(Dev, Epi, long long, int, double, double);
+    if (p64)
+        kern = rpy ? k_resident<1, 0, 1> : k_resident<1, 0, 0>;
+    else if (hilo)
+        kern = rpy ? k_resident<0, 1, 1> : k_resident<0, 1, 0>;
+    else
+        kern = rpy ? k_resident<0, 0, 1> : k_resident<0, 0, 0>;
+    if (ev_start)
+        hipExtLaunchKernelGGL(kern, dim3(d.nfitems), dim3(RES_T), lds, s, ev_start, ev_stop, 0, d, e, step0, nsteps,
+                              st0, ct0);
+    else
+        hipLaunchKernelGGL(kern, dim3(d.nfitems), dim3(RES_T), lds, s, d, e, step0, nsteps, st0, ct0);
+    return hipGetLastError();
 }
 
 hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, int maxNb, hipStream_t s,

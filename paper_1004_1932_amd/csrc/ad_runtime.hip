@@ -26,10 +26,16 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kTabSteps = 4096;          /* steps per table chunk */
-constexpr int kGraphSteps = 16;          /* steps per graph launch in runs of steps */
+/* steps per graph of a run of steps, longest first: a run replays the
+ * longest graph that fits before the next record point or table chunk */
+constexpr int kGraphSteps[] = {16, 4, 1};
+constexpr int kGraphs = 3;
 constexpr int kRing = 2 * kTabSteps;     /* table entries (two chunks) */
 
-thread_local std::string g_create_error;
+/* message of the last failure of a context-free call on this thread
+ * (ad_create, ad_mobility_apply_static); a fixed buffer, so that setting it
+ * allocates nothing */
+thread_local char g_thread_error[512];
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -70,18 +76,17 @@ struct ad_ctx {
 
     /* pinned host staging */
     double* h_tab = nullptr;    /* kRing*8 */
-    double2* h_phi = nullptr;   /* Stot */
+    double2* h_phi = nullptr;   /* Stot (sin phi, cos phi) */
+    double* h_phi_in = nullptr; /* Stot phases copied from the caller's device array */
     int* h_flag = nullptr;
     hipEvent_t tab_event = nullptr;
     bool tab_event_live = false;
 
-    /* graphs of one step and of kGraphSteps steps: one graph launch costs
-     * several microseconds, so runs of steps replay the longer graph */
+    /* graphs of kGraphSteps[g] steps: one graph launch costs several
+     * microseconds, so runs of steps replay the longest graph that fits */
     bool use_graph = false;
-    hipGraphExec_t graph_exec = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_run_exec = nullptr;
-    hipGraph_t graph_run = nullptr;
+    hipGraphExec_t graph_exec[kGraphs] = {};
+    hipGraph_t graph[kGraphs] = {};
     hipStream_t capture_stream = nullptr;
 
     /* pair-kernel timing */
@@ -103,9 +108,41 @@ static int fail(ad_ctx* c, int code, const char* fmt, ...) {
     if (c)
         c->err = buf;
     else
-        g_create_error = buf;
+        memcpy(g_thread_error, buf, sizeof g_thread_error);
     return code;
 }
+
+namespace ad {
+int thread_fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_thread_error, sizeof g_thread_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+void thread_clear_error() { g_thread_error[0] = 0; }
+
+Coef make_coef(const ad_params* p) {
+    Coef k{};
+    k.cs = 1.0 / (6.0 * kPi * p->eta * p->a);
+    k.co = 1.0 / (8.0 * kPi * p->eta);
+    k.k = p->k;
+    k.ell = p->ell;
+    k.lam = p->lambda;
+    k.dt = p->dt;
+    k.h2 = 0.5 * p->dt;
+    k.dt6 = p->dt / 6.0;
+    k.ks = p->steric_k;
+    k.rc = p->steric_r;
+    k.cr = 2.0 * p->a * p->a / (24.0 * kPi * p->eta);
+    k.crr = (float)(2.0 * p->a * p->a / 3.0);
+    k.rpy = p->tensor == AD_RPY ? 1 : 0;
+    k.noise = p->kT > 0.0 ? 1 : 0;
+    k.g = sqrt(2.0 * p->kT * (1.0 / (6.0 * kPi * p->eta * p->a)) * p->dt);
+    k.seed = p->seed;
+    return k;
+}
+}  // namespace ad
 
 #define HIPCHECK(ctx, expr)                                                                       \
     do {                                                                                          \
@@ -119,6 +156,7 @@ static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 /* ------------------------------------------------------------ work list */
 
 static bool is_dense(const ad_ctx* c) { return c->p.precision == AD_FP64_DENSE; }
+static int prec_of(const ad_ctx* c);
 
 /* dense mode: tensor bytes over all systems, 72 Nb^2 each */
 static double dense_bytes(int nsys, const int32_t* S) {
@@ -145,28 +183,11 @@ static ad_launch default_launch(const ad_ctx* c) {
         L.jchunk = jc;
         return L;
     }
-    if (c->p.precision == AD_FP64) {
-        L.ipl = 1;
-        L.wg = 64;
-        L.jchunk = maxN;
-        return L;
-    }
-    if (c->nsys > 1 || maxN < 1024) {
-        L.wg = 64;
-        L.ipl = 1;
-        L.jchunk = 256;
-        return L;
-    }
-    L.wg = 256;
-    L.ipl = 1;
-    if (c->p.precision == AD_FP32C) L.wj = 4;
-    /* about 1024 work-groups of 4 waves; j-chunks a multiple of the tile */
-    const int IB = L.ipl * L.wg / L.wj;
-    const int blocks = (maxN + IB - 1) / IB;
-    const int P = std::max(1, 1024 / blocks);
-    int jc = (maxN + P - 1) / P;
-    jc = std::max(L.wg, (jc + L.wg - 1) / L.wg * L.wg);
-    L.jchunk = jc;
+    const ad::PairShape sh = ad::default_pair_shape(prec_of(c), c->nsys, maxN);
+    L.ipl = sh.ipl;
+    L.wg = sh.wg;
+    L.wj = sh.wj;
+    L.jchunk = sh.jchunk;
     return L;
 }
 
@@ -186,7 +207,16 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
     if (c->p.precision == AD_FP32C && L.posmode != AD_POS_HILO && L.posmode != AD_POS_SINGLE)
         return fail(c, AD_EINVAL, "launch.posmode must be AD_POS_HILO or AD_POS_SINGLE");
     if (L.jchunk < 64 && c->p.precision != AD_FP64) return fail(c, AD_EINVAL, "launch.jchunk must be >= 64");
-    if (L.fused < 0 || L.fused > 3) return fail(c, AD_EINVAL, "launch.fused must be 0, 1, 2 or 3");
+    if (L.fused < 0 || L.fused > 4) return fail(c, AD_EINVAL, "launch.fused must be 0, 1, 2, 3 or 4");
+    if (L.fused == 4) {
+        const int p64 = c->p.precision != AD_FP32C;
+        if (c->p.steric_k != 0.0) return fail(c, AD_EINVAL, "launch.fused 4 takes no steric forces");
+        const int lim = p64 ? ad::RES_MAX64 : ad::RES_MAX32;
+        if (c->maxNb > lim)
+            return fail(c, AD_EINVAL, "launch.fused 4: systems of at most %d spheres in this precision (got %d)", lim,
+                        c->maxNb);
+        return AD_OK;
+    }
     if (L.fused) {
         if (c->p.precision != AD_FP32C || c->p.steric_k != 0.0)
             return fail(c, AD_EINVAL, "launch.fused needs AD_FP32C and no steric forces");
@@ -303,7 +333,20 @@ static void build_items(ad_ctx* c) {
      * ensemble in the first and the streamed form, 64 in the wide form, for
      * one system too), longest system first */
     c->fitems.clear();
-    if (((c->launch.fused == 1 || c->launch.fused == 3) && c->nsys > 1) || c->launch.fused == 2) {
+    if (c->launch.fused == 4) {
+        /* resident form: one work-group per system, longest first */
+        for (int b = 0; b < c->nsys; ++b) {
+            Item it{};
+            it.sys = b;
+            it.i0 = c->off[b];
+            it.ni = 2 * c->S[b];
+            it.ioff = c->off[b];
+            it.Nb = 2 * c->S[b];
+            c->fitems.push_back(it);
+        }
+        std::stable_sort(c->fitems.begin(), c->fitems.end(),
+                         [](const Item& a, const Item& b) { return a.Nb > b.Nb; });
+    } else if (((c->launch.fused == 1 || c->launch.fused == 3) && c->nsys > 1) || c->launch.fused == 2) {
         const int blk = c->launch.fused == 2 ? ad::FW_I : c->launch.fused == 3 ? ad::FT_I : 16;
         for (int b = 0; b < c->nsys; ++b) {
             const int Nb = 2 * c->S[b];
@@ -435,14 +478,12 @@ static void make_dev(ad_ctx* c) {
 }
 
 static void drop_graph(ad_ctx* c) {
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    if (c->graph_run_exec) (void)hipGraphExecDestroy(c->graph_run_exec);
-    if (c->graph_run) (void)hipGraphDestroy(c->graph_run);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
-    c->graph_run_exec = nullptr;
-    c->graph_run = nullptr;
+    for (int g = 0; g < kGraphs; ++g) {
+        if (c->graph_exec[g]) (void)hipGraphExecDestroy(c->graph_exec[g]);
+        if (c->graph[g]) (void)hipGraphDestroy(c->graph[g]);
+        c->graph_exec[g] = nullptr;
+        c->graph[g] = nullptr;
+    }
 }
 
 /* upload the work list and the per-system tables (synchronous) */
@@ -570,6 +611,28 @@ static int launch_pairs_timed(ad_ctx* c, const Dev& d, const ad::Epi& e, int mod
     return AD_OK;
 }
 
+/* a run of nsteps steps in the resident form, timed like a pair launch */
+static int launch_resident_timed(ad_ctx* c, long long step0, int nsteps, double st0, double ct0, hipStream_t st) {
+    const ad::Epi e = epi_of(c, 0, nullptr);
+    const int hilo = c->launch.posmode == AD_POS_HILO ? 1 : 0;
+    if (!c->profile) {
+        HIPCHECK(c, ad::launch_resident(c->dev, e, hilo, c->maxNb, step0, nsteps, st0, ct0, st));
+        return AD_OK;
+    }
+    if (c->ev.empty()) {
+        c->ev.resize(2 * kEventPairs);
+        for (auto& ev : c->ev) HIPCHECK(c, hipEventCreate(&ev));
+    }
+    if (c->ev_used == kEventPairs) {
+        int rc = profile_flush(c);
+        if (rc != AD_OK) return rc;
+    }
+    HIPCHECK(c, ad::launch_resident(c->dev, e, hilo, c->maxNb, step0, nsteps, st0, ct0, st, c->ev[2 * c->ev_used],
+                                    c->ev[2 * c->ev_used + 1]));
+    c->ev_used += 1;
+    return AD_OK;
+}
+
 /* launches of one step (no table, no initial pack) */
 static int launch_step_kernels(ad_ctx* c, hipStream_t st) {
     const int nst = c->p.integrator == AD_RK4 ? 4 : 2;
@@ -603,12 +666,18 @@ static int capture_steps(ad_ctx* c, int nsteps, hipGraph_t* graph, hipGraphExec_
     return AD_OK;
 }
 
-static int ensure_graph(ad_ctx* c) {
-    if (c->graph_exec && c->graph_run_exec) return AD_OK;
+/* capture every graph and upload each to the device on the call's stream,
+ * so that the first replay of each pays no upload */
+static int ensure_graph(ad_ctx* c, hipStream_t st) {
+    if (c->graph_exec[kGraphs - 1]) return AD_OK;
     drop_graph(c);
     if (!c->capture_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
-    int rc = capture_steps(c, 1, &c->graph, &c->graph_exec);
-    if (rc == AD_OK) rc = capture_steps(c, kGraphSteps, &c->graph_run, &c->graph_run_exec);
+    int rc = AD_OK;
+    for (int g = 0; g < kGraphs && rc == AD_OK; ++g) {
+        rc = capture_steps(c, kGraphSteps[g], &c->graph[g], &c->graph_exec[g]);
+        if (rc == AD_OK && hipGraphUpload(c->graph_exec[g], st) != hipSuccess)
+            rc = fail(c, AD_EDEVICE, "hipGraphUpload failed");
+    }
     if (rc != AD_OK) drop_graph(c);
     return rc;
 }
@@ -624,13 +693,14 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
     if (nsteps < 0) return fail(c, AD_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return AD_OK;
     const int prec = prec_of(c);
-    const bool graph = c->use_graph && !c->profile;
+    const bool resident = c->launch.fused == 4;
+    const bool graph = c->use_graph && !c->profile && !resident;
     if (graph) {
-        int rc = ensure_graph(c);
+        int rc = ensure_graph(c, st);
         if (rc != AD_OK) return rc;
     }
     HIPCHECK(c, ad::launch_set_step(c->dev, c->step, st));
-    if (!c->pack_valid) {
+    if (!c->pack_valid && !resident) {
         double s0, c0;
         trig_at(c, c->t0 + (double)c->step * c->p.dt, &s0, &c0);
         HIPCHECK(c, ad::launch_pack_state(c->dev, c->coef, prec, s0, c0, st));
@@ -645,16 +715,22 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
             /* steps left before the next record point or the chunk's end */
             long long room = chunk - q;
             if (record_every > 0) room = std::min<long long>(room, record_every - (done + q) % record_every);
-            if (graph && room >= kGraphSteps) {
-                HIPCHECK(c, hipGraphLaunch(c->graph_run_exec, st));
-                q += kGraphSteps;
+            if (resident) {
+                /* every step of the run in one launch */
+                const long long n0 = c->step + done + q;
+                double s0, c0;
+                trig_at(c, c->t0 + (double)n0 * c->p.dt, &s0, &c0);
+                rc = launch_resident_timed(c, n0, (int)room, s0, c0, st);
+                if (rc != AD_OK) return rc;
+                q += (int)room;
+            } else if (graph) {
+                int g = 0;
+                while (kGraphSteps[g] > room) ++g; /* the last graph is one step */
+                HIPCHECK(c, hipGraphLaunch(c->graph_exec[g], st));
+                q += kGraphSteps[g];
             } else {
-                if (graph) {
-                    HIPCHECK(c, hipGraphLaunch(c->graph_exec, st));
-                } else {
-                    rc = launch_step_kernels(c, st);
-                    if (rc != AD_OK) return rc;
-                }
+                rc = launch_step_kernels(c, st);
+                if (rc != AD_OK) return rc;
                 q += 1;
             }
             const long long n = done + q;
@@ -668,7 +744,8 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
         done += chunk;
     }
     c->step += nsteps;
-    c->pack_valid = true;
+    /* the resident form keeps its stages in LDS and leaves no pack behind */
+    c->pack_valid = !resident;
     return AD_OK;
 }
 
@@ -688,7 +765,7 @@ static int read_flag(ad_ctx* c, hipStream_t st) {
 extern "C" {
 
 int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx** out) {
-    g_create_error.clear();
+    g_thread_error[0] = 0;
     if (!p || !S_per_sys || !out) return fail(nullptr, AD_EINVAL, "null argument");
     *out = nullptr;
     if (nsys <= 0) return fail(nullptr, AD_EINVAL, "nsys must be >= 1");
@@ -728,23 +805,7 @@ int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx
     c->dsys.resize(c->Stot);
     for (int b = 0, s = 0; b < nsys; ++b)
         for (int q = 0; q < c->S[b]; ++q) c->dsys[s++] = b;
-    Coef& k = c->coef;
-    k.cs = 1.0 / (6.0 * kPi * p->eta * p->a);
-    k.co = 1.0 / (8.0 * kPi * p->eta);
-    k.k = p->k;
-    k.ell = p->ell;
-    k.lam = p->lambda;
-    k.dt = p->dt;
-    k.h2 = 0.5 * p->dt;
-    k.dt6 = p->dt / 6.0;
-    k.ks = p->steric_k;
-    k.rc = p->steric_r;
-    k.cr = 2.0 * p->a * p->a / (24.0 * kPi * p->eta);
-    k.crr = (float)(2.0 * p->a * p->a / 3.0);
-    k.rpy = p->tensor == AD_RPY ? 1 : 0;
-    k.noise = p->kT > 0.0 ? 1 : 0;
-    k.g = sqrt(2.0 * p->kT * (1.0 / (6.0 * kPi * p->eta * p->a)) * p->dt);
-    k.seed = p->seed;
+    c->coef = ad::make_coef(p);
     c->omega = 2.0 * kPi / p->T;
     for (int b = 0; b < nsys; ++b) c->maxNb = std::max(c->maxNb, 2 * c->S[b]);
     c->launch = default_launch(c);
@@ -761,6 +822,7 @@ int ad_destroy(ad_ctx* c) {
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     if (c->h_tab) (void)hipHostFree(c->h_tab);
     if (c->h_phi) (void)hipHostFree(c->h_phi);
+    if (c->h_phi_in) (void)hipHostFree(c->h_phi_in);
     if (c->h_flag) (void)hipHostFree(c->h_flag);
     delete c;
     return AD_OK;
@@ -782,6 +844,7 @@ int ad_bind_workspace(ad_ctx* c, void* ptr, uint64_t bytes) {
     if (!c->h_tab) {
         HIPCHECK(c, hipHostMalloc((void**)&c->h_tab, (size_t)kRing * 8 * sizeof(double), hipHostMallocDefault));
         HIPCHECK(c, hipHostMalloc((void**)&c->h_phi, (size_t)c->Stot * sizeof(double2), hipHostMallocDefault));
+        HIPCHECK(c, hipHostMalloc((void**)&c->h_phi_in, (size_t)c->Stot * sizeof(double), hipHostMallocDefault));
         HIPCHECK(c, hipHostMalloc((void**)&c->h_flag, sizeof(int), hipHostMallocDefault));
         HIPCHECK(c, hipEventCreateWithFlags(&c->tab_event, hipEventDisableTiming));
     }
@@ -836,9 +899,14 @@ int ad_set_state(ad_ctx* c, const double* X, const double* phi, double t0, int64
     if (!X || !phi) return fail(c, AD_EINVAL, "null X or phi");
     if (!isfinite(t0) || step0 < 0) return fail(c, AD_EINVAL, "t0 must be finite and step0 >= 0");
     hipStream_t st = as_stream(stream);
+    /* the phases come to the host once: (sin phi, cos phi) are taken with
+     * the host libm, like every sin and cos of the rest length */
+    HIPCHECK(c, hipMemcpyAsync(c->h_phi_in, phi, (size_t)c->Stot * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(c, hipStreamSynchronize(st));
     for (int s = 0; s < c->Stot; ++s) {
-        if (!isfinite(phi[s])) return fail(c, AD_EINVAL, "phi[%d] is not finite", s);
-        c->h_phi[s] = make_double2(sin(phi[s]), cos(phi[s]));
+        const double ph = c->h_phi_in[s];
+        if (!isfinite(ph)) return fail(c, AD_EINVAL, "phi[%d] is not finite", s);
+        c->h_phi[s] = make_double2(sin(ph), cos(ph));
     }
     HIPCHECK(c, hipMemcpyAsync(const_cast<double2*>(c->dev.phitrig), c->h_phi, (size_t)c->Stot * sizeof(double2),
                                hipMemcpyHostToDevice, st));
@@ -942,7 +1010,7 @@ int ad_profile_read(ad_ctx* c, double* total_ms, int64_t* launches) {
 }
 
 const char* ad_last_error(const ad_ctx* c) {
-    if (!c) return g_create_error.c_str();
+    if (!c) return g_thread_error;
     return c->err.c_str();
 }
 

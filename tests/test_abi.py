@@ -289,3 +289,27 @@ def test_bench_refuses_more_than_one_gpu():
                          text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in json.loads(res.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_resident_launch_limits():
+    """launch.fused = 4 (one work-group per system for a run of steps) takes
+    systems of at most 256 spheres in AD_FP32C and 128 in the FP64 modes, and
+    no steric forces; refused before any device work."""
+    def try_launch(S, precision, steric=False):
+        p = replace(Params(), steric_k=100.0) if steric else Params()
+        ctx = P.ad_create(P.make_params(p, precision), S)
+        try:
+            P.ad_set_launch(ctx, ipl=1, jchunk=256, wg=64, wj=1, posmode=1 if precision == "fp32c" else 0,
+                            fused=4)
+            return B.AD_OK
+        except P.ADError as e:
+            return e.code
+        finally:
+            P.ad_destroy(ctx)
+    assert try_launch([128, 3], "fp32c") == B.AD_OK
+    assert try_launch([129], "fp32c") == B.AD_EINVAL
+    assert try_launch([64, 10], "fp64") == B.AD_OK
+    assert try_launch([65], "fp64") == B.AD_EINVAL
+    assert try_launch([64], "fp64_tiled") == B.AD_OK
+    assert try_launch([20], "fp32c", steric=True) == B.AD_EINVAL
+    assert try_launch([20], "fp64_dense") == B.AD_EINVAL

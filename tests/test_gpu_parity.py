@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import paper_1004_1932_amd as P
+from parity_metrics import check_fp32c
 from workload import Params, make_ensemble, make_single, make_preset
 
 pytestmark = pytest.mark.gpu
@@ -135,11 +136,9 @@ def test_mobility_fp32c(oracle, S, side, launch):
     s.set_state(sus.X, sus.phi)
     F = oracle.forces(sus.params, X, sus.phi, 7.0)
     u = s.mobility(X, F).cpu().numpy()
-    e1 = relerr(u, oracle.mobility(sus.params, X, F))
+    check_fp32c(u, oracle.mobility(sus.params, X, F), "spring forces")
     G = np.random.default_rng(7).standard_normal(X.shape)
-    e2 = relerr(s.mobility(X, G).cpu().numpy(), oracle.mobility(sus.params, X, G))
-    say(f"  rel err spring-forces {e1:.3e} random-forces {e2:.3e}")
-    assert e1 <= 1e-6 and e2 <= 1e-6
+    check_fp32c(s.mobility(X, G).cpu().numpy(), oracle.mobility(sus.params, X, G), "random forces")
 
 
 @pytest.mark.parametrize("launch", [None, "tuned",
@@ -159,9 +158,7 @@ def test_mobility_fp32c_full_size_sampled(oracle, launch):
     u = s.mobility(X, F).cpu().numpy()
     rows = np.random.default_rng(7).choice(sus.N, 64, replace=False)
     uo = oracle.mobility_rows(sus.params, X, F, rows)
-    err = relerr(u[rows], uo)
-    say(f"  rel err {err:.3e}")
-    assert err <= 1e-6
+    check_fp32c(u[rows], uo, "64 sampled rows")
     del s
     torch.cuda.empty_cache()
 
@@ -241,9 +238,7 @@ def test_trajectory_fp32c_drift(oracle, name, nsteps, launch):
     assert max(drift) <= 1e-4
     t = nsteps * sus.params.dt
     F = oracle.forces(sus.params, Xg, sus.phi, t)
-    err = relerr(s.mobility(Xg, F).cpu().numpy(), oracle.mobility(sus.params, Xg, F))
-    say(f"  velocity rel err at the final state {err:.2e}")
-    assert err <= 1e-6
+    check_fp32c(s.mobility(Xg, F).cpu().numpy(), oracle.mobility(sus.params, Xg, F), "final-state velocity")
 
 
 def test_graph_equals_direct_launches(oracle):
@@ -359,7 +354,7 @@ def test_ensemble_matches_oracle(oracle, precision):
         for b in range(len(sizes)):
             sl = slice(off[b], off[b + 1])
             uo = oracle.mobility(ens.params, Xg[sl], F[sl])
-            assert relerr(u[sl], uo) <= 1e-6, b
+            check_fp32c(u[sl], uo, f"system {b}")
         assert np.abs(Xg - Xo).max() < 1e-6
 
 
@@ -376,7 +371,7 @@ def test_ensemble_full_size_sampled(oracle):
     u = s.mobility(ens.X, F).cpu().numpy()
     for b in np.random.default_rng(3).choice(ens.nsys, 8, replace=False):
         sl = slice(off[b], off[b + 1])
-        assert relerr(u[sl], oracle.mobility(ens.params, ens.X[sl], F[sl])) <= 1e-6, b
+        check_fp32c(u[sl], oracle.mobility(ens.params, ens.X[sl], F[sl]), f"system {b}")
     cen, com, code = s.run(20, 10)
     assert code == 0 and np.isfinite(com.cpu().numpy()).all()
 
@@ -398,10 +393,9 @@ def test_fused_forms_many_systems(oracle, fused):
     Xg = s.get_state()[0].cpu().numpy()
     Xo, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 30, S_per_sys=sizes)
     off = ens.sphere_offsets
-    worst = max(relerr(Xg[off[b]:off[b + 1]] - ens.X[off[b]:off[b + 1]],
-                       Xo[off[b]:off[b + 1]] - ens.X[off[b]:off[b + 1]]) for b in range(len(sizes)))
-    say(f"  worst system displacement rel err {worst:.2e}")
-    assert worst <= 1e-6
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        check_fp32c(Xg[sl] - ens.X[sl], Xo[sl] - ens.X[sl], f"system {b} displacement")
 
 
 # ---------------------------------------------------------------- failures
@@ -461,7 +455,7 @@ def test_steric_fp32c(oracle):
     F = s.forces(sus.X, 0.0).cpu().numpy()
     assert np.array_equal(F, oracle.forces(sus.params, sus.X, sus.phi, 0.0))
     u = s.mobility(sus.X, F).cpu().numpy()
-    assert relerr(u, oracle.mobility(sus.params, sus.X, F)) <= 1e-6
+    check_fp32c(u, oracle.mobility(sus.params, sus.X, F), "velocity at the overlapping start")
     Xg, cg, mg, Xo, co, mo = _run_both(oracle, sus, "fp32c", 200, 50)
     err = np.abs(Xg - Xo).max()
     say(f"  steric fp32c max position error after 200 steps {err:.2e}")
@@ -534,9 +528,11 @@ def test_rpy_mobility_tolerances(oracle, precision, launch):
     X = perturbed(sus, 0.2)
     F = oracle.forces(sus.params, X, sus.phi, 3.0)
     s = P.Simulator(sus.params, [sus.S], precision=precision, tensor="rpy", launch=launch)
-    err = relerr(s.mobility(X, F).cpu().numpy(), oracle.mobility(sus.params, X, F, tensor=1))
-    say(f"  rpy {precision} {launch} rel err {err:.2e}")
-    assert err <= (1e-13 if precision == "fp64_tiled" else 1e-6)
+    u, uo = s.mobility(X, F).cpu().numpy(), oracle.mobility(sus.params, X, F, tensor=1)
+    if precision == "fp64_tiled":
+        assert relerr(u, uo) <= 1e-13
+    else:
+        check_fp32c(u, uo, f"rpy {launch}")
 
 
 def test_rpy_trajectory_fp32c(oracle):
@@ -667,10 +663,8 @@ def test_fused_stage_matches_oracle(oracle, launch, integrator, tensor):
         Xu = s2.get_state()[0].cpu().numpy()
         Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 300, integrator=1 if integrator == "heun" else 0,
                                  tensor=1 if tensor == "rpy" else 0)
-        e_orc = relerr(Xf - sus.X, Xo - sus.X)
-        e_two = relerr(Xf - sus.X, Xu - sus.X)
-        say(f"  vs oracle {e_orc:.2e}, vs two-kernel path {e_two:.2e}")
-        assert e_orc <= 1e-6 and e_two <= 1e-6
+        check_fp32c(Xf - sus.X, Xo - sus.X, "displacement vs oracle")
+        check_fp32c(Xf - sus.X, Xu - sus.X, "displacement vs two-kernel path")
 
 
 @pytest.mark.parametrize("launch", [FUSED_SINGLE, FUSED_HILO])
@@ -693,8 +687,7 @@ def test_fused_stage_ensemble_matches_oracle(oracle, launch):
     off = ens.sphere_offsets
     for b in range(len(sizes)):
         sl = slice(off[b], off[b + 1])
-        e = relerr(Xg[sl] - ens.X[sl], Xo[sl] - ens.X[sl])
-        assert e <= 1e-6, (b, e)
+        check_fp32c(Xg[sl] - ens.X[sl], Xo[sl] - ens.X[sl], f"system {b} displacement")
 
 
 @pytest.mark.parametrize("S,posmode", [(3392, 2), (2272, 1)])
@@ -711,9 +704,7 @@ def test_fused_stage_at_the_lds_limit(oracle, S, posmode):
     _, _, code = s.run(2, 0)
     assert code == 0
     Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 2)
-    e = relerr(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X)
-    say(f"  displacement rel err {e:.2e}")
-    assert e <= 1e-6
+    check_fp32c(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X, "displacement")
 
 
 def test_fused_stage_deterministic_resumable_and_noise(oracle):
@@ -771,9 +762,8 @@ def test_wide_fused_stage_ensemble_matches_oracle(oracle, launch, integrator, te
     off = ens.sphere_offsets
     for b in range(len(sizes)):
         sl = slice(off[b], off[b + 1])
-        e = relerr(out["wide"][sl] - ens.X[sl], Xo[sl] - ens.X[sl])
-        e2 = relerr(out["wide"][sl] - ens.X[sl], out["two"][sl] - ens.X[sl])
-        assert e <= 1e-6 and e2 <= 1e-6, (b, e, e2)
+        check_fp32c(out["wide"][sl] - ens.X[sl], Xo[sl] - ens.X[sl], f"system {b} vs oracle")
+        check_fp32c(out["wide"][sl] - ens.X[sl], out["two"][sl] - ens.X[sl], f"system {b} vs two-kernel path")
 
 
 @pytest.mark.parametrize("S,posmode", [(300, 2), (3412, 2), (2274, 1)])
@@ -790,9 +780,7 @@ def test_wide_fused_stage_single_system(oracle, S, posmode):
     _, _, code = s.run(n, 0)
     assert code == 0
     Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, n)
-    e = relerr(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X)
-    say(f"  displacement rel err {e:.2e}")
-    assert e <= 1e-6
+    check_fp32c(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X, "displacement")
 
 
 def test_wide_fused_stage_deterministic_and_resumable():
@@ -836,10 +824,8 @@ def test_streamed_fused_stage_matches_oracle(oracle, launch, integrator, tensor)
             out[name] = s.get_state()[0].cpu().numpy()
         Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 200, integrator=1 if integrator == "heun" else 0,
                                  tensor=1 if tensor == "rpy" else 0)
-        e = relerr(out["stream"] - sus.X, Xo - sus.X)
-        e2 = relerr(out["stream"] - sus.X, out["two"] - sus.X)
-        say(f"  vs oracle {e:.2e}, vs two-kernel path {e2:.2e}")
-        assert e <= 1e-6 and e2 <= 1e-6
+        check_fp32c(out["stream"] - sus.X, Xo - sus.X, "displacement vs oracle")
+        check_fp32c(out["stream"] - sus.X, out["two"] - sus.X, "displacement vs two-kernel path")
 
 
 @pytest.mark.parametrize("S,posmode", [(2048, 2), (4100, 2), (4100, 1)])
@@ -854,9 +840,7 @@ def test_streamed_fused_stage_large_systems(oracle, S, posmode):
     _, _, code = s.run(2, 0)
     assert code == 0
     Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 2)
-    e = relerr(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X)
-    say(f"  displacement rel err {e:.2e}")
-    assert e <= 1e-6
+    check_fp32c(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X, "displacement")
 
 
 def test_streamed_fused_stage_ensemble_and_determinism(oracle):
@@ -878,7 +862,7 @@ def test_streamed_fused_stage_ensemble_and_determinism(oracle):
     off = ens.sphere_offsets
     for b in range(len(sizes)):
         sl = slice(off[b], off[b + 1])
-        assert relerr(out[0][sl] - ens.X[sl], Xo[sl] - ens.X[sl]) <= 1e-6, b
+        check_fp32c(out[0][sl] - ens.X[sl], Xo[sl] - ens.X[sl], f"system {b} displacement")
 
 
 def test_launch_changes_between_runs_repack(oracle):
@@ -901,9 +885,7 @@ def test_launch_changes_between_runs_repack(oracle):
     X, _, step = s.get_state()
     assert step == 240
     Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 240)
-    e = relerr(X.cpu().numpy() - sus.X, Xo - sus.X)
-    say(f"six forms in turn: displacement rel err {e:.2e}")
-    assert e <= 1e-6
+    check_fp32c(X.cpu().numpy() - sus.X, Xo - sus.X, "six forms in turn: displacement")
 
 
 def test_streamed_fused_stage_noise(oracle):
@@ -962,3 +944,133 @@ def test_split_step_calls_equal_one_call(oracle, precision, steric):
     assert code == 0
     parts.step(50)
     assert np.array_equal(one.get_state()[0].cpu().numpy(), parts.get_state()[0].cpu().numpy())
+
+
+# ---------------------------------------------------------------- resident form (small systems)
+
+RESIDENT = {"ipl": 1, "jchunk": 256, "wg": 64, "wj": 1, "posmode": 1, "fused": 4}
+RESIDENT_SINGLE = dict(RESIDENT, posmode=2)
+
+
+@pytest.mark.parametrize("integrator,tensor", [("rk4", "oseen"), ("heun", "oseen"), ("rk4", "rpy")])
+def test_resident_fp64_bitwise(oracle, integrator, tensor):
+    """The resident form in plain FP64: the 16-sphere workload over 2000
+    steps (records every 250), and a batch of uneven small systems over 300
+    steps (one of 128 spheres, whose terms take several column chunks),
+    bitwise equal to the oracle: state, centres and centre of mass."""
+    _torch()
+    it, te = (1 if integrator == "heun" else 0), (1 if tensor == "rpy" else 0)
+    sus = make_preset("n16")
+    s = P.Simulator(sus.params, [sus.S], precision="fp64", integrator=integrator, tensor=tensor,
+                    launch=RESIDENT, graph=True)
+    assert s.launch["fused"] == 4
+    s.set_state(sus.X, sus.phi)
+    cen, com, code = s.run(2000, 250)
+    assert code == 0
+    Xo, co, mo, _ = oracle.run(sus.params, sus.X, sus.phi, 2000, record_every=250, integrator=it, tensor=te)
+    assert np.array_equal(s.get_state()[0].cpu().numpy(), Xo)
+    assert np.array_equal(cen.cpu().numpy(), co) and np.array_equal(com.cpu().numpy(), mo)
+    sizes = np.array([1, 8, 27, 64, 3, 40], dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    s = P.Simulator(ens.params, sizes, precision="fp64", integrator=integrator, tensor=tensor, launch=RESIDENT)
+    s.set_state(ens.X, ens.phi)
+    cen, com, code = s.run(300, 100)
+    assert code == 0
+    Xo, co, mo, _ = oracle.run(ens.params, ens.X, ens.phi, 300, record_every=100, S_per_sys=sizes, integrator=it,
+                               tensor=te)
+    assert np.array_equal(s.get_state()[0].cpu().numpy(), Xo)
+    assert np.array_equal(cen.cpu().numpy(), co) and np.array_equal(com.cpu().numpy(), mo)
+
+
+def test_resident_fp64_full_n16(oracle):
+    """The plain FP64 workload in full in the resident form: 16 spheres,
+    1e4 RK4 steps, records every 1000, bitwise."""
+    _torch()
+    sus = make_preset("n16")
+    s = P.Simulator(sus.params, [sus.S], precision="fp64", launch=RESIDENT)
+    s.set_state(sus.X, sus.phi)
+    cen, com, code = s.run(10_000, 1000)
+    assert code == 0
+    Xo, co, mo, _ = oracle.run(sus.params, sus.X, sus.phi, 10_000, record_every=1000)
+    assert np.array_equal(s.get_state()[0].cpu().numpy(), Xo)
+    assert np.array_equal(cen.cpu().numpy(), co) and np.array_equal(com.cpu().numpy(), mo)
+
+
+@pytest.mark.parametrize("launch", [RESIDENT, RESIDENT_SINGLE])
+@pytest.mark.parametrize("integrator,tensor", [("rk4", "oseen"), ("heun", "oseen"), ("rk4", "rpy")])
+def test_resident_fp32c_matches_oracle(oracle, launch, integrator, tensor):
+    """The resident form in FP32C on uneven systems from 1 dumbbell to 128
+    (256 spheres, one lane per target) and the paper's 27-dumbbell lattice
+    size: 300 steps against the oracle per system, relative to the
+    displacement, and within the bars of the two-kernel path."""
+    _torch()
+    sizes = np.array([1, 27, 128, 3, 57, 8, 100], dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    it, te = (1 if integrator == "heun" else 0), (1 if tensor == "rpy" else 0)
+    out = {}
+    for name, L in (("res", launch), ("two", dict(launch, fused=0))):
+        s = P.Simulator(ens.params, sizes, precision="fp32c", integrator=integrator, tensor=tensor, launch=L,
+                        graph=True)
+        s.set_state(ens.X, ens.phi)
+        _, _, code = s.run(300, 0)
+        assert code == 0
+        out[name] = s.get_state()[0].cpu().numpy()
+    Xo, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 300, S_per_sys=sizes, integrator=it, tensor=te)
+    off = ens.sphere_offsets
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        check_fp32c(out["res"][sl] - ens.X[sl], Xo[sl] - ens.X[sl], f"system {b} (S={sizes[b]}) vs oracle")
+        check_fp32c(out["res"][sl] - ens.X[sl], out["two"][sl] - ens.X[sl], f"system {b} vs two-kernel path")
+
+
+def test_resident_noise_determinism_and_split_calls(oracle):
+    """Resident form: Heun with Brownian noise follows the oracle's
+    trajectory (same Philox numbers); two runs give the same bits; split
+    calls and record points (which split the launches) equal one call;
+    switching to a staged form and back keeps the state."""
+    _torch()
+    sus = make_single(20, 40.0, 5)
+    kT, seed = 0.01, 77
+    s = P.Simulator(sus.params, [sus.S], precision="fp32c", integrator="heun", kT=kT, seed=seed, launch=RESIDENT)
+    s.set_state(sus.X, sus.phi)
+    _, _, code = s.run(300, 0)
+    assert code == 0
+    Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 300, integrator=1, kT=kT, seed=seed)
+    assert np.abs(s.get_state()[0].cpu().numpy() - Xo).max() <= 1e-7
+    sizes = np.array([16, 27, 3, 60], dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    out = []
+    for calls in ((200,), (200,), (70, 130), ((200, 30),)):
+        s = P.Simulator(ens.params, sizes, precision="fp32c", launch=RESIDENT)
+        s.set_state(ens.X, ens.phi)
+        for n in calls:
+            nsteps, every = (n if isinstance(n, tuple) else (n, 0))
+            _, _, code = s.run(nsteps, every)
+            assert code == 0
+        out.append(s.get_state()[0].cpu().numpy())
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)
+    s = P.Simulator(ens.params, sizes, precision="fp32c", launch=RESIDENT)
+    s.set_state(ens.X, ens.phi)
+    for L in (RESIDENT, STREAM_SINGLE, RESIDENT, dict(RESIDENT, fused=0), RESIDENT):
+        s.set_launch(**L)
+        _, _, code = s.run(40, 0)
+        assert code == 0
+    Xo, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 200, S_per_sys=sizes)
+    off = ens.sphere_offsets
+    X = s.get_state()[0].cpu().numpy()
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        check_fp32c(X[sl] - ens.X[sl], Xo[sl] - ens.X[sl], f"forms in turn, system {b}")
+
+
+def test_resident_coincident_spheres_raise_flag():
+    _torch()
+    sus = make_single(8, 30.0, 3)
+    X = sus.X.copy()
+    X[5] = X[2]
+    for precision in ("fp64", "fp32c"):
+        s = P.Simulator(sus.params, [sus.S], precision=precision, launch=RESIDENT)
+        s.set_state(X, sus.phi)
+        _, _, code = s.run(2, 1)
+        assert code == P.binding.AD_ENONFINITE, precision

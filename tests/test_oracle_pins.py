@@ -140,6 +140,38 @@ def test_forces_internal_and_central(oracle):
     assert np.abs(F0).max() < 1e-14
 
 
+def test_spring_energy_hand_values(oracle):
+    """Eq. (e:swimmer_potential): U = sum_s k/2 (d_s - L_s(t))^2. Two
+    dumbbells with k = 3: d = 5 against L = 4 (phase 0, t = 0) gives 3/2;
+    d = 3 against L = 5 (phase pi/2) gives 6; a quarter period later the
+    first rest length is 5 as well (d - L = 0) and the second 4 (d - L =
+    -1, 3/2)."""
+    p = Params(k=3.0)
+    X = np.array([[1.0, 2.0, 3.0], [6.0, 2.0, 3.0], [-4.0, 0.0, 0.0], [-4.0, 0.0, 3.0]])
+    phi = np.array([0.0, PI / 2])
+    assert abs(oracle.energy(p, X, phi, 0.0) - 7.5) < 1e-13
+    assert abs(oracle.energy(p, X, phi, p.T / 4) - 1.5) < 1e-13
+
+
+def test_forces_are_minus_energy_gradient(oracle):
+    """F = -grad U (Sec. II): central differences of the oracle's energy
+    against the oracle's forces, sphere by sphere."""
+    sus = small_suspension(S=5)
+    p = Params(k=2.5)
+    X = sus.X + np.random.default_rng(4).normal(scale=0.3, size=sus.X.shape)
+    t, h = 21.3, 1e-6
+    F = oracle.forces(p, X, sus.phi, t)
+    G = np.empty_like(X)
+    for i in range(X.shape[0]):
+        for a in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[i, a] += h
+            Xm[i, a] -= h
+            G[i, a] = -(oracle.energy(p, Xp, sus.phi, t) - oracle.energy(p, Xm, sus.phi, t)) / (2 * h)
+    assert np.abs(F).max() > 0.1
+    np.testing.assert_allclose(G, F, rtol=0, atol=1e-7)
+
+
 def test_steric_repulsion(oracle):
     """Steric option: equal and opposite, along the separation, k_s (r_c - r)
     in magnitude below r_c, zero beyond."""
