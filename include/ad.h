@@ -240,8 +240,28 @@ int ad_sa_workspace_size(int32_t S, uint64_t* bytes);
 int ad_sa_run(const ad_params* p, int32_t S, double* R, double* N, const double* phi, double dt,
               int64_t nsteps, void* workspace, uint64_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * product of ad_mobility_apply, u = M(X) F for ONE system of N spheres
+ * (N even, dumbbell s = spheres 2s and 2s+1), with no context, no workspace
+ * and no allocation of any kind. p supplies a, eta, precision (AD_FP64,
+ * AD_FP64_TILED or AD_FP32C; the default launch shape of that precision) and
+ * tensor; the other fields are ignored. X, F, u: device [N][3] f64,
+ * caller-owned. Asynchronous on `stream`. The pack, partial sums and work
+ * list live in a 16 MiB device array that the library holds on every device
+ * until the process ends; sizes that need more are refused with AD_ENOMEM
+ * (every N up to 131072 fits, except AD_FP64_TILED with AD_RPY: up to
+ * 62948). Every call on one device uses that device's one array: calls that
+ * overlap on a device (other streams, other threads) race and must be
+ * serialised by the caller. Non-finite velocities are not reported.
+ * Errors: AD_EINVAL (null pointer, odd or too small N, bad parameter),
+ * AD_ENOMEM, AD_EDEVICE; message via ad_last_error(NULL). */
+int ad_mobility_apply_static(const ad_params* p, int32_t N, const double* X, const double* F, double* u,
+                             void* stream);
+
 /* Message of the last failure on ctx (never NULL; "" if none). With ctx ==
- * NULL: the last failure of ad_create on the calling thread. */
+ * NULL: the last failure of ad_create or ad_mobility_apply_static on the
+ * calling thread. */
 const char* ad_last_error(const ad_ctx* ctx);
 
 #ifdef __cplusplus

@@ -7,6 +7,6 @@ from .binding import (  # noqa: F401
     ADError, Simulator, ad_create, ad_destroy, ad_workspace_size, ad_bind_workspace, ad_set_launch,
     ad_get_launch, ad_set_state, ad_get_state, ad_forces, ad_mobility_apply, ad_step, ad_run, ad_check,
     ad_use_graph, ad_profile_pairs, ad_profile_read, ad_last_error, make_params, lib, LIB_PATH,
-    ad_sa_rhs, ad_sa_workspace_size, ad_sa_run, StrokeAveraged, ad_valu_probe,
+    ad_sa_rhs, ad_sa_workspace_size, ad_sa_run, StrokeAveraged, ad_mobility_apply_static, ad_valu_probe,
 )
 from . import observables  # noqa: F401

@@ -26,7 +26,8 @@ INTEGRATORS = {"rk4": AD_RK4, "heun": AD_HEUN}
 EXPORTS = ("ad_create", "ad_destroy", "ad_workspace_size", "ad_bind_workspace", "ad_set_launch",
            "ad_get_launch", "ad_set_state", "ad_get_state", "ad_forces", "ad_mobility_apply",
            "ad_step", "ad_run", "ad_check", "ad_use_graph", "ad_profile_pairs", "ad_profile_read",
-           "ad_valu_probe", "ad_sa_rhs", "ad_sa_workspace_size", "ad_sa_run", "ad_last_error")
+           "ad_valu_probe", "ad_sa_rhs", "ad_sa_workspace_size", "ad_sa_run", "ad_mobility_apply_static",
+           "ad_last_error")
 
 
 class ad_params(C.Structure):
@@ -82,6 +83,7 @@ def lib():
         L.ad_sa_workspace_size.argtypes = [i32, C.POINTER(C.c_uint64)]
         L.ad_sa_run.argtypes = [C.POINTER(ad_params), i32, vp, vp, vp, C.c_double, i64, vp, C.c_uint64, vp]
         L.ad_valu_probe.argtypes = [i32, i32, i32, vp, vp, vp]
+        L.ad_mobility_apply_static.argtypes = [C.POINTER(ad_params), i32, vp, vp, vp, vp]
         L.ad_last_error.argtypes = [vp]
         L.ad_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -262,6 +264,15 @@ def ad_sa_run(params: ad_params, R, N, phi, dt, nsteps, workspace, stream=None) 
         return code
     _sa_check(code, "ad_sa_run")
     return code
+
+
+def ad_mobility_apply_static(params: ad_params, X, F, u_out, stream=None) -> None:
+    """u = M(X) F for one system with no context, workspace or allocation
+    (the library's own per-device scratch array)."""
+    N = X.shape[0]
+    code = lib().ad_mobility_apply_static(C.byref(params), int(N), _dev(X, "X", (N, 3)), _dev(F, "F", (N, 3)),
+                                          _dev(u_out, "u_out", (N, 3)), _stream(stream))
+    _check(code, None)
 
 
 def ad_last_error(ctx=None) -> str:

@@ -9,7 +9,7 @@ PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libad.so"
 SOURCES = [CSRC / "ad_kernels.hip", CSRC / "ad_dense.hip", CSRC / "ad_runtime.hip", CSRC / "ad_sa.hip",
-           CSRC / "ad_calib.hip"]
+           CSRC / "ad_noalloc.hip", CSRC / "ad_calib.hip"]
 HEADERS = [CSRC / "ad_internal.h", CSRC / "ad_order.h", PKG.parent / "include" / "ad.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

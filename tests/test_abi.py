@@ -313,3 +313,19 @@ def test_resident_launch_limits():
     assert try_launch([64], "fp64_tiled") == B.AD_OK
     assert try_launch([20], "fp32c", steric=True) == B.AD_EINVAL
     assert try_launch([20], "fp64_dense") == B.AD_EINVAL
+
+
+def test_static_apply_refuses_before_any_device_work():
+    """ad_mobility_apply_static (no context, no allocation) rejects null
+    pointers, odd sizes and sizes beyond its fixed scratch with a message,
+    before touching a device."""
+    p = P.make_params(Params(), "fp32c")
+    fake = C.c_void_p(256)  # never dereferenced: the checks come first
+    lib = P.lib()
+    assert lib.ad_mobility_apply_static(C.byref(p), 8, None, fake, fake, None) == B.AD_EINVAL
+    assert lib.ad_mobility_apply_static(C.byref(p), 7, fake, fake, fake, None) == B.AD_EINVAL
+    assert "even" in P.ad_last_error(None)
+    assert lib.ad_mobility_apply_static(C.byref(p), 400000, fake, fake, fake, None) == B.AD_ENOMEM
+    assert "scratch" in P.ad_last_error(None)
+    bad = P.make_params(Params(), "fp64_dense")
+    assert lib.ad_mobility_apply_static(C.byref(bad), 8, fake, fake, fake, None) == B.AD_EINVAL
