@@ -107,9 +107,10 @@ def cpu_baseline(w, sizes, budget_s):
 # VALU instructions per loop trip of 8 terms in the issue-rate probe, from the
 # gfx950 assembly of k_valu_rate (8 terms plus the target's step; with hi/lo
 # positions the lo differences and the lo step as well; 8 FMAs for kind 1)
-PROBE_VALU_PER_TRIP = {0: 147, 1: 8, 2: 189}
+PROBE_VALU_PER_TRIP = {0: 147, 1: 8, 2: 189, 3: 147}
 PROBE_KINDS = {0: "Oseen pair term, single-float positions", 1: "independent FMA chains",
-               2: "Oseen pair term, hi/lo positions"}
+               2: "Oseen pair term, hi/lo positions",
+               3: "Oseen pair term, single-float positions, four accumulators"}
 
 
 def calibrate(iters: int = 4096):
@@ -129,7 +130,7 @@ def calibrate(iters: int = 4096):
         raise RuntimeError(f"hipDeviceGetAttribute(WallClockRate) failed: {rc}")
     wall_hz = rate.value * 1e3
     out = []
-    for kind in (0, 2, 1):
+    for kind in (0, 3, 2, 1):
         for wps in (1, 2, 4, 8):
             blocks = cus * wps  # 256-thread groups: one wave per SIMD each
             sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")

@@ -209,7 +209,8 @@ int ad_profile_read(ad_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Measurement support: the issue rate of the FP32 pair term's instruction
  * mix with operands in registers (kind 0: single-float positions, 2: hi/lo
- * positions) or of independent FMA chains (kind 1), in `blocks` work-groups
+ * positions, 3: single-float into four independent accumulators) or of
+ * independent FMA chains (kind 1), in `blocks` work-groups
  * of 256 threads, `iters` trips of 8 terms per thread. sink: device
  * [blocks*256] f32 (results, kept from being optimised away); clk: device [2]
  * i64, zeroed by the caller, receives the sums over work-groups of their

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(256) void k_valu_rate(int iters, float seed, float*
     float hx = 100.f + b, hy = -50.f + b, hz = 25.f;
     float lx = 1e-6f * b, ly = -1e-6f, lz = 2e-6f;
     float px = 0.f, py = 0.f, pz = 0.f;
+    float qx[4] = {0.f, 0.f, 0.f, 0.f}, qy[4] = {0.f, 0.f, 0.f, 0.f}, qz[4] = {0.f, 0.f, 0.f, 0.f};
     float a[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) a[k] = b + k;
@@ -68,6 +69,15 @@ __global__ __launch_bounds__(256) void k_valu_rate(int iters, float seed, float*
         if (KIND == 1) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) a[k] = __builtin_fmaf(a[k], 0.999f, 1e-3f);
+        } else if (KIND == 3) {
+            /* the same terms into four independent accumulators */
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                term(hx, hy, hz, lx, ly, lz, sx[k], sy[k], sz[k], 0.f, 0.f, 0.f, fx[k], fy[k], fz[k], false,
+                     qx[k & 3], qy[k & 3], qz[k & 3]);
+            hx += 1e-4f;
+            hy += 1e-4f;
+            hz += 1e-4f;
         } else {
 #pragma unroll
             for (int k = 0; k < 8; ++k)
@@ -85,6 +95,8 @@ __global__ __launch_bounds__(256) void k_valu_rate(int iters, float seed, float*
     }
     float out = px + py + pz;
 #pragma unroll
+    for (int k = 0; k < 4; ++k) out += qx[k] + qy[k] + qz[k];
+#pragma unroll
     for (int k = 0; k < 8; ++k) out += a[k];
     sink[g] = out;
     __syncthreads();
@@ -98,7 +110,7 @@ __global__ __launch_bounds__(256) void k_valu_rate(int iters, float seed, float*
 }  // namespace
 
 /* kind 0: Oseen term with single-float positions, 1: FMA chains, 2: Oseen
- * term with hi/lo positions. blocks work-groups of 256 threads, iters loop
+ * term with hi/lo positions, 3: kind 0 with four accumulators. blocks work-groups of 256 threads, iters loop
  * trips of 8 terms (or 8 FMAs) per thread; sink: device [blocks*256] floats;
  * clk: device [2], zeroed by the caller: the sums over work-groups of the
  * shader cycles and of the constant-rate counter ticks (hipDeviceAttribute-
@@ -106,13 +118,15 @@ __global__ __launch_bounds__(256) void k_valu_rate(int iters, float seed, float*
  * clock. Asynchronous. */
 extern "C" int ad_valu_probe(int32_t kind, int32_t blocks, int32_t iters, float* sink, long long* clk,
                              void* stream) {
-    if (blocks < 1 || iters < 1 || !sink || !clk || kind < 0 || kind > 2) return AD_EINVAL;
+    if (blocks < 1 || iters < 1 || !sink || !clk || kind < 0 || kind > 3) return AD_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (kind == 0)
         hipLaunchKernelGGL(k_valu_rate<0>, dim3(blocks), dim3(256), 0, s, iters, 0.25f, sink, clk);
     else if (kind == 1)
         hipLaunchKernelGGL(k_valu_rate<1>, dim3(blocks), dim3(256), 0, s, iters, 0.25f, sink, clk);
-    else
+    else if (kind == 2)
         hipLaunchKernelGGL(k_valu_rate<2>, dim3(blocks), dim3(256), 0, s, iters, 0.25f, sink, clk);
+    else
+        hipLaunchKernelGGL(k_valu_rate<3>, dim3(blocks), dim3(256), 0, s, iters, 0.25f, sink, clk);
     return hipGetLastError() == hipSuccess ? AD_OK : AD_EDEVICE;
 }

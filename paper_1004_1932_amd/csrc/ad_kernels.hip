@@ -1715,19 +1715,46 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
     int bad = 0;
     __syncthreads();
 
-    /* forces (and for FP32C the pack and U0) at the positions Y */
-    auto forces = [&](double st, double ct) {
+    /* One thread per dumbbell: the closing update of its two spheres (from
+     * the pair sums of the stage just summed: velocity, stage update, state
+     * and accumulator in LDS), or with stage < 0 their positions as they are,
+     * then the spring forces at (st, ct) and, for FP32C, the pack and U0 of
+     * the next stage. Each thread reads and writes only its own spheres'
+     * F, U0, X, R and Y, so no barrier is needed inside. */
+    auto close_and_force = [&](int stage, double st, double ct, long long step) {
         if (tid < S) {
             const int i0 = 2 * tid;
-            double y0[3], y1[3], f0[3], f1[3];
-            for (int a = 0; a < 3; ++a) {
-                y0[a] = Y[a * n + i0];
-                y1[a] = Y[a * n + i0 + 1];
+            double y[2][3];
+            for (int h = 0; h < 2; ++h) {
+                const int i = i0 + h;
+                for (int a = 0; a < 3; ++a) {
+                    const int o = a * n + i;
+                    if (stage < 0) {
+                        y[h][a] = Y[o];
+                        continue;
+                    }
+                    double k;
+                    if (P64) {
+                        k = c.cs * F[o] + c.co * Acc[3 * i + a];
+                        if (RPY) k = k + c.cr * Bcc[3 * i + a];
+                    } else {
+                        k = U0[o] + c.co * Acc[o];
+                    }
+                    if (!isfinite(k)) bad = 1;
+                    const double nz =
+                        (e.integ == 1 && c.noise) ? c.g * gauss_component(c.seed, ioff + i, step, a) : 0.0;
+                    double x = X[o], r = R[o];
+                    y[h][a] = res_update(c, e.integ, stage, e.nst, k, x, r, nz);
+                    X[o] = x;
+                    R[o] = r;
+                    Y[o] = y[h][a];
+                }
             }
+            double f0[3], f1[3];
             if (P64) {
-                spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+                spring_forces(c, y[0], y[1], tp.x, tp.y, st, ct, f0, f1);
             } else {
-                spring_forces_rs(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+                spring_forces_rs(c, y[0], y[1], tp.x, tp.y, st, ct, f0, f1);
             }
             for (int a = 0; a < 3; ++a) {
                 F[a * n + i0] = f0[a];
@@ -1735,11 +1762,11 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
             }
             if (!P64) {
                 for (int h = 0; h < 2; ++h) {
-                    const double* y = h ? y1 : y0;
-                    const double* yp = h ? y0 : y1;
+                    const double* yy = y[h];
+                    const double* yp = y[h ^ 1];
                     const double* f = h ? f1 : f0;
                     const double* fp = h ? f0 : f1;
-                    const double r[3] = {y[0] - yp[0], y[1] - yp[1], y[2] - yp[2]};
+                    const double r[3] = {yy[0] - yp[0], yy[1] - yp[1], yy[2] - yp[2]};
                     const double ir = rsqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
                     const double ir2 = ir * ir;
                     const double tt = ((r[0] * fp[0] + r[1] * fp[1]) + r[2] * fp[2]) * ir2;
@@ -1749,7 +1776,7 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
                         U0[a * n + i0 + h] = u;
                     }
                     float hi[3], lo[3];
-                    for (int a = 0; a < 3; ++a) split_f32(y[a], hi[a], lo[a]);
+                    for (int a = 0; a < 3; ++a) split_f32(yy[a], hi[a], lo[a]);
                     pA[i0 + h] = make_float4(hi[0], hi[1], hi[2], (float)f[0]);
                     pB[i0 + h] = make_float4(lo[0], lo[1], lo[2], (float)f[1]);
                     pz[i0 + h] = (float)f[2];
@@ -1758,12 +1785,21 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
         }
         __syncthreads();
     };
-    forces(st0, ct0);
+    /* this step's (sin, cos)(omega t) row of the step table, in the dumbbell
+     * threads; the next step's row is loaded while a step runs */
+    double tb[8], nb[8];
+    for (int q = 0; q < 8; ++q) tb[q] = nb[q] = 0.0;
+    if (tid < S)
+        for (int q = 0; q < 8; ++q) tb[q] = d.tab[(step0 % d.ring) * 8 + q];
+    close_and_force(-1, st0, ct0, step0);
 
     const float crr = c.crr;
     for (int sn = 0; sn < nsteps; ++sn) {
         const long long step = step0 + sn;
-        const long long row = step % d.ring;
+        if (tid < S) {
+            const long long nrow = (step + 1) % d.ring;
+            for (int q = 0; q < 8; ++q) nb[q] = d.tab[nrow * 8 + q];
+        }
         for (int stage = 0; stage < e.nst; ++stage) {
             /* ---- pair sums */
             if (P64) {
@@ -1860,32 +1896,10 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
                 }
                 __syncthreads();
             }
-            /* ---- closing: velocity, stage update, next stage positions */
-            for (int q = tid; q < 3 * n; q += RES_T) {
-                int i, a, o;
-                double k;
-                if (P64) {
-                    i = q / 3;
-                    a = q - 3 * i;
-                    o = a * n + i;
-                    k = c.cs * F[o] + c.co * Acc[q];
-                    if (RPY) k = k + c.cr * Bcc[q];
-                } else {
-                    a = q / n;
-                    i = q - a * n;
-                    o = q;
-                    k = U0[o] + c.co * Acc[o];
-                }
-                if (!isfinite(k)) bad = 1;
-                const double nz = (e.integ == 1 && c.noise) ? c.g * gauss_component(c.seed, ioff + i, step, a) : 0.0;
-                double x = X[o], r = R[o];
-                Y[o] = res_update(c, e.integ, stage, e.nst, k, x, r, nz);
-                X[o] = x;
-                R[o] = r;
-            }
-            __syncthreads();
-            forces(d.tab[row * 8 + 2 * stage], d.tab[row * 8 + 2 * stage + 1]);
+            /* ---- closing, next stage positions and forces */
+            close_and_force(stage, tb[2 * stage], tb[2 * stage + 1], step);
         }
+        for (int q = 0; q < 8; ++q) tb[q] = nb[q];
     }
     for (int q = tid; q < 3 * n; q += RES_T) {
         const int a = q / n, i = q - a * n;

@@ -38,6 +38,9 @@ import paper_1004_1932_amd as P  # noqa: E402
 from oracle import adref  # noqa: E402
 from workload import make_preset  # noqa: E402
 
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+from parity_metrics import sphere_err  # noqa: E402
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -59,11 +62,16 @@ def systems(w):
 
 
 def velocity_errors(w, sim, X, t):
-    """per-system velocity error at state X (host array), time t"""
+    """per-system (norm, per-sphere) velocity errors at state X (host array),
+    time t"""
     S, sl = systems(w)
     F = np.concatenate([adref.forces(w.params, X[s], w.phi[s.start // 2:s.stop // 2], t) for s in sl])
     u = sim.mobility(X, F).cpu().numpy()
-    return [relerr(u[s], adref.mobility(w.params, X[s], F[s])) for s in sl]
+    out = []
+    for s in sl:
+        uo = adref.mobility(w.params, X[s], F[s])
+        out.append((relerr(u[s], uo), sphere_err(u[s], uo)))
+    return out
 
 
 def trajectory_report(name, precision, nsteps, chunk, launch="tuned"):
@@ -74,7 +82,7 @@ def trajectory_report(name, precision, nsteps, chunk, launch="tuned"):
     sim.set_state(w.X, w.phi)
     Xo = w.X.copy()
     c0 = centres(w.X)
-    verr, drift, bitwise = [], [], True
+    verr, serr, drift, bitwise = [], [], [], True
     t_gpu = t_orc = 0.0
     for n0 in range(0, nsteps, chunk):
         k = min(chunk, nsteps - n0)
@@ -92,13 +100,16 @@ def trajectory_report(name, precision, nsteps, chunk, launch="tuned"):
         d = [relerr(dg[s.start // 2:s.stop // 2], do[s.start // 2:s.stop // 2]) for s in sl]
         drift.append(max(d))
         if precision == "fp32c":
-            verr.append(max(velocity_errors(w, sim, Xg, n * p.dt)))
+            ve = velocity_errors(w, sim, Xg, n * p.dt)
+            verr.append(max(e for e, _ in ve))
+            serr.append(max(x for _, x in ve))
         log(f"  {name} {precision} step {n}: drift {drift[-1]:.3e}"
             + (f", velocity error {verr[-1]:.3e}" if verr else "") + f" (gpu {t_gpu:.1f} s, oracle {t_orc:.1f} s)")
     out = {"workload": name, "form": precision, "steps": nsteps, "checkpoints": len(drift),
            "centre_drift_end": drift[-1], "centre_drift_max": max(drift), "bitwise_equal_to_oracle": bitwise}
     if verr:
-        out.update({"velocity_error_max": max(verr), "velocity_error_median": float(np.median(verr))})
+        out.update({"velocity_error_max": max(verr), "velocity_error_median": float(np.median(verr)),
+                    "per_sphere_error_max": max(serr)})
     if precision == "fp32c":
         out["launch"] = sim.launch
     sim.close()
@@ -110,7 +121,7 @@ def spot_report(name, nsteps, every):
     p = w.params
     sim = P.Simulator(p, [w.S], precision="fp32c", launch="tuned", graph=True)
     sim.set_state(w.X, w.phi)
-    errs = []
+    errs, serrs = [], []
     for n0 in range(0, nsteps, every):
         _, _, code = sim.run(every, 0)
         assert code == 0, f"{name}: status {code}"
@@ -122,10 +133,11 @@ def spot_report(name, nsteps, every):
         rows = np.random.default_rng(7 + n).choice(w.N, 64, replace=False)
         uo = adref.mobility_rows(p, Xh, Fh, rows)
         errs.append(relerr(u[rows], uo))
-        log(f"  {name} step {n}: sampled velocity error {errs[-1]:.3e}")
+        serrs.append(sphere_err(u[rows], uo))
+        log(f"  {name} step {n}: sampled velocity error {errs[-1]:.3e}, per-sphere {serrs[-1]:.3e}")
     out = {"workload": name, "form": "fp32c", "steps": nsteps, "checkpoints": len(errs),
            "sampled_velocity_error_max": max(errs), "sampled_velocity_error_median": float(np.median(errs)),
-           "launch": sim.launch}
+           "sampled_per_sphere_error_max": max(serrs), "launch": sim.launch}
     sim.close()
     return out
 

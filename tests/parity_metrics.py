@@ -35,16 +35,41 @@ def relerr(a, b) -> float:
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def sphere_err(a, b) -> float:
+def sphere_err(a, b, extra=None) -> float:
+    """extra: an optional per-sphere addition to the scale (see
+    near_term_scale)."""
     a = np.asarray(a, dtype=np.float64).reshape(-1, 3)
     b = np.asarray(b, dtype=np.float64).reshape(-1, 3)
     nb = np.linalg.norm(b, axis=1)
-    return float((np.linalg.norm(a - b, axis=1) / (nb + np.median(nb))).max())
+    scale = nb + np.median(nb)
+    if extra is not None:
+        scale = scale + np.asarray(extra, dtype=np.float64)
+    return float((np.linalg.norm(a - b, axis=1) / scale).max())
 
 
-def check_fp32c(a, b, what: str = "", norm_bar: float = NORM_BAR, sphere_bar: float = SPHERE_BAR):
+def near_term_scale(X, F, eta=1.0, radius=8.0):
+    """Per sphere, the sum of the magnitudes of the Oseen terms of its
+    neighbours closer than `radius`, 2 |F_j| / (8 pi eta r_ij) each (the
+    largest the term can be): the size of the terms whose FP32 rounding
+    survives when they cancel each other, as around a steric contact, where
+    the two forces are large, equal and opposite."""
+    from scipy.spatial import cKDTree
+    X = np.asarray(X, dtype=np.float64)
+    Fn = np.linalg.norm(np.asarray(F, dtype=np.float64), axis=1)
+    pairs = np.array(sorted(cKDTree(X).query_pairs(radius)), dtype=np.int64).reshape(-1, 2)
+    out = np.zeros(X.shape[0])
+    if len(pairs):
+        i, j = pairs[:, 0], pairs[:, 1]
+        r = np.linalg.norm(X[i] - X[j], axis=1)
+        c = 2.0 / (8.0 * np.pi * eta * r)
+        np.add.at(out, i, c * Fn[j])
+        np.add.at(out, j, c * Fn[i])
+    return out
+
+
+def check_fp32c(a, b, what: str = "", norm_bar: float = NORM_BAR, sphere_bar: float = SPHERE_BAR, extra=None):
     """Both bars at once; returns (norm error, per-sphere error)."""
-    e, s = relerr(a, b), sphere_err(a, b)
+    e, s = relerr(a, b), sphere_err(a, b, extra)
     print(f"  {what} rel err {e:.2e}, per-sphere {s:.2e}", flush=True)
     assert e <= norm_bar, (what, e)
     assert s <= sphere_bar, (what, s)

@@ -1050,10 +1050,14 @@ def test_resident_noise_determinism_and_split_calls(oracle):
         out.append(s.get_state()[0].cpu().numpy())
     for o in out[1:]:
         assert np.array_equal(out[0], o)
-    s = P.Simulator(ens.params, sizes, precision="fp32c", launch=RESIDENT)
+    # the streamed form needs the largest workspace of the three: created with
+    # it, the context keeps its state through every change of form
+    s = P.Simulator(ens.params, sizes, precision="fp32c", launch=STREAM_SINGLE)
     s.set_state(ens.X, ens.phi)
+    ctx = s.ctx
     for L in (RESIDENT, STREAM_SINGLE, RESIDENT, dict(RESIDENT, fused=0), RESIDENT):
         s.set_launch(**L)
+        assert s.ctx == ctx
         _, _, code = s.run(40, 0)
         assert code == 0
     Xo, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 200, S_per_sys=sizes)
