@@ -213,10 +213,9 @@ int ad_profile_read(ad_ctx* ctx, double* total_ms, int64_t* launches);
  * independent FMA chains (kind 1), in `blocks` work-groups
  * of 256 threads, `iters` trips of 8 terms per thread. sink: device
  * [blocks*256] f32 (results, kept from being optimised away); clk: device [2]
- * i64, zeroed by the caller, receives the sums over work-groups of their
- * shader cycles and of their constant-rate counter ticks (rate:
- * hipDeviceAttributeWallClockRate), whose ratio is the shader clock under
- * the load. Asynchronous on stream. */
+ * i64, zeroed by the caller, receives the longest life of a work-group in
+ * shader cycles (over the kernel's duration: the shader clock under the
+ * load) and the sum over work-groups. Asynchronous on stream. */
 int ad_valu_probe(int32_t kind, int32_t blocks, int32_t iters, float* sink, long long* clk, void* stream);
 
 /* ---- Stroke-averaged far-field equations (Sec. III, Eqs. e:eom, J, K) ----

@@ -1,6 +1,7 @@
 /*
  * Measurement support: the vector-ALU issue rate of the FP32 Oseen pair
- * term's own instruction mix, and the shader clock under that load.
+ * term's own instruction mix, and the shader clock under that load (the
+ * longest work-group life in shader cycles over the kernel's duration).
  *
  * Every lane evaluates pair terms of one target against 8 sources held in
  * registers (no memory traffic inside the loop), exactly as the pair loops
@@ -46,7 +47,7 @@ template <int KIND>
 __global__ __launch_bounds__(256) void k_valu_rate(int iters, float seed, float* __restrict__ sink,
                                                    long long* __restrict__ clk) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const long long c0 = clock64(), w0 = wall_clock64();
+    const long long c0 = clock64();
     const float b = seed + 1e-3f * (float)(threadIdx.x & 63);
     float sx[8], sy[8], sz[8], fx[8], fy[8], fz[8];
 #pragma unroll
@@ -101,21 +102,21 @@ __global__ __launch_bounds__(256) void k_valu_rate(int iters, float seed, float*
     sink[g] = out;
     __syncthreads();
     if (threadIdx.x == 0) {
-        /* shader cycles and constant-rate ticks of this work-group's life */
-        atomicAdd(reinterpret_cast<unsigned long long*>(&clk[0]), (unsigned long long)(clock64() - c0));
-        atomicAdd(reinterpret_cast<unsigned long long*>(&clk[1]), (unsigned long long)(wall_clock64() - w0));
+        /* shader cycles of this work-group's life: the longest, and the sum */
+        const unsigned long long cyc = (unsigned long long)(clock64() - c0);
+        atomicMax(reinterpret_cast<unsigned long long*>(&clk[0]), cyc);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&clk[1]), cyc);
     }
 }
 
 }  // namespace
 
 /* kind 0: Oseen term with single-float positions, 1: FMA chains, 2: Oseen
- * term with hi/lo positions, 3: kind 0 with four accumulators. blocks work-groups of 256 threads, iters loop
- * trips of 8 terms (or 8 FMAs) per thread; sink: device [blocks*256] floats;
- * clk: device [2], zeroed by the caller: the sums over work-groups of the
- * shader cycles and of the constant-rate counter ticks (hipDeviceAttribute-
- * WallClockRate) that each work-group lived, whose ratio is the shader
- * clock. Asynchronous. */
+ * term with hi/lo positions, 3: kind 0 with four accumulators. blocks
+ * work-groups of 256 threads, iters loop trips of 8 terms (or 8 FMAs) per
+ * thread; sink: device [blocks*256] floats; clk: device [2], zeroed by the
+ * caller: the longest life of a work-group in shader cycles, and the sum
+ * over work-groups. Asynchronous. */
 extern "C" int ad_valu_probe(int32_t kind, int32_t blocks, int32_t iters, float* sink, long long* clk,
                              void* stream) {
     if (blocks < 1 || iters < 1 || !sink || !clk || kind < 0 || kind > 3) return AD_EINVAL;

@@ -274,11 +274,16 @@ __host__ __device__ inline int resident_lds_bytes(int n, int p64, int rpy) {
     if (p64) return b + resident_cols(n, rpy) * n * 24 * (rpy ? 2 : 1);
     return b + n * 36;
 }
+/* threads of a resident work-group: for FP32C one wave up to 32 spheres
+ * (its barriers then cost next to nothing), RES_T above and for FP64, whose
+ * term evaluations are long dependent chains best spread over the four
+ * SIMDs */
+__host__ __device__ inline int resident_threads(int maxn, int p64) { return (!p64 && maxn <= 32) ? 64 : RES_T; }
 /* target lanes per system sphere in the FP32C resident pair sum: the
- * largest power of two s <= 64 with s n <= RES_T */
-__host__ __device__ inline int resident_split(int n) {
+ * largest power of two s <= 64 with s n <= t (t threads) */
+__host__ __device__ inline int resident_split(int n, int t) {
     int s = 1;
-    while (s < 64 && 2 * s * n <= RES_T) s *= 2;
+    while (s < 64 && 2 * s * n <= t) s *= 2;
     return s;
 }
 hipError_t launch_resident(const Dev& d, const Epi& e, int hilo, int maxNb, long long step0, int nsteps,

@@ -1677,9 +1677,9 @@ __device__ __forceinline__ double res_update(const Coef& c, int integ, int stage
  *   in a fixed tree.
  * The state comes from and returns to d.X; the first stage's forces are
  * formed at (st0, ct0) = (sin, cos)(omega t) of step step0. */
-template <int P64, int SPLIT, int RPY>
-__global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step0, int nsteps, double st0,
-                                                    double ct0) {
+template <int P64, int SPLIT, int RPY, int T>
+__global__ __launch_bounds__(T) void k_resident(Dev d, Epi e, long long step0, int nsteps, double st0,
+                                                double ct0) {
     extern __shared__ double res_lds[];
     const Item it = d.fitems[blockIdx.x];
     const int n = it.Nb, ioff = it.ioff, S = n / 2;
@@ -1695,108 +1695,107 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
     double* Bcc = Acc + 3 * n;
     char* tail = reinterpret_cast<char*>(res_lds) +
                  ((3 * n * (4 + ((P64 && RPY) ? 2 : 1) + (P64 ? 0 : 1))) * 8 + 15) / 16 * 16;
-    double* T = reinterpret_cast<double*>(tail); /* FP64 term chunk [n][cc][3] (RPY: then [n][cc][3]) */
+    double* Tm = reinterpret_cast<double*>(tail); /* FP64 term chunk [n][cc][3] (RPY: then [n][cc][3]) */
     float4* pA = reinterpret_cast<float4*>(tail);
     float4* pB = pA + n;
     float* pz = reinterpret_cast<float*>(pB + n);
     const int cc = P64 ? resident_cols(n, RPY) : 0;
-    double* Tb = T + 3 * n * cc;
-    const int split = P64 ? 1 : resident_split(n);
+    double* Tb = Tm + 3 * n * cc;
+    const int split = P64 ? 1 : resident_split(n, T);
 
     /* state in, phases of this thread's dumbbell */
-    for (int q = tid; q < 3 * n; q += RES_T) {
+    for (int q = tid; q < 3 * n; q += T) {
         const int a = q / n, i = q - a * n;
         const double v = d.X[a * N + ioff + i];
         X[q] = v;
         Y[q] = v;
     }
     double2 tp = make_double2(0.0, 0.0);
-    if (tid < S) tp = d.phitrig[(ioff >> 1) + tid];
+    if (tid < n) tp = d.phitrig[(ioff >> 1) + (tid >> 1)];
     int bad = 0;
     __syncthreads();
 
-    /* One thread per dumbbell: the closing update of its two spheres (from
-     * the pair sums of the stage just summed: velocity, stage update, state
-     * and accumulator in LDS), or with stage < 0 their positions as they are,
-     * then the spring forces at (st, ct) and, for FP32C, the pack and U0 of
-     * the next stage. Each thread reads and writes only its own spheres'
-     * F, U0, X, R and Y, so no barrier is needed inside. */
-    auto close_and_force = [&](int stage, double st, double ct, long long step) {
-        if (tid < S) {
-            const int i0 = 2 * tid;
-            double y[2][3];
-            for (int h = 0; h < 2; ++h) {
-                const int i = i0 + h;
-                for (int a = 0; a < 3; ++a) {
-                    const int o = a * n + i;
-                    if (stage < 0) {
-                        y[h][a] = Y[o];
-                        continue;
-                    }
-                    double k;
-                    if (P64) {
-                        k = c.cs * F[o] + c.co * Acc[3 * i + a];
-                        if (RPY) k = k + c.cr * Bcc[3 * i + a];
-                    } else {
-                        k = U0[o] + c.co * Acc[o];
-                    }
-                    if (!isfinite(k)) bad = 1;
-                    const double nz =
-                        (e.integ == 1 && c.noise) ? c.g * gauss_component(c.seed, ioff + i, step, a) : 0.0;
-                    double x = X[o], r = R[o];
-                    y[h][a] = res_update(c, e.integ, stage, e.nst, k, x, r, nz);
-                    X[o] = x;
-                    R[o] = r;
-                    Y[o] = y[h][a];
-                }
-            }
-            double f0[3], f1[3];
+    /* Closing of the stage just summed, one thread per sphere component:
+     * velocity, stage update (state and RK accumulator in LDS), next stage
+     * position Y. */
+    auto closing = [&](int stage, long long step) {
+        for (int q = tid; q < 3 * n; q += T) {
+            int i, a, o;
+            double k;
             if (P64) {
-                spring_forces(c, y[0], y[1], tp.x, tp.y, st, ct, f0, f1);
+                i = q / 3;
+                a = q - 3 * i;
+                o = a * n + i;
+                k = c.cs * F[o] + c.co * Acc[q];
+                if (RPY) k = k + c.cr * Bcc[q];
             } else {
-                spring_forces_rs(c, y[0], y[1], tp.x, tp.y, st, ct, f0, f1);
+                a = q / n;
+                i = q - a * n;
+                o = q;
+                k = U0[o] + c.co * Acc[o];
             }
+            if (!isfinite(k)) bad = 1;
+            const double nz = (e.integ == 1 && c.noise) ? c.g * gauss_component(c.seed, ioff + i, step, a) : 0.0;
+            double x = X[o], r = R[o];
+            Y[o] = res_update(c, e.integ, stage, e.nst, k, x, r, nz);
+            X[o] = x;
+            R[o] = r;
+        }
+        __syncthreads();
+    };
+    /* Spring forces at (st, ct) and the positions Y, one thread per sphere:
+     * both threads of a dumbbell evaluate its forces from the same inputs
+     * (the same bits) and each keeps its own sphere's force, and for FP32C
+     * forms its own U0 and pack entry. */
+    auto forces = [&](double st, double ct) {
+        if (tid < n) {
+            const int h = tid & 1, i0 = tid & ~1;
+            double y0[3], y1[3], f0[3], f1[3];
             for (int a = 0; a < 3; ++a) {
-                F[a * n + i0] = f0[a];
-                F[a * n + i0 + 1] = f1[a];
+                y0[a] = Y[a * n + i0];
+                y1[a] = Y[a * n + i0 + 1];
             }
+            if (P64) {
+                spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+            } else {
+                spring_forces_rs(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+            }
+            const double* yy = h ? y1 : y0;
+            const double* yp = h ? y0 : y1;
+            const double* f = h ? f1 : f0;
+            const double* fp = h ? f0 : f1;
+            for (int a = 0; a < 3; ++a) F[a * n + tid] = f[a];
             if (!P64) {
-                for (int h = 0; h < 2; ++h) {
-                    const double* yy = y[h];
-                    const double* yp = y[h ^ 1];
-                    const double* f = h ? f1 : f0;
-                    const double* fp = h ? f0 : f1;
-                    const double r[3] = {yy[0] - yp[0], yy[1] - yp[1], yy[2] - yp[2]};
-                    const double ir = rsqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
-                    const double ir2 = ir * ir;
-                    const double tt = ((r[0] * fp[0] + r[1] * fp[1]) + r[2] * fp[2]) * ir2;
-                    for (int a = 0; a < 3; ++a) {
-                        double u = c.cs * f[a] + c.co * (ir * (fp[a] + tt * r[a]));
-                        if (RPY) u = u + c.cr * ((ir * ir2) * (fp[a] - (3.0 * tt) * r[a]));
-                        U0[a * n + i0 + h] = u;
-                    }
-                    float hi[3], lo[3];
-                    for (int a = 0; a < 3; ++a) split_f32(yy[a], hi[a], lo[a]);
-                    pA[i0 + h] = make_float4(hi[0], hi[1], hi[2], (float)f[0]);
-                    pB[i0 + h] = make_float4(lo[0], lo[1], lo[2], (float)f[1]);
-                    pz[i0 + h] = (float)f[2];
+                const double r[3] = {yy[0] - yp[0], yy[1] - yp[1], yy[2] - yp[2]};
+                const double ir = rsqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+                const double ir2 = ir * ir;
+                const double tt = ((r[0] * fp[0] + r[1] * fp[1]) + r[2] * fp[2]) * ir2;
+                for (int a = 0; a < 3; ++a) {
+                    double u = c.cs * f[a] + c.co * (ir * (fp[a] + tt * r[a]));
+                    if (RPY) u = u + c.cr * ((ir * ir2) * (fp[a] - (3.0 * tt) * r[a]));
+                    U0[a * n + tid] = u;
                 }
+                float hi[3], lo[3];
+                for (int a = 0; a < 3; ++a) split_f32(yy[a], hi[a], lo[a]);
+                pA[tid] = make_float4(hi[0], hi[1], hi[2], (float)f[0]);
+                pB[tid] = make_float4(lo[0], lo[1], lo[2], (float)f[1]);
+                pz[tid] = (float)f[2];
             }
         }
         __syncthreads();
     };
-    /* this step's (sin, cos)(omega t) row of the step table, in the dumbbell
+    /* this step's (sin, cos)(omega t) row of the step table, in the sphere
      * threads; the next step's row is loaded while a step runs */
     double tb[8], nb[8];
     for (int q = 0; q < 8; ++q) tb[q] = nb[q] = 0.0;
-    if (tid < S)
+    if (tid < n)
         for (int q = 0; q < 8; ++q) tb[q] = d.tab[(step0 % d.ring) * 8 + q];
-    close_and_force(-1, st0, ct0, step0);
+    forces(st0, ct0);
 
     const float crr = c.crr;
     for (int sn = 0; sn < nsteps; ++sn) {
         const long long step = step0 + sn;
-        if (tid < S) {
+        if (tid < n) {
             const long long nrow = (step + 1) % d.ring;
             for (int q = 0; q < 8; ++q) nb[q] = d.tab[nrow * 8 + q];
         }
@@ -1805,9 +1804,9 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
             if (P64) {
                 for (int j0 = 0; j0 < n; j0 += cc) {
                     const int nc = min(cc, n - j0);
-                    for (int p = tid; p < n * nc; p += RES_T) {
+                    for (int p = tid; p < n * nc; p += T) {
                         const int i = p / nc, jj = p - i * nc, j = j0 + jj;
-                        double* t = T + (i * cc + jj) * 3;
+                        double* t = Tm + (i * cc + jj) * 3;
                         double* tb = Tb + (i * cc + jj) * 3;
                         const double r[3] = {Y[i] - Y[j], Y[n + i] - Y[n + j], Y[2 * n + i] - Y[2 * n + j]};
                         const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
@@ -1822,14 +1821,26 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
                         if (RPY) rpy_term64(r, Fj, tb);
                     }
                     __syncthreads();
-                    for (int q = tid; q < 3 * n; q += RES_T) {
+                    for (int q = tid; q < 3 * n; q += T) {
                         const int i = q / 3, a = q - 3 * i;
                         double acc = (j0 == 0) ? 0.0 : Acc[q];
                         double bcc = (RPY && j0 > 0) ? Bcc[q] : 0.0;
-                        for (int jj = 0; jj < nc; ++jj) {
-                            if (j0 + jj == i) continue;
-                            acc = acc + T[(i * cc + jj) * 3 + a];
-                            if (RPY) bcc = bcc + Tb[(i * cc + jj) * 3 + a];
+                        /* the row in ascending j, its LDS loads eight at a time */
+                        for (int jb = 0; jb < nc; jb += 8) {
+                            double v[8], w[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int jj = jb + u < nc ? jb + u : 0;
+                                v[u] = Tm[(i * cc + jj) * 3 + a];
+                                w[u] = RPY ? Tb[(i * cc + jj) * 3 + a] : 0.0;
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int jj = jb + u;
+                                if (jj >= nc || j0 + jj == i) continue;
+                                acc = acc + v[u];
+                                if (RPY) bcc = bcc + w[u];
+                            }
                         }
                         Acc[q] = acc;
                         if (RPY) Bcc[q] = bcc;
@@ -1844,25 +1855,41 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
                     const float4 Bi = pB[t];
                     const int dt = t >> 1;
                     float px = 0.f, py = 0.f, pzz = 0.f;
+                    /* four sources at a time, their LDS loads issued together; the
+                     * own dumbbell and the sources past the end are masked by a zero
+                     * 1/r (their term is then exactly zero) */
                     int cnt = 0;
-                    for (int j = sub; j < n; j += split) {
-                        if ((j >> 1) == dt) continue;
-                        const float4 Aj = pA[j];
-                        const float4 Bj = pB[j];
-                        float rx, ry, rz;
-                        if (SPLIT) {
-                            rx = (Ai.x - Aj.x) + (Bi.x - Bj.x);
-                            ry = (Ai.y - Aj.y) + (Bi.y - Bj.y);
-                            rz = (Ai.z - Aj.z) + (Bi.z - Bj.z);
-                        } else {
-                            rx = Ai.x - Aj.x;
-                            ry = Ai.y - Aj.y;
-                            rz = Ai.z - Aj.z;
+                    for (int j0 = sub; j0 < n; j0 += 4 * split) {
+                        float4 Aj[4], Bj[4];
+                        float Fz[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int j = j0 + u * split;
+                            const int jj = j < n ? j : t;
+                            Aj[u] = pA[jj];
+                            Bj[u] = pB[jj];
+                            Fz[u] = pz[jj];
                         }
-                        const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
-                        const float ir = __builtin_amdgcn_rsqf(r2);
-                        pair_term<RPY>(ir, rx, ry, rz, Aj.w, Bj.w, pz[j], crr, px, py, pzz);
-                        if (++cnt == 32) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int j = j0 + u * split;
+                            float rx, ry, rz;
+                            if (SPLIT) {
+                                rx = (Ai.x - Aj[u].x) + (Bi.x - Bj[u].x);
+                                ry = (Ai.y - Aj[u].y) + (Bi.y - Bj[u].y);
+                                rz = (Ai.z - Aj[u].z) + (Bi.z - Bj[u].z);
+                            } else {
+                                rx = Ai.x - Aj[u].x;
+                                ry = Ai.y - Aj[u].y;
+                                rz = Ai.z - Aj[u].z;
+                            }
+                            const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                            float ir = __builtin_amdgcn_rsqf(r2);
+                            if (j >= n || (j >> 1) == dt) ir = 0.f;
+                            pair_term<RPY>(ir, rx, ry, rz, Aj[u].w, Bj[u].w, Fz[u], crr, px, py, pzz);
+                        }
+                        cnt += 4;
+                        if (cnt == 32) {
                             two_sum_acc(ax, bx, px);
                             two_sum_acc(ay, by, py);
                             two_sum_acc(az, bz, pzz);
@@ -1897,11 +1924,12 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
                 __syncthreads();
             }
             /* ---- closing, next stage positions and forces */
-            close_and_force(stage, tb[2 * stage], tb[2 * stage + 1], step);
+            closing(stage, step);
+            forces(tb[2 * stage], tb[2 * stage + 1]);
         }
         for (int q = 0; q < 8; ++q) tb[q] = nb[q];
     }
-    for (int q = tid; q < 3 * n; q += RES_T) {
+    for (int q = tid; q < 3 * n; q += T) {
         const int a = q / n, i = q - a * n;
         d.X[a * N + ioff + i] = X[q];
     }
@@ -2077,12 +2105,13 @@ hipError_t prepare_fused() {
             return err;
         }
     }
-    const void* resident[] = {reinterpret_cast<const void*>(&k_resident<1, 0, 0>),
-                              reinterpret_cast<const void*>(&k_resident<1, 0, 1>),
-                              reinterpret_cast<const void*>(&k_resident<0, 0, 0>),
-                              reinterpret_cast<const void*>(&k_resident<0, 0, 1>),
-                              reinterpret_cast<const void*>(&k_resident<0, 1, 0>),
-                              reinterpret_cast<const void*>(&k_resident<0, 1, 1>)};
+    const void* resident[] = {
+        reinterpret_cast<const void*>(&k_resident<1, 0, 0, 64>), reinterpret_cast<const void*>(&k_resident<1, 0, 1, 64>),
+        reinterpret_cast<const void*>(&k_resident<0, 0, 0, 64>), reinterpret_cast<const void*>(&k_resident<0, 0, 1, 64>),
+        reinterpret_cast<const void*>(&k_resident<0, 1, 0, 64>), reinterpret_cast<const void*>(&k_resident<0, 1, 1, 64>),
+        reinterpret_cast<const void*>(&k_resident<1, 0, 0, 256>), reinterpret_cast<const void*>(&k_resident<1, 0, 1, 256>),
+        reinterpret_cast<const void*>(&k_resident<0, 0, 0, 256>), reinterpret_cast<const void*>(&k_resident<0, 0, 1, 256>),
+        reinterpret_cast<const void*>(&k_resident<0, 1, 0, 256>), reinterpret_cast<const void*>(&k_resident<0, 1, 1, 256>)};
     for (const void* k : resident) {
         hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, RES_LDS_MAX);
         if (err != hipSuccess) {
@@ -2101,18 +2130,29 @@ hipError_t launch_resident(const Dev& d, const Epi& e, int hilo, int maxNb, long
     if (maxNb > (p64 ? RES_MAX64 : RES_MAX32)) return hipErrorInvalidValue;
     const size_t lds = (size_t)resident_lds_bytes(maxNb, p64, rpy);
     if (lds > (size_t)RES_LDS_MAX) return hipErrorInvalidValue;
+    /* one wave per system up to 32 spheres, four above */
+    const int T = resident_threads(maxNb, p64);
     void (*kern)(Dev, Epi, long long, int, double, double);
-    if (p64)
-        kern = rpy ? k_resident<1, 0, 1> : k_resident<1, 0, 0>;
-    else if (hilo)
-        kern = rpy ? k_resident<0, 1, 1> : k_resident<0, 1, 0>;
-    else
-        kern = rpy ? k_resident<0, 0, 1> : k_resident<0, 0, 0>;
+    if (T == 64) {
+        if (p64)
+            kern = rpy ? k_resident<1, 0, 1, 64> : k_resident<1, 0, 0, 64>;
+        else if (hilo)
+            kern = rpy ? k_resident<0, 1, 1, 64> : k_resident<0, 1, 0, 64>;
+        else
+            kern = rpy ? k_resident<0, 0, 1, 64> : k_resident<0, 0, 0, 64>;
+    } else {
+        if (p64)
+            kern = rpy ? k_resident<1, 0, 1, 256> : k_resident<1, 0, 0, 256>;
+        else if (hilo)
+            kern = rpy ? k_resident<0, 1, 1, 256> : k_resident<0, 1, 0, 256>;
+        else
+            kern = rpy ? k_resident<0, 0, 1, 256> : k_resident<0, 0, 0, 256>;
+    }
     if (ev_start)
-        hipExtLaunchKernelGGL(kern, dim3(d.nfitems), dim3(RES_T), lds, s, ev_start, ev_stop, 0, d, e, step0, nsteps,
-                              st0, ct0);
+        hipExtLaunchKernelGGL(kern, dim3(d.nfitems), dim3(T), lds, s, ev_start, ev_stop, 0, d, e, step0, nsteps, st0,
+                              ct0);
     else
-        hipLaunchKernelGGL(kern, dim3(d.nfitems), dim3(RES_T), lds, s, d, e, step0, nsteps, st0, ct0);
+        hipLaunchKernelGGL(kern, dim3(d.nfitems), dim3(T), lds, s, d, e, step0, nsteps, st0, ct0);
     return hipGetLastError();
 }
 

@@ -71,6 +71,10 @@ struct ad_ctx {
      * stage of the previous step call); anything that overwrites or moves it
      * clears this */
     bool pack_valid = false;
+    /* the device step slot holds c->step (every staged step leaves it so) */
+    bool slot_valid = false;
+    /* steps [tab_lo, tab_hi) have their rows in the device step table */
+    long long tab_lo = 0, tab_hi = 0;
     double t0 = 0.0;
     long long step = 0;
 
@@ -421,6 +425,10 @@ static Layout layout(const ad_ctx* c) {
 }
 
 static void make_dev(ad_ctx* c) {
+    /* the step table and the control block are re-laid out: nothing in them
+     * is current any more */
+    c->tab_lo = c->tab_hi = 0;
+    c->slot_valid = false;
     Layout L = layout(c);
     char* b = static_cast<char*>(c->ws);
     Dev& d = c->dev;
@@ -517,8 +525,13 @@ static void trig_at(const ad_ctx* c, double t, double* s, double* co) {
     *co = cos(wt);
 }
 
-/* Fill the device table for steps [s0, s0 + count), count <= kTabSteps. */
+/* Make the device table hold steps [s0, s0 + count), count <= kTabSteps:
+ * nothing to do if they are there; else the rows of kTabSteps steps from s0
+ * are computed and copied, so that runs of a few steps at a time copy once
+ * per kTabSteps steps. */
 static int fill_table(ad_ctx* c, long long s0, int count, hipStream_t st) {
+    if (s0 >= c->tab_lo && s0 + count <= c->tab_hi) return AD_OK;
+    count = kTabSteps;
     if (c->tab_event_live) HIPCHECK(c, hipEventSynchronize(c->tab_event));
     const double dt = c->p.dt;
     for (int q = 0; q < count; ++q) {
@@ -549,6 +562,8 @@ static int fill_table(ad_ctx* c, long long s0, int count, hipStream_t st) {
         HIPCHECK(c, hipMemcpyAsync(dtab, c->h_tab, (count - first) * 8 * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHECK(c, hipEventRecord(c->tab_event, st));
     c->tab_event_live = true;
+    c->tab_lo = s0;
+    c->tab_hi = s0 + count;
     return AD_OK;
 }
 
@@ -699,7 +714,8 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
         int rc = ensure_graph(c, st);
         if (rc != AD_OK) return rc;
     }
-    HIPCHECK(c, ad::launch_set_step(c->dev, c->step, st));
+    if (!c->slot_valid) HIPCHECK(c, ad::launch_set_step(c->dev, c->step, st));
+    c->slot_valid = false; /* until this call completes */
     if (!c->pack_valid && !resident) {
         double s0, c0;
         trig_at(c, c->t0 + (double)c->step * c->p.dt, &s0, &c0);
@@ -744,8 +760,10 @@ static int advance(ad_ctx* c, long long nsteps, int record_every, double* centre
         done += chunk;
     }
     c->step += nsteps;
-    /* the resident form keeps its stages in LDS and leaves no pack behind */
+    /* the resident form keeps its stages in LDS and leaves no pack or step
+     * slot behind */
     c->pack_valid = !resident;
+    c->slot_valid = !resident;
     return AD_OK;
 }
 
@@ -917,6 +935,8 @@ int ad_set_state(ad_ctx* c, const double* X, const double* phi, double t0, int64
     c->t0 = t0;
     c->step = step0;
     c->state = true;
+    c->slot_valid = false;
+    c->tab_lo = c->tab_hi = 0; /* the rows depend on t0 */
     c->pack_valid = false;
     return AD_OK;
 }
