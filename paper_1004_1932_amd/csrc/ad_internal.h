@@ -253,7 +253,7 @@ constexpr int RES_MAX64 = 128;
 constexpr int RES_MAX32 = 256;
 /* FP64 term-matrix budget per column chunk */
 constexpr int RES_TERM_BYTES = 64 * 1024;
-/* dynamic LDS a resident work-group may use (the largest need is 81 KiB:
+/* dynamic LDS a resident work-group may use (the largest need is 78 KiB:
  * 128 FP64 spheres with RPY); the kernels also hold a little static LDS */
 constexpr int RES_LDS_MAX = 96 * 1024;
 /* source columns of one FP64 term-matrix chunk for a system of n spheres */
@@ -263,27 +263,37 @@ __host__ __device__ inline int resident_cols(int n, int rpy) {
     if (cc < 1) cc = 1;
     return cc < n ? cc : n;
 }
-/* LDS bytes of a resident work-group for a system of n spheres: X, R, Y and
- * F (FP64, 3n each) and the pair sums (3n, twice with FP64 RPY), then with
- * FP64 the term-matrix chunk, with FP32C the self-and-partner velocities
- * (3n doubles) and the float pack A, B (16 B each) and Fz (4 B) */
+/* float4 entries of one FP32C resident pack buffer: A = (hi.xyz, Fx) and
+ * B = (lo.xyz, Fy) per sphere, then Fz per sphere */
+__host__ __device__ inline int resident_pack_f4(int n) { return 2 * n + (n + 3) / 4; }
+/* LDS bytes of a resident work-group for a system of n spheres: FP64 holds
+ * X, R, Y and F (3n doubles each) and the pair sums (3n, twice with RPY),
+ * then the term-matrix chunk; FP32C keeps its state in registers and holds
+ * two pack buffers */
 __host__ __device__ inline int resident_lds_bytes(int n, int p64, int rpy) {
-    const int dbl = 3 * n * (4 + ((p64 && rpy) ? 2 : 1) + (p64 ? 0 : 1));
-    int b = dbl * 8;
-    b = (b + 15) / 16 * 16;
-    if (p64) return b + resident_cols(n, rpy) * n * 24 * (rpy ? 2 : 1);
-    return b + n * 36;
+    if (!p64) return 2 * resident_pack_f4(n) * 16;
+    const int b = (3 * n * (5 + (rpy ? 1 : 0)) * 8 + 15) / 16 * 16;
+    return b + resident_cols(n, rpy) * n * 24 * (rpy ? 2 : 1);
 }
-/* threads of a resident work-group: for FP32C one wave up to 32 spheres
- * (its barriers then cost next to nothing), RES_T above and for FP64, whose
- * term evaluations are long dependent chains best spread over the four
- * SIMDs */
-__host__ __device__ inline int resident_threads(int maxn, int p64) { return (!p64 && maxn <= 32) ? 64 : RES_T; }
-/* target lanes per system sphere in the FP32C resident pair sum: the
- * largest power of two s <= 64 with s n <= t (t threads) */
+/* threads of a resident work-group: FP64 RES_T (its term evaluations are
+ * long dependent chains, best spread over the four SIMDs); FP32C one wave up
+ * to 16 spheres (its barriers cost next to nothing), above that the smallest
+ * power of two up to 512 with 8 lanes per sphere of the largest system (4
+ * lanes measured slower from 32 to 64 spheres, 8 lanes over two waves
+ * slower at 16) */
+__host__ __device__ inline int resident_threads(int maxn, int p64) {
+    if (p64) return RES_T;
+    if (maxn <= 16) return 64;
+    int t = 128;
+    while (t < 512 && t < 8 * maxn) t *= 2;
+    return t;
+}
+/* lanes per target sphere in the FP32C resident pair sum: the largest power
+ * of two s <= 32 with s n <= t (t threads); at most 32, so the lanes of both
+ * spheres of a dumbbell lie in one wave */
 __host__ __device__ inline int resident_split(int n, int t) {
     int s = 1;
-    while (s < 64 && 2 * s * n <= t) s *= 2;
+    while (s < 32 && 2 * s * n <= t) s *= 2;
     return s;
 }
 hipError_t launch_resident(const Dev& d, const Epi& e, int hilo, int maxNb, long long step0, int nsteps,

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "ad_internal.h"
 
 namespace ad {
@@ -187,10 +189,10 @@ __device__ __forceinline__ void store_pack_sphere(const Dev& d, const Coef& c, i
  * below theirs (about 1e-7); the FP64 paths keep the IEEE forms, whose
  * operation order the bitwise parity with the plain sum depends on. With
  * single-float positions (SPLIT = 0) no stage kernel reads the lo parts, so
- * B is not written. */
-__device__ __forceinline__ void spring_forces_rs(const Coef& c, const double y0[3], const double y1[3],
-                                                 double sphi, double cphi, double st, double ct,
-                                                 double f0[3], double f1[3]) {
+ * B is not written. spring_forces_rs returns the 1/d it used. */
+__device__ __forceinline__ double spring_forces_rs(const Coef& c, const double y0[3], const double y1[3],
+                                                   double sphi, double cphi, double st, double ct,
+                                                   double f0[3], double f1[3]) {
     /* -k (d - L) n / d = k (L / d - 1) n */
     const double nx = y1[0] - y0[0], ny = y1[1] - y0[1], nz = y1[2] - y0[2];
     const double id = rsqrt((nx * nx + ny * ny) + nz * nz);
@@ -202,6 +204,7 @@ __device__ __forceinline__ void spring_forces_rs(const Coef& c, const double y0[
     f0[0] = -f1[0];
     f0[1] = -f1[1];
     f0[2] = -f1[2];
+    return id;
 }
 
 template <int SPLIT>
@@ -1659,30 +1662,28 @@ __device__ __forceinline__ double res_update(const Coef& c, int integ, int stage
     return y;
 }
 
-/* Resident form (ad_launch.fused = 4): one work-group per system, the whole
- * system in LDS, every stage of nsteps steps in one launch with work-group
- * barriers between the phases of a stage:
- *   pair sums at the stage positions Y and forces F;
- *   closing: velocity, stage update (state X and RK accumulator R stay in
- *   LDS), next stage positions;
- *   forces of the next stage at the table's (sin, cos)(omega t), one thread
- *   per dumbbell.
- * P64 = 1: the plain FP64 sum, bitwise that of the sequential oracle: the
- *   terms of a chunk of source columns are evaluated in parallel into LDS,
- *   then every (target, component) adds its row of the chunk in ascending j.
- * P64 = 0: FP32C. Each target has `split` adjacent lanes that take every
- *   split-th source in ascending order (self and partner skipped: they are in
- *   the FP64 self-and-partner velocity U0), fold their FP32 sum into a
- *   (hi, lo) pair with TwoSum every 32 sources, and are combined by shuffles
- *   in a fixed tree.
- * The state comes from and returns to d.X; the first stage's forces are
- * formed at (st0, ct0) = (sin, cos)(omega t) of step step0. */
-template <int P64, int SPLIT, int RPY, int T>
-__global__ __launch_bounds__(T) void k_resident(Dev d, Epi e, long long step0, int nsteps, double st0,
-                                                double ct0) {
+/* Resident form (ad_launch.fused = 4): one work-group per system holds the
+ * system on chip and runs every stage of nsteps steps in one launch, with
+ * work-group barriers between the phases of a stage. The state comes from
+ * and returns to d.X; the first stage's forces are formed at
+ * (st0, ct0) = (sin, cos)(omega t) of step step0, and every later stage's
+ * at the step table's row, the next step's row loaded while a step runs. */
+
+/* FP64 (the plain sum, bitwise that of the sequential oracle): X, R, Y, F
+ * and the pair sums in LDS. Per stage: the terms of a chunk of source
+ * columns are evaluated in parallel into an LDS matrix, then every
+ * (target, component) thread adds its row of the chunk in ascending j;
+ * the closing (velocity, stage update, next stage position) takes one
+ * thread per sphere component, the next stage's spring forces one thread
+ * per sphere (both threads of a dumbbell evaluate them from the same
+ * inputs, so they agree bit for bit). */
+template <int RPY>
+__global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step0, int nsteps, double st0,
+                                                    double ct0) {
+    constexpr int T = RES_T;
     extern __shared__ double res_lds[];
     const Item it = d.fitems[blockIdx.x];
-    const int n = it.Nb, ioff = it.ioff, S = n / 2;
+    const int n = it.Nb, ioff = it.ioff;
     const int N = d.Ntot;
     const int tid = threadIdx.x;
     const Coef& c = e.c;
@@ -1690,20 +1691,13 @@ __global__ __launch_bounds__(T) void k_resident(Dev d, Epi e, long long step0, i
     double* R = X + 3 * n;
     double* Y = R + 3 * n;
     double* F = Y + 3 * n;
-    double* Acc = F + 3 * n; /* pair sums [3n] (FP64 RPY: [6n]) */
-    double* U0 = Acc + 3 * n;
+    double* Acc = F + 3 * n; /* pair sums [3n] (RPY: then [3n]) */
     double* Bcc = Acc + 3 * n;
-    char* tail = reinterpret_cast<char*>(res_lds) +
-                 ((3 * n * (4 + ((P64 && RPY) ? 2 : 1) + (P64 ? 0 : 1))) * 8 + 15) / 16 * 16;
-    double* Tm = reinterpret_cast<double*>(tail); /* FP64 term chunk [n][cc][3] (RPY: then [n][cc][3]) */
-    float4* pA = reinterpret_cast<float4*>(tail);
-    float4* pB = pA + n;
-    float* pz = reinterpret_cast<float*>(pB + n);
-    const int cc = P64 ? resident_cols(n, RPY) : 0;
-    double* Tb = Tm + 3 * n * cc;
-    const int split = P64 ? 1 : resident_split(n, T);
+    double* Tm = reinterpret_cast<double*>(reinterpret_cast<char*>(res_lds) +
+                                           ((3 * n * (5 + (RPY ? 1 : 0))) * 8 + 15) / 16 * 16);
+    const int cc = resident_cols(n, RPY);
+    double* Tb = Tm + 3 * n * cc; /* RPY corrections of the chunk */
 
-    /* state in, phases of this thread's dumbbell */
     for (int q = tid; q < 3 * n; q += T) {
         const int a = q / n, i = q - a * n;
         const double v = d.X[a * N + ioff + i];
@@ -1715,25 +1709,11 @@ __global__ __launch_bounds__(T) void k_resident(Dev d, Epi e, long long step0, i
     int bad = 0;
     __syncthreads();
 
-    /* Closing of the stage just summed, one thread per sphere component:
-     * velocity, stage update (state and RK accumulator in LDS), next stage
-     * position Y. */
     auto closing = [&](int stage, long long step) {
         for (int q = tid; q < 3 * n; q += T) {
-            int i, a, o;
-            double k;
-            if (P64) {
-                i = q / 3;
-                a = q - 3 * i;
-                o = a * n + i;
-                k = c.cs * F[o] + c.co * Acc[q];
-                if (RPY) k = k + c.cr * Bcc[q];
-            } else {
-                a = q / n;
-                i = q - a * n;
-                o = q;
-                k = U0[o] + c.co * Acc[o];
-            }
+            const int i = q / 3, a = q - 3 * i, o = a * n + i;
+            double k = c.cs * F[o] + c.co * Acc[q];
+            if (RPY) k = k + c.cr * Bcc[q];
             if (!isfinite(k)) bad = 1;
             const double nz = (e.integ == 1 && c.noise) ? c.g * gauss_component(c.seed, ioff + i, step, a) : 0.0;
             double x = X[o], r = R[o];
@@ -1743,56 +1723,26 @@ __global__ __launch_bounds__(T) void k_resident(Dev d, Epi e, long long step0, i
         }
         __syncthreads();
     };
-    /* Spring forces at (st, ct) and the positions Y, one thread per sphere:
-     * both threads of a dumbbell evaluate its forces from the same inputs
-     * (the same bits) and each keeps its own sphere's force, and for FP32C
-     * forms its own U0 and pack entry. */
     auto forces = [&](double st, double ct) {
         if (tid < n) {
-            const int h = tid & 1, i0 = tid & ~1;
+            const int i0 = tid & ~1;
             double y0[3], y1[3], f0[3], f1[3];
             for (int a = 0; a < 3; ++a) {
                 y0[a] = Y[a * n + i0];
                 y1[a] = Y[a * n + i0 + 1];
             }
-            if (P64) {
-                spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
-            } else {
-                spring_forces_rs(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
-            }
-            const double* yy = h ? y1 : y0;
-            const double* yp = h ? y0 : y1;
-            const double* f = h ? f1 : f0;
-            const double* fp = h ? f0 : f1;
+            spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+            const double* f = (tid & 1) ? f1 : f0;
             for (int a = 0; a < 3; ++a) F[a * n + tid] = f[a];
-            if (!P64) {
-                const double r[3] = {yy[0] - yp[0], yy[1] - yp[1], yy[2] - yp[2]};
-                const double ir = rsqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
-                const double ir2 = ir * ir;
-                const double tt = ((r[0] * fp[0] + r[1] * fp[1]) + r[2] * fp[2]) * ir2;
-                for (int a = 0; a < 3; ++a) {
-                    double u = c.cs * f[a] + c.co * (ir * (fp[a] + tt * r[a]));
-                    if (RPY) u = u + c.cr * ((ir * ir2) * (fp[a] - (3.0 * tt) * r[a]));
-                    U0[a * n + tid] = u;
-                }
-                float hi[3], lo[3];
-                for (int a = 0; a < 3; ++a) split_f32(yy[a], hi[a], lo[a]);
-                pA[tid] = make_float4(hi[0], hi[1], hi[2], (float)f[0]);
-                pB[tid] = make_float4(lo[0], lo[1], lo[2], (float)f[1]);
-                pz[tid] = (float)f[2];
-            }
         }
         __syncthreads();
     };
-    /* this step's (sin, cos)(omega t) row of the step table, in the sphere
-     * threads; the next step's row is loaded while a step runs */
     double tb[8], nb[8];
     for (int q = 0; q < 8; ++q) tb[q] = nb[q] = 0.0;
     if (tid < n)
         for (int q = 0; q < 8; ++q) tb[q] = d.tab[(step0 % d.ring) * 8 + q];
     forces(st0, ct0);
 
-    const float crr = c.crr;
     for (int sn = 0; sn < nsteps; ++sn) {
         const long long step = step0 + sn;
         if (tid < n) {
@@ -1800,130 +1750,51 @@ __global__ __launch_bounds__(T) void k_resident(Dev d, Epi e, long long step0, i
             for (int q = 0; q < 8; ++q) nb[q] = d.tab[nrow * 8 + q];
         }
         for (int stage = 0; stage < e.nst; ++stage) {
-            /* ---- pair sums */
-            if (P64) {
-                for (int j0 = 0; j0 < n; j0 += cc) {
-                    const int nc = min(cc, n - j0);
-                    for (int p = tid; p < n * nc; p += T) {
-                        const int i = p / nc, jj = p - i * nc, j = j0 + jj;
-                        double* t = Tm + (i * cc + jj) * 3;
-                        double* tb = Tb + (i * cc + jj) * 3;
-                        const double r[3] = {Y[i] - Y[j], Y[n + i] - Y[n + j], Y[2 * n + i] - Y[2 * n + j]};
-                        const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
-                        if (j == i || r2 == 0.0) {
-                            if (j != i) bad = 1;
-                            t[0] = t[1] = t[2] = 0.0;
-                            if (RPY) tb[0] = tb[1] = tb[2] = 0.0;
-                            continue;
-                        }
-                        const double Fj[3] = {F[j], F[n + j], F[2 * n + j]};
-                        oseen_term64(r, Fj, t);
-                        if (RPY) rpy_term64(r, Fj, tb);
+            for (int j0 = 0; j0 < n; j0 += cc) {
+                const int nc = min(cc, n - j0);
+                for (int p = tid; p < n * nc; p += T) {
+                    const int i = p / nc, jj = p - i * nc, j = j0 + jj;
+                    double* t = Tm + (i * cc + jj) * 3;
+                    double* tq = Tb + (i * cc + jj) * 3;
+                    const double r[3] = {Y[i] - Y[j], Y[n + i] - Y[n + j], Y[2 * n + i] - Y[2 * n + j]};
+                    const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+                    if (j == i || r2 == 0.0) {
+                        if (j != i) bad = 1;
+                        t[0] = t[1] = t[2] = 0.0;
+                        if (RPY) tq[0] = tq[1] = tq[2] = 0.0;
+                        continue;
                     }
-                    __syncthreads();
-                    for (int q = tid; q < 3 * n; q += T) {
-                        const int i = q / 3, a = q - 3 * i;
-                        double acc = (j0 == 0) ? 0.0 : Acc[q];
-                        double bcc = (RPY && j0 > 0) ? Bcc[q] : 0.0;
-                        /* the row in ascending j, its LDS loads eight at a time */
-                        for (int jb = 0; jb < nc; jb += 8) {
-                            double v[8], w[8];
-#pragma unroll
-                            for (int u = 0; u < 8; ++u) {
-                                const int jj = jb + u < nc ? jb + u : 0;
-                                v[u] = Tm[(i * cc + jj) * 3 + a];
-                                w[u] = RPY ? Tb[(i * cc + jj) * 3 + a] : 0.0;
-                            }
-#pragma unroll
-                            for (int u = 0; u < 8; ++u) {
-                                const int jj = jb + u;
-                                if (jj >= nc || j0 + jj == i) continue;
-                                acc = acc + v[u];
-                                if (RPY) bcc = bcc + w[u];
-                            }
-                        }
-                        Acc[q] = acc;
-                        if (RPY) Bcc[q] = bcc;
-                    }
-                    __syncthreads();
+                    const double Fj[3] = {F[j], F[n + j], F[2 * n + j]};
+                    oseen_term64(r, Fj, t);
+                    if (RPY) rpy_term64(r, Fj, tq);
                 }
-            } else {
-                const int t = tid / split, sub = tid - t * split;
-                float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
-                if (t < n) {
-                    const float4 Ai = pA[t];
-                    const float4 Bi = pB[t];
-                    const int dt = t >> 1;
-                    float px = 0.f, py = 0.f, pzz = 0.f;
-                    /* four sources at a time, their LDS loads issued together; the
-                     * own dumbbell and the sources past the end are masked by a zero
-                     * 1/r (their term is then exactly zero) */
-                    int cnt = 0;
-                    for (int j0 = sub; j0 < n; j0 += 4 * split) {
-                        float4 Aj[4], Bj[4];
-                        float Fz[4];
+                __syncthreads();
+                for (int q = tid; q < 3 * n; q += T) {
+                    const int i = q / 3, a = q - 3 * i;
+                    double acc = (j0 == 0) ? 0.0 : Acc[q];
+                    double bcc = (RPY && j0 > 0) ? Bcc[q] : 0.0;
+                    /* the row in ascending j, its LDS loads eight at a time */
+                    for (int jb = 0; jb < nc; jb += 8) {
+                        double v[8], w[8];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int j = j0 + u * split;
-                            const int jj = j < n ? j : t;
-                            Aj[u] = pA[jj];
-                            Bj[u] = pB[jj];
-                            Fz[u] = pz[jj];
+                        for (int u = 0; u < 8; ++u) {
+                            const int jj = jb + u < nc ? jb + u : 0;
+                            v[u] = Tm[(i * cc + jj) * 3 + a];
+                            w[u] = RPY ? Tb[(i * cc + jj) * 3 + a] : 0.0;
                         }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int j = j0 + u * split;
-                            float rx, ry, rz;
-                            if (SPLIT) {
-                                rx = (Ai.x - Aj[u].x) + (Bi.x - Bj[u].x);
-                                ry = (Ai.y - Aj[u].y) + (Bi.y - Bj[u].y);
-                                rz = (Ai.z - Aj[u].z) + (Bi.z - Bj[u].z);
-                            } else {
-                                rx = Ai.x - Aj[u].x;
-                                ry = Ai.y - Aj[u].y;
-                                rz = Ai.z - Aj[u].z;
-                            }
-                            const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
-                            float ir = __builtin_amdgcn_rsqf(r2);
-                            if (j >= n || (j >> 1) == dt) ir = 0.f;
-                            pair_term<RPY>(ir, rx, ry, rz, Aj[u].w, Bj[u].w, Fz[u], crr, px, py, pzz);
-                        }
-                        cnt += 4;
-                        if (cnt == 32) {
-                            two_sum_acc(ax, bx, px);
-                            two_sum_acc(ay, by, py);
-                            two_sum_acc(az, bz, pzz);
-                            px = py = pzz = 0.f;
-                            cnt = 0;
+                        for (int u = 0; u < 8; ++u) {
+                            const int jj = jb + u;
+                            if (jj >= nc || j0 + jj == i) continue;
+                            acc = acc + v[u];
+                            if (RPY) bcc = bcc + w[u];
                         }
                     }
-                    two_sum_acc(ax, bx, px);
-                    two_sum_acc(ay, by, py);
-                    two_sum_acc(az, bz, pzz);
-                }
-                auto combine = [](float& hi, float& lo, float oh, float ol) {
-                    const float s = hi + oh;
-                    const float bb = s - hi;
-                    const float err = (hi - (s - bb)) + (oh - bb);
-                    hi = s;
-                    lo = (lo + ol) + err;
-                };
-                for (int sh = 1; sh < split; sh *= 2) {
-                    const float oax = __shfl_xor(ax, sh), obx = __shfl_xor(bx, sh);
-                    const float oay = __shfl_xor(ay, sh), oby = __shfl_xor(by, sh);
-                    const float oaz = __shfl_xor(az, sh), obz = __shfl_xor(bz, sh);
-                    combine(ax, bx, oax, obx);
-                    combine(ay, by, oay, oby);
-                    combine(az, bz, oaz, obz);
-                }
-                if (t < n && sub == 0) {
-                    Acc[t] = (double)ax + (double)bx;
-                    Acc[n + t] = (double)ay + (double)by;
-                    Acc[2 * n + t] = (double)az + (double)bz;
+                    Acc[q] = acc;
+                    if (RPY) Bcc[q] = bcc;
                 }
                 __syncthreads();
             }
-            /* ---- closing, next stage positions and forces */
             closing(stage, step);
             forces(tb[2 * stage], tb[2 * stage + 1]);
         }
@@ -1933,6 +1804,234 @@ __global__ __launch_bounds__(T) void k_resident(Dev d, Epi e, long long step0, i
         const int a = q / n, i = q - a * n;
         d.X[a * N + ioff + i] = X[q];
     }
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+}
+
+/* One level of the fixed butterfly that combines the (hi, lo) sums
+ * v = (hi.x, lo.x, hi.y, lo.y, hi.z, lo.z) of adjacent lanes: each lane takes
+ * the sums of lane (itself xor distance) and adds them in with TwoSum. */
+__device__ __forceinline__ void combine_hilo(float v[6], const float o[6]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float& hi = v[2 * a];
+        float& lo = v[2 * a + 1];
+        const float oh = o[2 * a], ol = o[2 * a + 1];
+        const float s = hi + oh;
+        const float bb = s - hi;
+        const float err = (hi - (s - bb)) + (oh - bb);
+        hi = s;
+        lo = (lo + ol) + err;
+    }
+}
+/* distances 1 and 2 through DPP quad permutations (CTRL 0xB1 swaps the lanes
+ * of each pair, 0x4E the pairs of each quad): a VALU operation, no LDS round
+ * trip */
+template <int CTRL>
+__device__ __forceinline__ void combine_level_dpp(float v[6]) {
+    float o[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        o[q] = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[q]), CTRL, 0xF,
+                                                                     0xF, false));
+    combine_hilo(v, o);
+}
+/* larger distances (uniform over the wave) through ds_bpermute */
+__device__ __forceinline__ void combine_level_shfl(float v[6], int sh) {
+    float o[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) o[q] = __shfl_xor(v[q], sh);
+    combine_hilo(v, o);
+}
+
+/* Work-group barrier that orders LDS only: vector-memory loads in flight
+ * (the step table's next row) are not waited for. */
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+/* FP32C: the state in registers, only the float pack in LDS. Target sphere
+ * t of the system has `split` adjacent lanes (a power of two <= 32, so a
+ * dumbbell's lanes lie in one wave); lane 0 of them, the sphere's own lane,
+ * holds its FP64 state x, RK accumulator r, stage position y and
+ * self-and-partner velocity u0. Per stage:
+ *   pair sums: each of the split lanes takes every split-th source in
+ *   ascending order (own dumbbell masked by a zero 1/r), folding into
+ *   (hi, lo) with TwoSum every 32 sources; the lanes are combined in a
+ *   fixed butterfly;
+ *   closing in the own lane: velocity, stage update, next stage position;
+ *   next forces in the own lane: the partner's position by a lane exchange,
+ *   the spring forces (both lanes of a dumbbell evaluate the same
+ *   expression), u0 (the partner term reusing the spring's 1/d), and the
+ *   sphere's pack entry, written into the other of two pack buffers;
+ * then one work-group barrier. Stage s reads buffer s mod 2 and writes the
+ * other, and every read of a buffer precedes the barrier that precedes its
+ * next write. */
+template <int SPLIT, int RPY, int T, int INTEG>
+__global__ __launch_bounds__(T) void k_resident_c(Dev d, Epi e, long long step0, int nsteps, double st0,
+                                                  double ct0) {
+    /* INTEG: 0 RK4, 1 Heun, 2 Heun with noise; the stages are unrolled, so
+     * every stage's update and table entries are fixed at compile time */
+    constexpr int NST = INTEG == 0 ? 4 : 2;
+    extern __shared__ float4 rc_lds[];
+    const Item it = d.fitems[blockIdx.x];
+    const int n = it.Nb, ioff = it.ioff;
+    const int N = d.Ntot;
+    const int tid = threadIdx.x;
+    const Coef& c = e.c;
+    const int split = resident_split(n, T);
+    const int t = tid >> __builtin_ctz(split), sub = tid & (split - 1);
+    const bool own = t < n && sub == 0;
+    const int h = t & 1;
+    const int pstride = resident_pack_f4(n); /* float4 per pack buffer */
+
+    double x[3], r[3], y[3], u0[3];
+    double2 tp = make_double2(0.0, 0.0);
+    double tb[8], nb[8];
+    for (int a = 0; a < 3; ++a) x[a] = r[a] = y[a] = u0[a] = 0.0;
+    for (int q = 0; q < 8; ++q) tb[q] = nb[q] = 0.0;
+    /* the step table's row index, held in a vector register so that its
+     * loads are vector loads, which the LDS waits and barriers do not wait
+     * for (a scalar load would be waited for by every LDS wait) */
+    int row = (int)(step0 % d.ring);
+    asm volatile("" : "+v"(row));
+    if (own) {
+        for (int a = 0; a < 3; ++a) x[a] = y[a] = d.X[a * N + ioff + t];
+        tp = d.phitrig[(ioff >> 1) + (t >> 1)];
+        for (int q = 0; q < 8; ++q) tb[q] = d.tab[row * 8 + q];
+    }
+    int bad = 0;
+
+    auto forces = [&](double st, double ct, int buf) {
+        double yp[3];
+        for (int a = 0; a < 3; ++a) yp[a] = __shfl_xor(y[a], split);
+        if (own) {
+            /* lower and upper sphere of the dumbbell, by value selects (a
+             * select of array pointers would put the arrays in scratch) */
+            double ya[3], yb[3], f0[3], f1[3], f[3], fp[3];
+            for (int a = 0; a < 3; ++a) {
+                ya[a] = h ? yp[a] : y[a];
+                yb[a] = h ? y[a] : yp[a];
+            }
+            const double id = spring_forces_rs(c, ya, yb, tp.x, tp.y, st, ct, f0, f1);
+            for (int a = 0; a < 3; ++a) {
+                f[a] = h ? f1[a] : f0[a];
+                fp[a] = h ? f0[a] : f1[a];
+            }
+            /* r = y - yp is +-(y1 - y0) exactly, so 1/|r| is the spring's 1/d */
+            const double rr[3] = {y[0] - yp[0], y[1] - yp[1], y[2] - yp[2]};
+            const double ir2 = id * id;
+            const double tt = ((rr[0] * fp[0] + rr[1] * fp[1]) + rr[2] * fp[2]) * ir2;
+            for (int a = 0; a < 3; ++a) {
+                double u = c.cs * f[a] + c.co * (id * (fp[a] + tt * rr[a]));
+                if (RPY) u = u + c.cr * ((id * ir2) * (fp[a] - (3.0 * tt) * rr[a]));
+                u0[a] = u;
+            }
+            float hi[3], lo[3];
+            for (int a = 0; a < 3; ++a) split_f32(y[a], hi[a], lo[a]);
+            float4* pA = rc_lds + buf * pstride;
+            float4* pB = pA + n;
+            float* pz = reinterpret_cast<float*>(pB + n);
+            pA[t] = make_float4(hi[0], hi[1], hi[2], (float)f[0]);
+            pB[t] = make_float4(lo[0], lo[1], lo[2], (float)f[1]);
+            pz[t] = (float)f[2];
+        }
+        lds_barrier();
+    };
+
+    int buf = 0;
+    forces(st0, ct0, buf);
+    const float crr = c.crr;
+    auto stage_pass = [&](auto stage_c, long long step) {
+        constexpr int stage = decltype(stage_c)::value;
+        const float4* pA = rc_lds + buf * pstride;
+        const float4* pB = pA + n;
+        const float* pz = reinterpret_cast<const float*>(pB + n);
+        float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+        if (t < n) {
+            const float4 Ai = pA[t];
+            const float4 Bi = pB[t];
+            const int dt = t >> 1;
+            float px = 0.f, py = 0.f, pzz = 0.f;
+            int cnt = 0;
+            /* four sources at a time, their LDS loads issued together; the
+             * own dumbbell and the sources past the end are masked by a zero
+             * 1/r (their term is then exactly zero) */
+            for (int j0 = sub; j0 < n; j0 += 4 * split) {
+                float4 Aj[4], Bj[4];
+                float Fz[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * split;
+                    const int jj = j < n ? j : t;
+                    Aj[u] = pA[jj];
+                    Bj[u] = pB[jj];
+                    Fz[u] = pz[jj];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * split;
+                    float rx, ry, rz;
+                    if (SPLIT) {
+                        rx = (Ai.x - Aj[u].x) + (Bi.x - Bj[u].x);
+                        ry = (Ai.y - Aj[u].y) + (Bi.y - Bj[u].y);
+                        rz = (Ai.z - Aj[u].z) + (Bi.z - Bj[u].z);
+                    } else {
+                        rx = Ai.x - Aj[u].x;
+                        ry = Ai.y - Aj[u].y;
+                        rz = Ai.z - Aj[u].z;
+                    }
+                    const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                    float ir = __builtin_amdgcn_rsqf(r2);
+                    if (j >= n || (j >> 1) == dt) ir = 0.f;
+                    pair_term<RPY>(ir, rx, ry, rz, Aj[u].w, Bj[u].w, Fz[u], crr, px, py, pzz);
+                }
+                cnt += 4;
+                if (cnt == 32) {
+                    two_sum_acc(ax, bx, px);
+                    two_sum_acc(ay, by, py);
+                    two_sum_acc(az, bz, pzz);
+                    px = py = pzz = 0.f;
+                    cnt = 0;
+                }
+            }
+            two_sum_acc(ax, bx, px);
+            two_sum_acc(ay, by, py);
+            two_sum_acc(az, bz, pzz);
+        }
+        float v[6] = {ax, bx, ay, by, az, bz};
+        if (split > 1) combine_level_dpp<0xB1>(v);
+        if (split > 2) combine_level_dpp<0x4E>(v);
+        for (int sh = 4; sh < split; sh *= 2) combine_level_shfl(v, sh);
+        if (own) {
+            const double acc[3] = {(double)v[0] + (double)v[1], (double)v[2] + (double)v[3],
+                                   (double)v[4] + (double)v[5]};
+            for (int a = 0; a < 3; ++a) {
+                const double k = u0[a] + c.co * acc[a];
+                if (!isfinite(k)) bad = 1;
+                const double nz = INTEG == 2 ? c.g * gauss_component(c.seed, ioff + t, step, a) : 0.0;
+                y[a] = res_update(c, INTEG == 0 ? 0 : 1, stage, NST, k, x[a], r[a], nz);
+            }
+        }
+        buf ^= 1;
+        forces(tb[2 * stage], tb[2 * stage + 1], buf);
+    };
+    for (int sn = 0; sn < nsteps; ++sn) {
+        const long long step = step0 + sn;
+        row = row + 1 == d.ring ? 0 : row + 1;
+        if (own)
+            for (int q = 0; q < 8; ++q) nb[q] = d.tab[row * 8 + q];
+        stage_pass(std::integral_constant<int, 0>{}, step);
+        stage_pass(std::integral_constant<int, 1>{}, step);
+        if constexpr (NST == 4) {
+            stage_pass(std::integral_constant<int, 2>{}, step);
+            stage_pass(std::integral_constant<int, 3>{}, step);
+        }
+        for (int q = 0; q < 8; ++q) tb[q] = nb[q];
+    }
+    if (own)
+        for (int a = 0; a < 3; ++a) d.X[a * N + ioff + t] = x[a];
     if (__syncthreads_or(bad) && tid == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
 }
 
@@ -2081,6 +2180,33 @@ static hipError_t go_stream(const Dev& d, const Epi& e, hipStream_t s, const Tim
     return hipGetLastError();
 }
 
+typedef void (*ResidentKernel)(Dev, Epi, long long, int, double, double);
+
+template <int SPLIT, int RPY, int T>
+static ResidentKernel resident_c_integ(int integ) {
+    if (integ == 0) return k_resident_c<SPLIT, RPY, T, 0>;
+    if (integ == 1) return k_resident_c<SPLIT, RPY, T, 1>;
+    return k_resident_c<SPLIT, RPY, T, 2>;
+}
+
+template <int T>
+static ResidentKernel resident_c_threads(int hilo, int rpy, int integ) {
+    if (hilo) return rpy ? resident_c_integ<1, 1, T>(integ) : resident_c_integ<1, 0, T>(integ);
+    return rpy ? resident_c_integ<0, 1, T>(integ) : resident_c_integ<0, 0, T>(integ);
+}
+
+/* the FP32C resident kernel for hi/lo positions or not, RPY or not, T
+ * threads (64, 128, 256 or 512) and integrator integ (0 RK4, 1 Heun, 2 Heun
+ * with noise) */
+static ResidentKernel resident_c_kernel(int hilo, int rpy, int T, int integ) {
+    switch (T) {
+        case 64: return resident_c_threads<64>(hilo, rpy, integ);
+        case 128: return resident_c_threads<128>(hilo, rpy, integ);
+        case 256: return resident_c_threads<256>(hilo, rpy, integ);
+        default: return resident_c_threads<512>(hilo, rpy, integ);
+    }
+}
+
 hipError_t prepare_fused() {
     const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_stream<0, 0, FT_I>),
                              reinterpret_cast<const void*>(&k_stage_stream<0, 1, FT_I>),
@@ -2105,13 +2231,11 @@ hipError_t prepare_fused() {
             return err;
         }
     }
-    const void* resident[] = {
-        reinterpret_cast<const void*>(&k_resident<1, 0, 0, 64>), reinterpret_cast<const void*>(&k_resident<1, 0, 1, 64>),
-        reinterpret_cast<const void*>(&k_resident<0, 0, 0, 64>), reinterpret_cast<const void*>(&k_resident<0, 0, 1, 64>),
-        reinterpret_cast<const void*>(&k_resident<0, 1, 0, 64>), reinterpret_cast<const void*>(&k_resident<0, 1, 1, 64>),
-        reinterpret_cast<const void*>(&k_resident<1, 0, 0, 256>), reinterpret_cast<const void*>(&k_resident<1, 0, 1, 256>),
-        reinterpret_cast<const void*>(&k_resident<0, 0, 0, 256>), reinterpret_cast<const void*>(&k_resident<0, 0, 1, 256>),
-        reinterpret_cast<const void*>(&k_resident<0, 1, 0, 256>), reinterpret_cast<const void*>(&k_resident<0, 1, 1, 256>)};
+    const void* resident[50] = {reinterpret_cast<const void*>(&k_resident<0>),
+                                reinterpret_cast<const void*>(&k_resident<1>)};
+    for (int q = 0; q < 48; ++q)
+        resident[2 + q] = reinterpret_cast<const void*>(
+            resident_c_kernel(q & 1, (q >> 1) & 1, 64 << ((q >> 2) & 3), q >> 4));
     for (const void* k : resident) {
         hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, RES_LDS_MAX);
         if (err != hipSuccess) {
@@ -2130,24 +2254,12 @@ hipError_t launch_resident(const Dev& d, const Epi& e, int hilo, int maxNb, long
     if (maxNb > (p64 ? RES_MAX64 : RES_MAX32)) return hipErrorInvalidValue;
     const size_t lds = (size_t)resident_lds_bytes(maxNb, p64, rpy);
     if (lds > (size_t)RES_LDS_MAX) return hipErrorInvalidValue;
-    /* one wave per system up to 32 spheres, four above */
     const int T = resident_threads(maxNb, p64);
-    void (*kern)(Dev, Epi, long long, int, double, double);
-    if (T == 64) {
-        if (p64)
-            kern = rpy ? k_resident<1, 0, 1, 64> : k_resident<1, 0, 0, 64>;
-        else if (hilo)
-            kern = rpy ? k_resident<0, 1, 1, 64> : k_resident<0, 1, 0, 64>;
-        else
-            kern = rpy ? k_resident<0, 0, 1, 64> : k_resident<0, 0, 0, 64>;
-    } else {
-        if (p64)
-            kern = rpy ? k_resident<1, 0, 1, 256> : k_resident<1, 0, 0, 256>;
-        else if (hilo)
-            kern = rpy ? k_resident<0, 1, 1, 256> : k_resident<0, 1, 0, 256>;
-        else
-            kern = rpy ? k_resident<0, 0, 1, 256> : k_resident<0, 0, 0, 256>;
-    }
+    ResidentKernel kern;
+    if (p64)
+        kern = rpy ? k_resident<1> : k_resident<0>;
+    else
+        kern = resident_c_kernel(hilo, rpy, T, e.integ == 0 ? 0 : (e.c.noise ? 2 : 1));
     if (ev_start)
         hipExtLaunchKernelGGL(kern, dim3(d.nfitems), dim3(T), lds, s, ev_start, ev_stop, 0, d, e, step0, nsteps, st0,
                               ct0);

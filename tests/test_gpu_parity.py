@@ -1000,9 +1000,10 @@ def test_resident_fp64_full_n16(oracle):
 @pytest.mark.parametrize("integrator,tensor", [("rk4", "oseen"), ("heun", "oseen"), ("rk4", "rpy")])
 def test_resident_fp32c_matches_oracle(oracle, launch, integrator, tensor):
     """The resident form in FP32C on uneven systems from 1 dumbbell to 128
-    (256 spheres, one lane per target) and the paper's 27-dumbbell lattice
-    size: 300 steps against the oracle per system, relative to the
-    displacement, and within the bars of the two-kernel path."""
+    (256 spheres: 512 threads, two lanes per target; a 2-sphere system
+    there has 32 lanes per target) and the paper's 27-dumbbell lattice size:
+    300 steps against the oracle per system, relative to the displacement,
+    and within the bars of the two-kernel path."""
     _torch()
     sizes = np.array([1, 27, 128, 3, 57, 8, 100], dtype=np.int32)
     ens = make_ensemble(nsys=len(sizes), sizes=sizes)
