@@ -20,6 +20,8 @@ FLAGS = [
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # roctx ranges over the stepping and mobility calls
+    "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -99,7 +99,7 @@ struct Dev {
     int nfitems;        /* 0: one system, blocks in order */
     const long long* sys_hbase; /* [nsys] dense mode: first element of the system's tensor */
     const double* tab;  /* [ring][8] (sin, cos) of omega*t per epilogue stage */
-    int ring;           /* entries in tab */
+    int ring;           /* entries in tab, a power of two (rows are step & (ring - 1)) */
     int Ntot, Stot, nsys, nitems;
     int ncomp; /* partial-sum components per sphere: 3, or 6 for FP64 with RPY
                   (Oseen and correction summed apart, as the plain sum does) */
@@ -132,7 +132,7 @@ __device__ __forceinline__ void advance_slots(const Dev& d, const Epi& e) {
         step = d.ctl->slot[1];
     }
     if (e.stage == e.nst - 1) d.ctl->slot[0] = step + 1;
-    const long long row = step % d.ring;
+    const long long row = step & (d.ring - 1);
     d.ctl->trig[e.stage][0] = d.tab[row * 8 + 2 * e.stage];
     d.ctl->trig[e.stage][1] = d.tab[row * 8 + 2 * e.stage + 1];
 }

@@ -907,7 +907,7 @@ __global__ __launch_bounds__(64 * NW) void k_stage_fused(Dev d, Epi e) {
     double st = 0.0, ct = 0.0;
     double2 tp = make_double2(0.0, 0.0);
     if (tid < ni) {
-        const long long row = step % d.ring;
+        const long long row = step & (d.ring - 1);
         st = d.tab[row * 8 + 2 * e.stage];
         ct = d.tab[row * 8 + 2 * e.stage + 1];
         tp = d.phitrig[(i0 >> 1) + (tid >> 1)];
@@ -1103,7 +1103,7 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
     double st = 0.0, ct = 0.0;
     double2 tp = make_double2(0.0, 0.0);
     if (tid < ni) {
-        const long long row = step % d.ring;
+        const long long row = step & (d.ring - 1);
         st = d.tab[row * 8 + 2 * e.stage];
         ct = d.tab[row * 8 + 2 * e.stage + 1];
         tp = d.phitrig[(i0 >> 1) + (tid >> 1)];
@@ -1300,7 +1300,7 @@ __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
     double st = 0.0, ct = 0.0;
     double2 tp = make_double2(0.0, 0.0);
     if (tid < ni) {
-        const long long row = step % d.ring;
+        const long long row = step & (d.ring - 1);
         st = d.tab[row * 8 + 2 * e.stage];
         ct = d.tab[row * 8 + 2 * e.stage + 1];
         tp = d.phitrig[(i0 >> 1) + (tid >> 1)];
@@ -1740,13 +1740,13 @@ __global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step
     double tb[8], nb[8];
     for (int q = 0; q < 8; ++q) tb[q] = nb[q] = 0.0;
     if (tid < n)
-        for (int q = 0; q < 8; ++q) tb[q] = d.tab[(step0 % d.ring) * 8 + q];
+        for (int q = 0; q < 8; ++q) tb[q] = d.tab[(step0 & (d.ring - 1)) * 8 + q];
     forces(st0, ct0);
 
     for (int sn = 0; sn < nsteps; ++sn) {
         const long long step = step0 + sn;
         if (tid < n) {
-            const long long nrow = (step + 1) % d.ring;
+            const long long nrow = (step + 1) & (d.ring - 1);
             for (int q = 0; q < 8; ++q) nb[q] = d.tab[nrow * 8 + q];
         }
         for (int stage = 0; stage < e.nst; ++stage) {
@@ -1894,7 +1894,7 @@ __global__ __launch_bounds__(T) void k_resident_c(Dev d, Epi e, long long step0,
     /* the step table's row index, held in a vector register so that its
      * loads are vector loads, which the LDS waits and barriers do not wait
      * for (a scalar load would be waited for by every LDS wait) */
-    int row = (int)(step0 % d.ring);
+    int row = (int)(step0 & (d.ring - 1));
     asm volatile("" : "+v"(row));
     if (own) {
         for (int a = 0; a < 3; ++a) x[a] = y[a] = d.X[a * N + ioff + t];

@@ -5,6 +5,7 @@
  */
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -31,6 +32,7 @@ constexpr int kTabSteps = 4096;          /* steps per table chunk */
 constexpr int kGraphSteps[] = {16, 4, 1};
 constexpr int kGraphs = 3;
 constexpr int kRing = 2 * kTabSteps;     /* table entries (two chunks) */
+static_assert((kRing & (kRing - 1)) == 0, "the kernels take table rows as step & (ring - 1)");
 
 /* message of the last failure of a context-free call on this thread
  * (ad_create, ad_mobility_apply_static); a fixed buffer, so that setting it
@@ -780,6 +782,17 @@ static int read_flag(ad_ctx* c, hipStream_t st) {
 
 /* ------------------------------------------------------------ ABI */
 
+/* A roctx range over a stepping or mobility call: the host span of the call
+ * (its launches and, for ad_run, the flag read) in `rocprofv3 --marker-trace`
+ * output, nested under the caller's own ranges. Without a profiler attached
+ * a push and a pop cost a few nanoseconds. */
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+
 extern "C" {
 
 int ad_create(const ad_params* p, int32_t nsys, const int32_t* S_per_sys, ad_ctx** out) {
@@ -954,6 +967,7 @@ int ad_get_state(ad_ctx* c, double* X, double* t0, int64_t* step, void* stream) 
 
 int ad_forces(ad_ctx* c, const double* X, double t, double* F, void* stream) {
     if (!c) return AD_EINVAL;
+    const Range range("ad_forces");
     if (!c->ws || !c->state) return fail(c, AD_ESTATE, "no state loaded (phases needed)");
     if (!X || !F) return fail(c, AD_EINVAL, "null X or F");
     if (!isfinite(t)) return fail(c, AD_EINVAL, "t must be finite");
@@ -965,6 +979,7 @@ int ad_forces(ad_ctx* c, const double* X, double t, double* F, void* stream) {
 
 int ad_mobility_apply(ad_ctx* c, const double* X, const double* F, double* u, void* stream) {
     if (!c) return AD_EINVAL;
+    const Range range("ad_mobility_apply");
     if (!c->ws) return fail(c, AD_ESTATE, "no workspace bound");
     if (!X || !F || !u) return fail(c, AD_EINVAL, "null X, F or u");
     hipStream_t st = as_stream(stream);
@@ -984,12 +999,14 @@ int ad_mobility_apply(ad_ctx* c, const double* X, const double* F, double* u, vo
 
 int ad_step(ad_ctx* c, int64_t nsteps, void* stream) {
     if (!c) return AD_EINVAL;
+    const Range range("ad_step");
     return advance(c, nsteps, 0, nullptr, nullptr, as_stream(stream));
 }
 
 int ad_run(ad_ctx* c, int64_t nsteps, int32_t record_every, double* centres, double* com, void* stream) {
     if (!c) return AD_EINVAL;
     if (record_every < 0) return fail(c, AD_EINVAL, "record_every must be >= 0");
+    const Range range("ad_run");
     hipStream_t st = as_stream(stream);
     int rc = advance(c, nsteps, record_every, centres, com, st);
     if (rc != AD_OK) return rc;

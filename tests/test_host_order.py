@@ -1,6 +1,7 @@
 """The XCD-aware order of the fused stages' work lists (host logic of the
-runtime, paper_1004_1932_amd/csrc/ad_order.h), compiled with g++ on its own:
-a permutation of the input; with many systems every system on one XCD
+runtime, paper_1004_1932_amd/csrc/ad_order.h), compiled with g++ on its own,
+plain and under AddressSanitizer and UndefinedBehaviorSanitizer: a
+permutation of the input; with many systems every system on one XCD
 (position mod 8) and the XCDs' pair work balanced; with few systems the
 input order."""
 import json
@@ -55,14 +56,18 @@ int main() {
 """
 
 
-@pytest.fixture(scope="module")
-def results(tmp_path_factory):
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+@pytest.fixture(scope="module", params=["plain", "sanitized"])
+def results(request, tmp_path_factory):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ is not available")
     d = tmp_path_factory.mktemp("order")
     (d / "t.cpp").write_text(PROGRAM)
-    subprocess.run([gxx, "-O2", "-std=c++17", "-I", str(ROOT / "paper_1004_1932_amd" / "csrc"), str(d / "t.cpp"),
+    flags = SANITIZE if request.param == "sanitized" else ["-O2"]
+    subprocess.run([gxx, *flags, "-std=c++17", "-I", str(ROOT / "paper_1004_1932_amd" / "csrc"), str(d / "t.cpp"),
                     "-o", str(d / "t")], check=True)
     out = subprocess.run([str(d / "t")], check=True, capture_output=True, text=True).stdout
     return {r["nsys"]: r for r in map(json.loads, out.splitlines())}
