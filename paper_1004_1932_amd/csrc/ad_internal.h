@@ -253,7 +253,7 @@ constexpr int RES_MAX64 = 128;
 constexpr int RES_MAX32 = 256;
 /* FP64 term-matrix budget per column chunk */
 constexpr int RES_TERM_BYTES = 64 * 1024;
-/* dynamic LDS a resident work-group may use (the largest need is 78 KiB:
+/* dynamic LDS a resident work-group may use (the largest need is 84 KiB:
  * 128 FP64 spheres with RPY); the kernels also hold a little static LDS */
 constexpr int RES_LDS_MAX = 96 * 1024;
 /* source columns of one FP64 term-matrix chunk for a system of n spheres */
@@ -263,6 +263,8 @@ __host__ __device__ inline int resident_cols(int n, int rpy) {
     if (cc < 1) cc = 1;
     return cc < n ? cc : n;
 }
+/* LDS row stride (doubles) of an FP64 term chunk of cc columns: odd */
+__host__ __device__ inline int resident_col_stride(int cc) { return cc | 1; }
 /* float4 entries of one FP32C resident pack buffer: A = (hi.xyz, Fx) and
  * B = (lo.xyz, Fy) per sphere, then Fz per sphere */
 __host__ __device__ inline int resident_pack_f4(int n) { return 2 * n + (n + 3) / 4; }
@@ -273,7 +275,7 @@ __host__ __device__ inline int resident_pack_f4(int n) { return 2 * n + (n + 3) 
 __host__ __device__ inline int resident_lds_bytes(int n, int p64, int rpy) {
     if (!p64) return 2 * resident_pack_f4(n) * 16;
     const int b = (3 * n * (5 + (rpy ? 1 : 0)) * 8 + 15) / 16 * 16;
-    return b + resident_cols(n, rpy) * n * 24 * (rpy ? 2 : 1);
+    return b + resident_col_stride(resident_cols(n, rpy)) * n * 24 * (rpy ? 2 : 1);
 }
 /* threads of a resident work-group: FP64 RES_T (its term evaluations are
  * long dependent chains, best spread over the four SIMDs); FP32C one wave up

@@ -1669,144 +1669,6 @@ __device__ __forceinline__ double res_update(const Coef& c, int integ, int stage
  * (st0, ct0) = (sin, cos)(omega t) of step step0, and every later stage's
  * at the step table's row, the next step's row loaded while a step runs. */
 
-/* FP64 (the plain sum, bitwise that of the sequential oracle): X, R, Y, F
- * and the pair sums in LDS. Per stage: the terms of a chunk of source
- * columns are evaluated in parallel into an LDS matrix, then every
- * (target, component) thread adds its row of the chunk in ascending j;
- * the closing (velocity, stage update, next stage position) takes one
- * thread per sphere component, the next stage's spring forces one thread
- * per sphere (both threads of a dumbbell evaluate them from the same
- * inputs, so they agree bit for bit). */
-template <int RPY>
-__global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step0, int nsteps, double st0,
-                                                    double ct0) {
-    constexpr int T = RES_T;
-    extern __shared__ double res_lds[];
-    const Item it = d.fitems[blockIdx.x];
-    const int n = it.Nb, ioff = it.ioff;
-    const int N = d.Ntot;
-    const int tid = threadIdx.x;
-    const Coef& c = e.c;
-    double* X = res_lds;
-    double* R = X + 3 * n;
-    double* Y = R + 3 * n;
-    double* F = Y + 3 * n;
-    double* Acc = F + 3 * n; /* pair sums [3n] (RPY: then [3n]) */
-    double* Bcc = Acc + 3 * n;
-    double* Tm = reinterpret_cast<double*>(reinterpret_cast<char*>(res_lds) +
-                                           ((3 * n * (5 + (RPY ? 1 : 0))) * 8 + 15) / 16 * 16);
-    const int cc = resident_cols(n, RPY);
-    double* Tb = Tm + 3 * n * cc; /* RPY corrections of the chunk */
-
-    for (int q = tid; q < 3 * n; q += T) {
-        const int a = q / n, i = q - a * n;
-        const double v = d.X[a * N + ioff + i];
-        X[q] = v;
-        Y[q] = v;
-    }
-    double2 tp = make_double2(0.0, 0.0);
-    if (tid < n) tp = d.phitrig[(ioff >> 1) + (tid >> 1)];
-    int bad = 0;
-    __syncthreads();
-
-    auto closing = [&](int stage, long long step) {
-        for (int q = tid; q < 3 * n; q += T) {
-            const int i = q / 3, a = q - 3 * i, o = a * n + i;
-            double k = c.cs * F[o] + c.co * Acc[q];
-            if (RPY) k = k + c.cr * Bcc[q];
-            if (!isfinite(k)) bad = 1;
-            const double nz = (e.integ == 1 && c.noise) ? c.g * gauss_component(c.seed, ioff + i, step, a) : 0.0;
-            double x = X[o], r = R[o];
-            Y[o] = res_update(c, e.integ, stage, e.nst, k, x, r, nz);
-            X[o] = x;
-            R[o] = r;
-        }
-        __syncthreads();
-    };
-    auto forces = [&](double st, double ct) {
-        if (tid < n) {
-            const int i0 = tid & ~1;
-            double y0[3], y1[3], f0[3], f1[3];
-            for (int a = 0; a < 3; ++a) {
-                y0[a] = Y[a * n + i0];
-                y1[a] = Y[a * n + i0 + 1];
-            }
-            spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
-            const double* f = (tid & 1) ? f1 : f0;
-            for (int a = 0; a < 3; ++a) F[a * n + tid] = f[a];
-        }
-        __syncthreads();
-    };
-    double tb[8], nb[8];
-    for (int q = 0; q < 8; ++q) tb[q] = nb[q] = 0.0;
-    if (tid < n)
-        for (int q = 0; q < 8; ++q) tb[q] = d.tab[(step0 & (d.ring - 1)) * 8 + q];
-    forces(st0, ct0);
-
-    for (int sn = 0; sn < nsteps; ++sn) {
-        const long long step = step0 + sn;
-        if (tid < n) {
-            const long long nrow = (step + 1) & (d.ring - 1);
-            for (int q = 0; q < 8; ++q) nb[q] = d.tab[nrow * 8 + q];
-        }
-        for (int stage = 0; stage < e.nst; ++stage) {
-            for (int j0 = 0; j0 < n; j0 += cc) {
-                const int nc = min(cc, n - j0);
-                for (int p = tid; p < n * nc; p += T) {
-                    const int i = p / nc, jj = p - i * nc, j = j0 + jj;
-                    double* t = Tm + (i * cc + jj) * 3;
-                    double* tq = Tb + (i * cc + jj) * 3;
-                    const double r[3] = {Y[i] - Y[j], Y[n + i] - Y[n + j], Y[2 * n + i] - Y[2 * n + j]};
-                    const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
-                    if (j == i || r2 == 0.0) {
-                        if (j != i) bad = 1;
-                        t[0] = t[1] = t[2] = 0.0;
-                        if (RPY) tq[0] = tq[1] = tq[2] = 0.0;
-                        continue;
-                    }
-                    const double Fj[3] = {F[j], F[n + j], F[2 * n + j]};
-                    oseen_term64(r, Fj, t);
-                    if (RPY) rpy_term64(r, Fj, tq);
-                }
-                __syncthreads();
-                for (int q = tid; q < 3 * n; q += T) {
-                    const int i = q / 3, a = q - 3 * i;
-                    double acc = (j0 == 0) ? 0.0 : Acc[q];
-                    double bcc = (RPY && j0 > 0) ? Bcc[q] : 0.0;
-                    /* the row in ascending j, its LDS loads eight at a time */
-                    for (int jb = 0; jb < nc; jb += 8) {
-                        double v[8], w[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int jj = jb + u < nc ? jb + u : 0;
-                            v[u] = Tm[(i * cc + jj) * 3 + a];
-                            w[u] = RPY ? Tb[(i * cc + jj) * 3 + a] : 0.0;
-                        }
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int jj = jb + u;
-                            if (jj >= nc || j0 + jj == i) continue;
-                            acc = acc + v[u];
-                            if (RPY) bcc = bcc + w[u];
-                        }
-                    }
-                    Acc[q] = acc;
-                    if (RPY) Bcc[q] = bcc;
-                }
-                __syncthreads();
-            }
-            closing(stage, step);
-            forces(tb[2 * stage], tb[2 * stage + 1]);
-        }
-        for (int q = 0; q < 8; ++q) tb[q] = nb[q];
-    }
-    for (int q = tid; q < 3 * n; q += T) {
-        const int a = q / n, i = q - a * n;
-        d.X[a * N + ioff + i] = X[q];
-    }
-    if (__syncthreads_or(bad) && tid == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
-}
-
 /* One level of the fixed butterfly that combines the (hi, lo) sums
  * v = (hi.x, lo.x, hi.y, lo.y, hi.z, lo.z) of adjacent lanes: each lane takes
  * the sums of lane (itself xor distance) and adds them in with TwoSum. */
@@ -1849,6 +1711,168 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+/* FP64 (the plain sum, bitwise that of the sequential oracle): X, R, Y, F
+ * and the pair sums in LDS. Per stage: the terms of a chunk of source
+ * columns are evaluated in parallel into an LDS matrix, then every
+ * (target, component) thread adds its row of the chunk in ascending j;
+ * the closing (velocity, stage update, next stage position) takes one
+ * thread per sphere component, the next stage's spring forces one thread
+ * per sphere (both threads of a dumbbell evaluate them from the same
+ * inputs, so they agree bit for bit). */
+template <int RPY, int INTEG>
+__global__ __launch_bounds__(RES_T) void k_resident(Dev d, Epi e, long long step0, int nsteps, double st0,
+                                                    double ct0) {
+    /* INTEG: 0 RK4, 1 Heun, 2 Heun with noise; the stages are unrolled, so
+     * every stage's update and table entries are fixed at compile time */
+    constexpr int NST = INTEG == 0 ? 4 : 2;
+    constexpr int T = RES_T;
+    extern __shared__ double res_lds[];
+    const Item it = d.fitems[blockIdx.x];
+    const int n = it.Nb, ioff = it.ioff;
+    const int N = d.Ntot;
+    const int tid = threadIdx.x;
+    const Coef& c = e.c;
+    double* X = res_lds;
+    double* R = X + 3 * n;
+    double* Y = R + 3 * n;
+    double* F = Y + 3 * n;
+    double* Acc = F + 3 * n; /* pair sums [3][n] (RPY: then [3][n]) */
+    double* Bcc = Acc + 3 * n;
+    double* Tm = reinterpret_cast<double*>(reinterpret_cast<char*>(res_lds) +
+                                           ((3 * n * (5 + (RPY ? 1 : 0))) * 8 + 15) / 16 * 16);
+    const int cc = resident_cols(n, RPY);
+    /* the chunk's terms [3][n][cs]: a row of cs (odd) doubles, so that the
+     * threads of consecutive targets read distinct LDS banks */
+    const int cs = resident_col_stride(cc);
+    double* Tb = Tm + 3 * n * cs; /* RPY corrections of the chunk */
+
+    for (int q = tid; q < 3 * n; q += T) {
+        const int a = q / n, i = q - a * n;
+        const double v = d.X[a * N + ioff + i];
+        X[q] = v;
+        Y[q] = v;
+    }
+    double2 tp = make_double2(0.0, 0.0);
+    if (tid < n) tp = d.phitrig[(ioff >> 1) + (tid >> 1)];
+    int bad = 0;
+    /* the step table's row index in a vector register: its loads are then
+     * vector loads, which the LDS-only barriers do not wait for */
+    int row = (int)(step0 & (d.ring - 1));
+    asm volatile("" : "+v"(row));
+    double tb[8], nb[8];
+    for (int q = 0; q < 8; ++q) tb[q] = nb[q] = 0.0;
+    if (tid < n)
+        for (int q = 0; q < 8; ++q) tb[q] = d.tab[row * 8 + q];
+    __syncthreads();
+
+    auto forces = [&](double st, double ct) {
+        if (tid < n) {
+            const int i0 = tid & ~1;
+            double y0[3], y1[3], f0[3], f1[3];
+            for (int a = 0; a < 3; ++a) {
+                y0[a] = Y[a * n + i0];
+                y1[a] = Y[a * n + i0 + 1];
+            }
+            spring_forces(c, y0, y1, tp.x, tp.y, st, ct, f0, f1);
+            for (int a = 0; a < 3; ++a) F[a * n + tid] = (tid & 1) ? f1[a] : f0[a];
+        }
+        lds_barrier();
+    };
+    forces(st0, ct0);
+
+    auto stage_pass = [&](auto stage_c, long long step) {
+        constexpr int stage = decltype(stage_c)::value;
+        for (int j0 = 0; j0 < n; j0 += cc) {
+            const int nc = min(cc, n - j0);
+            for (int p = tid; p < n * nc; p += T) {
+                const int i = p / nc, jj = p - i * nc, j = j0 + jj;
+                const int o = i * cs + jj;
+                const int m = n * cs; /* component stride */
+                const double r[3] = {Y[i] - Y[j], Y[n + i] - Y[n + j], Y[2 * n + i] - Y[2 * n + j]};
+                const double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+                double t[3] = {0.0, 0.0, 0.0}, tq[3] = {0.0, 0.0, 0.0};
+                if (j != i && r2 != 0.0) {
+                    const double Fj[3] = {F[j], F[n + j], F[2 * n + j]};
+                    oseen_term64(r, Fj, t);
+                    if (RPY) rpy_term64(r, Fj, tq);
+                } else if (j != i) {
+                    bad = 1;
+                }
+                for (int a = 0; a < 3; ++a) {
+                    Tm[a * m + o] = t[a];
+                    if (RPY) Tb[a * m + o] = tq[a];
+                }
+            }
+            lds_barrier();
+            /* one thread per (component, target): the target's row of the
+             * chunk in ascending j, its LDS loads eight at a time */
+            for (int q = tid; q < 3 * n; q += T) {
+                const double* row = Tm + q * cs; /* component q / n of target q mod n */
+                const double* rowb = Tb + q * cs;
+                /* The self term was stored as +0.0 and is added like the
+                 * others: a sum that starts at +0.0 is never -0.0 in
+                 * round-to-nearest, so adding +0.0 leaves it unchanged, bit
+                 * for bit the sum that skips j = i. */
+                double acc = (j0 == 0) ? 0.0 : Acc[q];
+                double bcc = (RPY && j0 > 0) ? Bcc[q] : 0.0;
+                int jb = 0;
+                for (; jb + 8 <= nc; jb += 8) {
+                    double v[8], w[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        v[u] = row[jb + u];
+                        w[u] = RPY ? rowb[jb + u] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        acc = acc + v[u];
+                        if (RPY) bcc = bcc + w[u];
+                    }
+                }
+                for (; jb < nc; ++jb) {
+                    acc = acc + row[jb];
+                    if (RPY) bcc = bcc + rowb[jb];
+                }
+                Acc[q] = acc;
+                if (RPY) Bcc[q] = bcc;
+            }
+            lds_barrier();
+        }
+        /* closing, one thread per (component, sphere) */
+        for (int q = tid; q < 3 * n; q += T) {
+            const int a = (q >= n) + (q >= 2 * n), i = q - a * n, o = q;
+            double k = c.cs * F[o] + c.co * Acc[o];
+            if (RPY) k = k + c.cr * Bcc[o];
+            if (!isfinite(k)) bad = 1;
+            const double nz = INTEG == 2 ? c.g * gauss_component(c.seed, ioff + i, step, a) : 0.0;
+            double x = X[o], r = R[o];
+            Y[o] = res_update(c, INTEG == 0 ? 0 : 1, stage, NST, k, x, r, nz);
+            X[o] = x;
+            R[o] = r;
+        }
+        lds_barrier();
+        forces(tb[2 * stage], tb[2 * stage + 1]);
+    };
+    for (int sn = 0; sn < nsteps; ++sn) {
+        const long long step = step0 + sn;
+        row = row + 1 == d.ring ? 0 : row + 1;
+        if (tid < n)
+            for (int q = 0; q < 8; ++q) nb[q] = d.tab[row * 8 + q];
+        stage_pass(std::integral_constant<int, 0>{}, step);
+        stage_pass(std::integral_constant<int, 1>{}, step);
+        if constexpr (NST == 4) {
+            stage_pass(std::integral_constant<int, 2>{}, step);
+            stage_pass(std::integral_constant<int, 3>{}, step);
+        }
+        for (int q = 0; q < 8; ++q) tb[q] = nb[q];
+    }
+    for (int q = tid; q < 3 * n; q += T) {
+        const int a = q / n, i = q - a * n;
+        d.X[a * N + ioff + i] = X[q];
+    }
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
 }
 
 /* FP32C: the state in registers, only the float pack in LDS. Target sphere
@@ -2231,10 +2255,12 @@ hipError_t prepare_fused() {
             return err;
         }
     }
-    const void* resident[50] = {reinterpret_cast<const void*>(&k_resident<0>),
-                                reinterpret_cast<const void*>(&k_resident<1>)};
+    const void* resident[54] = {
+        reinterpret_cast<const void*>(&k_resident<0, 0>), reinterpret_cast<const void*>(&k_resident<1, 0>),
+        reinterpret_cast<const void*>(&k_resident<0, 1>), reinterpret_cast<const void*>(&k_resident<1, 1>),
+        reinterpret_cast<const void*>(&k_resident<0, 2>), reinterpret_cast<const void*>(&k_resident<1, 2>)};
     for (int q = 0; q < 48; ++q)
-        resident[2 + q] = reinterpret_cast<const void*>(
+        resident[6 + q] = reinterpret_cast<const void*>(
             resident_c_kernel(q & 1, (q >> 1) & 1, 64 << ((q >> 2) & 3), q >> 4));
     for (const void* k : resident) {
         hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, RES_LDS_MAX);
@@ -2256,10 +2282,13 @@ hipError_t launch_resident(const Dev& d, const Epi& e, int hilo, int maxNb, long
     if (lds > (size_t)RES_LDS_MAX) return hipErrorInvalidValue;
     const int T = resident_threads(maxNb, p64);
     ResidentKernel kern;
+    const int integ = e.integ == 0 ? 0 : (e.c.noise ? 2 : 1);
     if (p64)
-        kern = rpy ? k_resident<1> : k_resident<0>;
+        kern = integ == 0 ? (rpy ? k_resident<1, 0> : k_resident<0, 0>)
+               : integ == 1 ? (rpy ? k_resident<1, 1> : k_resident<0, 1>)
+                            : (rpy ? k_resident<1, 2> : k_resident<0, 2>);
     else
-        kern = resident_c_kernel(hilo, rpy, T, e.integ == 0 ? 0 : (e.c.noise ? 2 : 1));
+        kern = resident_c_kernel(hilo, rpy, T, integ);
     if (ev_start)
         hipExtLaunchKernelGGL(kern, dim3(d.nfitems), dim3(T), lds, s, ev_start, ev_stop, 0, d, e, step0, nsteps, st0,
                               ct0);
