@@ -94,7 +94,7 @@ def candidates(N: int, ensemble: bool):
                 out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=3))
         else:
             out.append(dict(wg=256, wj=4, ipl=1, jchunk=256, posmode=posmode, fused=1))
-            if N >= 1024:  # the streamed form pads every system to 1024 sources
+            if N >= 256:  # the streamed form pads every system to 1024 sources
                 out.append(dict(wg=256, wj=4, ipl=1, jchunk=256, posmode=posmode, fused=3))
         if N <= 256:  # the resident form: one work-group per system for a run of steps
             out.append(dict(wg=64, wj=1, ipl=1, jchunk=128, posmode=posmode, fused=4))

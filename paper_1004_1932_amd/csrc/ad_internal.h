@@ -234,11 +234,21 @@ __host__ __device__ inline int fused_wide_lds_bytes(int n, int split) {
     const int red = 4 * FW_I * 6 * 4 + FW_I * 3 * 8 + 16;
     return b > red ? b : red;
 }
-/* target spheres per work-group of the streamed fused stage */
+/* the most target spheres per work-group of the streamed fused stage */
 constexpr int FT_I = 16;
+/* target spheres per work-group of the streamed fused stage for Ntot
+ * spheres in all: 4, 8 or 16, about Ntot / 256, so that the launch holds
+ * about one work-group per compute unit (every work-group reads every source
+ * of its system: two on a compute unit double that traffic; fewer than 256
+ * leave compute units idle) */
+__host__ __device__ inline int stream_targets(int Ntot) {
+    int ti = 4;
+    while (ti < FT_I && 2 * 256 * ti <= Ntot) ti *= 2;
+    return ti;
+}
 /* LDS bytes of a streamed fused work-group: 16 waves x 2 slots x 64 source
- * entries, followed by the combination area (16 waves x 16 targets x 6
- * floats, 16 x 3 stage positions) */
+ * entries, followed by the combination area (16 waves x at most 16 targets
+ * x 6 floats, 16 x 3 stage positions) */
 __host__ __device__ inline int fused_stream_lds_bytes(int split) {
     const int b = 16 * 2 * 64 * (split ? 36 : 24);
     const int red = 16 * 16 * 6 * 4 + 16 * 3 * 8;

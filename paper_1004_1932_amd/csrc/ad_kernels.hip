@@ -1205,9 +1205,11 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
 }
 
 /* Streamed form of the fused stage (ad_launch.fused = 3). The work-group of
- * 16 waves owns TI = FT_I = 16 target spheres, like k_stage_fused (TI = 8,
- * which lets two work-groups share a compute unit, measured slower at
- * N = 4096: every work-group reads every source). Each of its source splits
+ * 16 waves owns TI target spheres, TI = 4, 8 or 16 chosen by stream_targets
+ * so that a launch holds about one work-group per compute unit (at
+ * N = 4096, TI = 8 puts two work-groups on a compute unit and measured 22 %
+ * slower, since every work-group reads every source; at N = 2048, TI = 16
+ * leaves half the compute units idle and measured 18 % slower). Each of its source splits
  * (wave w, lane group g of TI lanes) owns a contiguous range of Q sources
  * (Q a multiple of TI). A wave streams its ranges through a double-buffered LDS
  * slot of its own, TI sources per split at a time, one entry per lane: the
@@ -2195,8 +2197,10 @@ static hipError_t go_wide(const Dev& d, const Epi& e, int maxNb, hipStream_t s, 
 template <int SPLIT, int RPY>
 static hipError_t go_stream(const Dev& d, const Epi& e, hipStream_t s, const Timing& tm) {
     const int lds = fused_stream_lds_bytes(SPLIT);
-    const dim3 grid(d.nfitems ? d.nfitems : (d.Ntot + FT_I - 1) / FT_I);
-    auto kern = k_stage_stream<SPLIT, RPY, FT_I>;
+    const int ti = stream_targets(d.Ntot);
+    const dim3 grid(d.nfitems ? d.nfitems : (d.Ntot + ti - 1) / ti);
+    auto kern = ti == 16 ? k_stage_stream<SPLIT, RPY, 16>
+                : ti == 8 ? k_stage_stream<SPLIT, RPY, 8> : k_stage_stream<SPLIT, RPY, 4>;
     if (tm.start)
         hipExtLaunchKernelGGL(kern, grid, dim3(1024), lds, s, tm.start, tm.stop, 0, d, e);
     else
@@ -2232,10 +2236,18 @@ static ResidentKernel resident_c_kernel(int hilo, int rpy, int T, int integ) {
 }
 
 hipError_t prepare_fused() {
-    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_stream<0, 0, FT_I>),
-                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, FT_I>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, FT_I>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, FT_I>),
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_stream<0, 0, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 0, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 0, 4>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 4>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 4>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 4>),
                              reinterpret_cast<const void*>(&k_stage_wide<0, 0>),
                              reinterpret_cast<const void*>(&k_stage_wide<0, 1>),
                              reinterpret_cast<const void*>(&k_stage_wide<1, 0>),

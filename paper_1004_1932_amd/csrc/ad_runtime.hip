@@ -353,7 +353,7 @@ static void build_items(ad_ctx* c) {
         std::stable_sort(c->fitems.begin(), c->fitems.end(),
                          [](const Item& a, const Item& b) { return a.Nb > b.Nb; });
     } else if (((c->launch.fused == 1 || c->launch.fused == 3) && c->nsys > 1) || c->launch.fused == 2) {
-        const int blk = c->launch.fused == 2 ? ad::FW_I : c->launch.fused == 3 ? ad::FT_I : 16;
+        const int blk = c->launch.fused == 2 ? ad::FW_I : c->launch.fused == 3 ? ad::stream_targets(c->Ntot) : 16;
         for (int b = 0; b < c->nsys; ++b) {
             const int Nb = 2 * c->S[b];
             for (int i = 0; i < Nb; i += blk) {
