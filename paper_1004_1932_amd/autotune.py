@@ -63,6 +63,26 @@ def tuned_launch(S_per_sys, path: Path = TABLE):
     return None
 
 
+# the plain FP64 forms take the resident form (one work-group per system, every
+# stage of a run of steps in one launch; bitwise the same sums as the
+# two-kernel form) up to this many spheres per system: 16 spheres 4.4 us per
+# step against 34 for two kernels per stage, 64 lattices of 27 dumbbells 24
+# against 70. Past about 64 spheres its term chunks become long sequential
+# loops per thread and the two-kernel form wins.
+RESIDENT_FP64_MAX = 64
+RESIDENT_FP64 = {"ipl": 1, "jchunk": 128, "wg": 64, "wj": 1, "posmode": 0, "fused": 4}
+
+
+def tuned_launch_fp64(S_per_sys, steric: bool = False):
+    """Launch of the plain FP64 forms (AD_FP64, AD_FP64_TILED) under
+    launch="tuned": the resident form for systems of up to RESIDENT_FP64_MAX
+    spheres without steric forces, else None (the library default)."""
+    S = np.asarray(S_per_sys).reshape(-1)
+    if steric or len(S) == 0 or 2 * int(S.max()) > RESIDENT_FP64_MAX:
+        return None
+    return dict(RESIDENT_FP64)
+
+
 def candidates(N: int, ensemble: bool):
     out = []
     for posmode in (B.AD_POS_HILO, B.AD_POS_SINGLE):

@@ -303,7 +303,9 @@ class Simulator:
     def __init__(self, params, S_per_sys, precision="fp32c", integrator="rk4", device="cuda:0",
                  launch=None, graph=False, tensor="oseen", kT=0.0, seed=0):
         """launch: None (library default), a dict of ad_launch fields, or
-        "tuned" (the autotuned shape for this size bucket, if any)."""
+        "tuned": for FP32C the autotuned shape of this size bucket (if any),
+        for the plain FP64 forms the resident form up to 64 spheres per
+        system, for the dense form the library default."""
         import torch
         self.device = torch.device(device)
         self.S_per_sys = np.asarray(S_per_sys, dtype=np.int32).reshape(-1)
@@ -313,8 +315,13 @@ class Simulator:
         self._p = make_params(params, precision, integrator, tensor, kT, seed)
         self._graph = bool(graph)
         if launch == "tuned":
-            from .autotune import tuned_launch
-            launch = tuned_launch(self.S_per_sys) if self._p.precision == AD_FP32C else None
+            from .autotune import tuned_launch, tuned_launch_fp64
+            if self._p.precision == AD_FP32C:
+                launch = tuned_launch(self.S_per_sys)
+            elif self._p.precision in (AD_FP64, AD_FP64_TILED):
+                launch = tuned_launch_fp64(self.S_per_sys, steric=self._p.steric_k != 0.0)
+            else:
+                launch = None
         self.ctx = None
         self.ws = None
         self._create(launch)

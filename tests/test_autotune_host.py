@@ -60,3 +60,14 @@ def test_shipped_table_is_gated():
     for key, rec in table.items():
         assert rec["err"] <= rec["gate"] <= 5e-7, key
         assert rec["ms_per_step"] > 0 and isinstance(rec["launch"], dict), key
+
+
+def test_fp64_tuned_launch_is_resident_for_small_systems():
+    """launch="tuned" for the plain FP64 forms: the resident form for systems
+    of up to 64 spheres without steric forces, else the library default."""
+    assert A.tuned_launch_fp64([8]) == A.RESIDENT_FP64
+    assert A.tuned_launch_fp64([27] * 64)["fused"] == 4
+    assert A.tuned_launch_fp64([32, 5]) == A.RESIDENT_FP64
+    assert A.tuned_launch_fp64([33]) is None
+    assert A.tuned_launch_fp64([8], steric=True) is None
+    assert A.tuned_launch_fp64([]) is None

@@ -983,11 +983,13 @@ def test_resident_fp64_bitwise(oracle, integrator, tensor):
 
 
 def test_resident_fp64_full_n16(oracle):
-    """The plain FP64 workload in full in the resident form: 16 spheres,
-    1e4 RK4 steps, records every 1000, bitwise."""
+    """The plain FP64 workload in full in the resident form, which is what
+    launch="tuned" picks for it: 16 spheres, 1e4 RK4 steps, records every
+    1000, bitwise."""
     _torch()
     sus = make_preset("n16")
-    s = P.Simulator(sus.params, [sus.S], precision="fp64", launch=RESIDENT)
+    s = P.Simulator(sus.params, [sus.S], precision="fp64", launch="tuned")
+    assert s.launch["fused"] == 4
     s.set_state(sus.X, sus.phi)
     cen, com, code = s.run(10_000, 1000)
     assert code == 0
