@@ -349,6 +349,24 @@ def main():
     sim64.close()
     del sim64
 
+    # FP64 in the FP32C form's own shape: the streamed stage kernel in FP64
+    # arithmetic (rsqrt with a Newton step and FMAs), for a like-for-like
+    # comparison of the two arithmetics (no steric forces)
+    stream64 = None
+    if getattr(w.params, "steric_k", 0.0) == 0.0:
+        sims = P.Simulator(w.params, sizes, precision="fp64_tiled", graph=not args.no_graph,
+                           launch=dict(ipl=1, jchunk=256, wg=64, wj=1, posmode=0, fused=3), **model)
+        sims.set_state(w.X, w.phi)
+        secss, _ = time_steps(sims, fp64_steps, max(1, fp64_steps // 10))
+        assert sims.check() == 0
+        vs = pairs_per_step * fp64_steps / secss
+        log(f"fp64 streamed: {secss / fp64_steps * 1e3:.4f} ms/step, {vs:.4e} pairs/s")
+        stream64 = {"value": vs, "unit": "pair interactions/s", "ms_per_step": secss / fp64_steps * 1e3,
+                    "steps": fp64_steps,
+                    "form": "the streamed stage kernel in FP64 (v_rsq_f64 with one Newton step, FMAs)"}
+        sims.close()
+        del sims
+
     # the paper's own design: assembled full tensor, then the product (Sec. V);
     # per step 4 stages, each tensor written once and read once
     dense_bytes = 4 * 2 * 72.0 * float((Nb * Nb).sum())
@@ -428,6 +446,8 @@ def main():
         "fp64_tiled": {"value": v64, "unit": "pair interactions/s", "ms_per_step": secs64 / fp64_steps * 1e3,
                        "steps": fp64_steps},
         "speedup_vs_fp64": value / v64,
+        "fp64_streamed": stream64,
+        "speedup_vs_fp64_streamed": value / stream64["value"] if stream64 else None,
         "fp64_dense": dense,
         "speedup_vs_dense": value / dense["value"] if dense else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

@@ -61,6 +61,7 @@ struct Coef {
     double rc;   /* steric contact distance */
     double cr;   /* 2 a^2/(24 pi eta): Rotne-Prager-Yamakawa-Mazur coefficient */
     float crr;   /* cr / co = 2 a^2 / 3, for the FP32 pair sum */
+    double crr64; /* the same in FP64, for the FP64 streamed stage */
     int rpy;     /* 1: Oseen plus the RPY-Mazur correction; 0: Oseen */
     int noise;   /* 1: Heun with additive noise */
     double g;    /* noise amplitude sqrt(2 kT dt/(6 pi eta a)) */
@@ -254,6 +255,10 @@ __host__ __device__ inline int fused_stream_lds_bytes(int split) {
     const int red = 16 * 16 * 6 * 4 + 16 * 3 * 8;
     return b + red;
 }
+/* LDS bytes of an FP64 streamed work-group: 16 waves x 2 slots x 64 source
+ * entries of 48 B, then the combination area (16 waves x at most 16 targets x
+ * 3 doubles, 16 x 3 stage positions) */
+__host__ __device__ inline int fused_stream64_lds_bytes() { return 16 * 2 * 64 * 48 + 16 * 16 * 3 * 8 + 16 * 3 * 8; }
 /* Resident form (launch.fused = 4): one work-group of RES_T threads per
  * system holds the whole system in LDS and runs every stage of a run of
  * steps in one launch. Systems of at most RES_MAX64 spheres with FP64 pair

@@ -1421,6 +1421,189 @@ __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
     }
 }
 
+/* FP64 streamed form of the fused stage (AD_FP64_TILED with
+ * ad_launch.fused = 3): k_stage_stream's work-group shape, streaming and
+ * combination order in FP64 arithmetic, for a like-for-like comparison with
+ * the FP32C form. The pair term uses v_rsq_f64 refined by one Newton step
+ * and FMAs (a relative error of a few ulp, not the IEEE sqrt and divisions
+ * of the plain sum); the partial sums are plain FP64 sums. As in the other
+ * FP64 forms, the pair sum includes the dumbbell partner and only the self
+ * term is masked, u0 is the self term alone, and the pack is the FP64 one
+ * (3 double2 per sphere). */
+template <int RPY>
+__device__ __forceinline__ void pair_term64(double ir, double rx, double ry, double rz, double Fx, double Fy,
+                                            double Fz, double crr, double& px, double& py, double& pz) {
+    const double fr = __builtin_fma(rz, Fz, __builtin_fma(ry, Fy, rx * Fx));
+    const double ir2 = ir * ir;
+    const double tt = fr * ir2;
+    if (RPY) {
+        const double ir3 = ir * ir2;
+        const double av = __builtin_fma(crr, ir3, ir);
+        const double bv = tt * __builtin_fma(-3.0 * crr, ir3, ir);
+        px = __builtin_fma(av, Fx, __builtin_fma(bv, rx, px));
+        py = __builtin_fma(av, Fy, __builtin_fma(bv, ry, py));
+        pz = __builtin_fma(av, Fz, __builtin_fma(bv, rz, pz));
+    } else {
+        px = __builtin_fma(ir, __builtin_fma(tt, rx, Fx), px);
+        py = __builtin_fma(ir, __builtin_fma(tt, ry, Fy), py);
+        pz = __builtin_fma(ir, __builtin_fma(tt, rz, Fz), pz);
+    }
+}
+
+/* 1/sqrt(r2) from v_rsq_f64 and one Newton step y (1 + (1 - r2 y^2) / 2) */
+__device__ __forceinline__ double rsqrt64_nr(double r2) {
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double e = __builtin_fma(-r2 * y, y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
+}
+
+template <int RPY, int TI>
+__global__ __launch_bounds__(1024) void k_stage_stream64(Dev d, Epi e) {
+    constexpr int NW = 16;
+    constexpr int G = 64 / TI;  /* lane groups (splits) per wave */
+    constexpr int JS = NW * G;  /* source splits */
+    extern __shared__ double4 fs64_lds[];
+    const int N = d.Ntot;
+    const int tid = threadIdx.x;
+    int i0, off, Nb;
+    if (d.nfitems == 0) {
+        i0 = blockIdx.x * TI;
+        off = 0;
+        Nb = N;
+    } else {
+        const Item it = d.fitems[blockIdx.x];
+        i0 = it.i0;
+        off = it.ioff;
+        Nb = it.Nb;
+    }
+    const int ni = min(TI, off + Nb - i0);
+    const int Q = (Nb + JS * TI - 1) / (JS * TI) * TI; /* sources per split */
+    const int K = Q / TI;                              /* chunks per split */
+    /* per wave and buffer 64 entries: A = (x, y, z, Fx), F = (Fy, Fz) */
+    double4* sA = fs64_lds;
+    double2* sF = reinterpret_cast<double2*>(fs64_lds + NW * 128);
+    const long long step = (e.stage == 0) ? d.ctl->slot[0] : d.ctl->slot[1];
+    double u0 = 0.0, xv = 0.0, rv = 0.0;
+    if (tid < 3 * ni) {
+        const int tt = tid / 3, a = tid - 3 * tt;
+        const int o = a * N + i0 + tt;
+        u0 = d.U0[o];
+        xv = d.X[o];
+        if (e.stage > 0) rv = d.R[o];
+    }
+    const int w = tid >> 6, l = tid & 63, t = l % TI, g = l / TI;
+    const int sp = G * w + g;
+    const int i = i0 + t;
+    double hx = 0.0, hy = 0.0, hz = 0.0;
+    if (t < ni) {
+        const double2 a0 = d.pD[3 * i], a1 = d.pD[3 * i + 1];
+        hx = a0.x; hy = a0.y; hz = a1.x;
+    }
+    const int so = (i0 - off) / Q, ko = ((i0 - off) - so * Q) / TI;
+    const bool own_wave = so / G == w;
+
+    double4 eA;
+    double2 eF;
+    auto fetch = [&](int k) {
+        const int j = sp * Q + k * TI + t;
+        if (off + j < off + Nb) {
+            const double2 a0 = d.pD[3 * (off + j)], a1 = d.pD[3 * (off + j) + 1], a2 = d.pD[3 * (off + j) + 2];
+            eA = make_double4(a0.x, a0.y, a1.x, a1.y);
+            eF = a2;
+        } else {
+            eA = make_double4(1.0e15, 1.0e15, 1.0e15, 0.0);
+            eF = make_double2(0.0, 0.0);
+        }
+    };
+    auto put = [&](int buf) {
+        const int x = (w * 2 + buf) * 64 + g * TI + t;
+        sA[x] = eA;
+        sF[x] = eF;
+    };
+    fetch(0);
+    put(0);
+    advance_slots(d, e);
+    double st = 0.0, ct = 0.0;
+    double2 tp = make_double2(0.0, 0.0);
+    if (tid < ni) {
+        const long long row = step & (d.ring - 1);
+        st = d.tab[row * 8 + 2 * e.stage];
+        ct = d.tab[row * 8 + 2 * e.stage + 1];
+        tp = d.phitrig[(i0 >> 1) + (tid >> 1)];
+    }
+
+    const double crr = e.c.crr64;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    auto term = [&](int x, int j, bool masked) {
+        const double4 Aj = sA[x];
+        const double2 Fj = sF[x];
+        const double rx = hx - Aj.x, ry = hy - Aj.y, rz = hz - Aj.z;
+        const double r2 = __builtin_fma(rz, rz, __builtin_fma(ry, ry, rx * rx));
+        double ir = rsqrt64_nr(r2);
+        if (masked && j == i - off) ir = 0.0;
+        pair_term64<RPY>(ir, rx, ry, rz, Aj.w, Fj.x, Fj.y, crr, px, py, pz);
+    };
+    for (int k = 0; k < K; ++k) {
+        const int buf = k & 1;
+        if (k + 1 < K) fetch(k + 1);
+        const int x0 = (w * 2 + buf) * 64 + g * TI;
+        const int j0 = sp * Q + k * TI;
+        if (own_wave && k == ko) {
+            for (int v = 0; v < TI; ++v) term(x0 + v, j0 + v, true);
+        } else {
+#pragma unroll
+            for (int v = 0; v < TI; ++v) term(x0 + v, j0 + v, false);
+        }
+        if (k + 1 < K) put(buf ^ 1);
+    }
+    /* the G groups of a wave by shuffles, then the waves through LDS in a
+     * pairwise tree: a fixed order */
+#pragma unroll
+    for (int sh = TI; sh < 64; sh *= 2) {
+        px = px + __shfl_xor(px, sh);
+        py = py + __shfl_xor(py, sh);
+        pz = pz + __shfl_xor(pz, sh);
+    }
+    double* red = reinterpret_cast<double*>(fs64_lds + NW * 128 + NW * 128 / 2); /* [NW][TI][3] */
+    double* ys = red + NW * TI * 3;                                              /* [TI][3] */
+    if (g == 0) {
+        double* r = red + (w * TI + t) * 3;
+        r[0] = px; r[1] = py; r[2] = pz;
+    }
+    __syncthreads();
+    if (w != 0) return;
+    int bad = 0;
+    if (tid < 3 * ni) {
+        const int tt = tid / 3, a = tid - 3 * tt;
+        double hs[NW];
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) hs[ww] = red[(ww * TI + tt) * 3 + a];
+#pragma unroll
+        for (int st2 = 1; st2 < NW; st2 *= 2)
+#pragma unroll
+            for (int ww = 0; ww < NW; ww += 2 * st2) hs[ww] = hs[ww] + hs[ww + st2];
+        const int ii = i0 + tt;
+        const double k = u0 + e.c.co * hs[0];
+        bad = !isfinite(k);
+        ys[tt * 3 + a] = stage_update(d, e, a * N + ii, ii, a, k, xv, rv, step);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (__any(bad) && tid == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+    if (tid < ni) {
+        const int q = tid >> 1, h = tid & 1;
+        double f[2][3];
+        spring_forces_rs(e.c, ys + (2 * q) * 3, ys + (2 * q + 1) * 3, tp.x, tp.y, st, ct, f[0], f[1]);
+        const double* y = ys + tid * 3;
+        const int ii = i0 + tid;
+        for (int a = 0; a < 3; ++a) d.U0[a * N + ii] = e.c.cs * f[h][a];
+        d.pD2[3 * ii + 0] = make_double2(y[0], y[1]);
+        d.pD2[3 * ii + 1] = make_double2(y[2], f[h][0]);
+        d.pD2[3 * ii + 2] = make_double2(f[h][1], f[h][2]);
+    }
+}
+
 /* FP64: the sum in ascending j with the plain operation order
  *   r2 = (rx*rx + ry*ry) + rz*rz; ir = 1/sqrt(r2); fr = (rx*Fx + ry*Fy) + rz*Fz;
  *   t = fr/r2; acc = acc + ir*(F + t*r)
@@ -2208,6 +2391,19 @@ static hipError_t go_stream(const Dev& d, const Epi& e, hipStream_t s, const Tim
     return hipGetLastError();
 }
 
+template <int RPY>
+static hipError_t go_stream64(const Dev& d, const Epi& e, hipStream_t s, const Timing& tm) {
+    const int lds = fused_stream64_lds_bytes();
+    const int ti = stream_targets(d.Ntot);
+    const dim3 grid(d.nfitems ? d.nfitems : (d.Ntot + ti - 1) / ti);
+    auto kern = ti == 16 ? k_stage_stream64<RPY, 16> : ti == 8 ? k_stage_stream64<RPY, 8> : k_stage_stream64<RPY, 4>;
+    if (tm.start)
+        hipExtLaunchKernelGGL(kern, grid, dim3(1024), lds, s, tm.start, tm.stop, 0, d, e);
+    else
+        hipLaunchKernelGGL(kern, grid, dim3(1024), lds, s, d, e);
+    return hipGetLastError();
+}
+
 typedef void (*ResidentKernel)(Dev, Epi, long long, int, double, double);
 
 template <int SPLIT, int RPY, int T>
@@ -2248,6 +2444,12 @@ hipError_t prepare_fused() {
                              reinterpret_cast<const void*>(&k_stage_stream<0, 1, 4>),
                              reinterpret_cast<const void*>(&k_stage_stream<1, 0, 4>),
                              reinterpret_cast<const void*>(&k_stage_stream<1, 1, 4>),
+                             reinterpret_cast<const void*>(&k_stage_stream64<0, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream64<1, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream64<0, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream64<1, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream64<0, 4>),
+                             reinterpret_cast<const void*>(&k_stage_stream64<1, 4>),
                              reinterpret_cast<const void*>(&k_stage_wide<0, 0>),
                              reinterpret_cast<const void*>(&k_stage_wide<0, 1>),
                              reinterpret_cast<const void*>(&k_stage_wide<1, 0>),
@@ -2311,8 +2513,12 @@ hipError_t launch_resident(const Dev& d, const Epi& e, int hilo, int maxNb, long
 
 hipError_t launch_fused(const Dev& d, const Epi& e, const Shape& sh, int maxNb, hipStream_t s,
                         hipEvent_t ev_start, hipEvent_t ev_stop) {
-    if (e.prec != PREC_FP32C || sh.steric || maxNb < 2) return hipErrorInvalidValue;
     const Timing tm0{ev_start, ev_stop};
+    if (e.prec == PREC_FP64_TILED && sh.fused == 3 && !sh.steric && maxNb >= 2) {
+        if ((d.nsys > 1) != (d.nfitems > 0)) return hipErrorInvalidValue;
+        return sh.rpy ? go_stream64<1>(d, e, s, tm0) : go_stream64<0>(d, e, s, tm0);
+    }
+    if (e.prec != PREC_FP32C || sh.steric || maxNb < 2) return hipErrorInvalidValue;
     if (sh.fused == 2) {
         /* every work-group takes its (system, 64-target block) from the list */
         if (d.nfitems <= 0 || fused_wide_lds_bytes(maxNb, sh.split) > FUSED_LDS_MAX) return hipErrorInvalidValue;

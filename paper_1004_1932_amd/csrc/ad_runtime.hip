@@ -142,6 +142,7 @@ Coef make_coef(const ad_params* p) {
     k.rc = p->steric_r;
     k.cr = 2.0 * p->a * p->a / (24.0 * kPi * p->eta);
     k.crr = (float)(2.0 * p->a * p->a / 3.0);
+    k.crr64 = 2.0 * p->a * p->a / 3.0;
     k.rpy = p->tensor == AD_RPY ? 1 : 0;
     k.noise = p->kT > 0.0 ? 1 : 0;
     k.g = sqrt(2.0 * p->kT * (1.0 / (6.0 * kPi * p->eta * p->a)) * p->dt);
@@ -223,9 +224,16 @@ static int validate_launch(ad_ctx* c, const ad_launch& L) {
                         c->maxNb);
         return AD_OK;
     }
+    if (L.fused == 3 && c->p.precision == AD_FP64_TILED) {
+        /* the FP64 streamed stage: every system size, no steric forces */
+        if (c->p.steric_k != 0.0) return fail(c, AD_EINVAL, "launch.fused 3 takes no steric forces");
+        if (ad::fused_stream64_lds_bytes() > ad::FUSED_LDS_MAX) return fail(c, AD_EINVAL, "launch.fused 3: LDS");
+        return AD_OK;
+    }
     if (L.fused) {
         if (c->p.precision != AD_FP32C || c->p.steric_k != 0.0)
-            return fail(c, AD_EINVAL, "launch.fused needs AD_FP32C and no steric forces");
+            return fail(c, AD_EINVAL, "launch.fused 1 and 2 need AD_FP32C (3 also AD_FP64_TILED) and no steric "
+                        "forces");
         const int hilo = L.posmode == AD_POS_HILO;
         const int lds = L.fused == 3   ? ad::fused_stream_lds_bytes(hilo)
                         : L.fused == 2 ? ad::fused_wide_lds_bytes(c->maxNb, hilo)

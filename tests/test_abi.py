@@ -226,8 +226,10 @@ def test_wide_fused_stage_launch_rules():
 
 
 def test_streamed_fused_stage_launch_rules():
-    """launch.fused = 3 (sources streamed per wave): AD_FP32C without steric
-    forces, any system size (no LDS limit), one system or an ensemble."""
+    """launch.fused = 3 (sources streamed per wave): AD_FP32C or
+    AD_FP64_TILED without steric forces, any system size (no LDS limit), one
+    system or an ensemble; not the plain FP64 form (bitwise the sequential
+    sum) nor the dense one."""
     for sizes in ([2048], [3414], [20000], [64, 32, 5]):
         ctx = P.ad_create(P.make_params(Params(), "fp32c"), sizes)
         try:
@@ -236,7 +238,15 @@ def test_streamed_fused_stage_launch_rules():
                 assert P.ad_get_launch(ctx)["fused"] == 3
         finally:
             P.ad_destroy(ctx)
-    for prec, sizes, params in (("fp64", [64], Params()), ("fp64_tiled", [64], Params()),
+    for sizes in ([2048], [20000], [64, 32, 5]):
+        ctx = P.ad_create(P.make_params(Params(), "fp64_tiled"), sizes)
+        try:
+            P.ad_set_launch(ctx, fused=3, posmode=0)
+            assert P.ad_get_launch(ctx)["fused"] == 3
+        finally:
+            P.ad_destroy(ctx)
+    for prec, sizes, params in (("fp64", [64], Params()), ("fp64_dense", [64], Params()),
+                                ("fp64_tiled", [64], Params(steric_k=100.0, steric_r=2.0)),
                                 ("fp32c", [64, 8], Params(steric_k=100.0, steric_r=2.0))):
         ctx = P.ad_create(P.make_params(params, prec), sizes)
         try:

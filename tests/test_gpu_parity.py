@@ -843,6 +843,65 @@ def test_streamed_fused_stage_large_systems(oracle, S, posmode):
     check_fp32c(s.get_state()[0].cpu().numpy() - sus.X, Xo - sus.X, "displacement")
 
 
+STREAM64 = {"ipl": 1, "jchunk": 256, "wg": 64, "wj": 1, "posmode": 0, "fused": 3}
+
+
+@pytest.mark.parametrize("integrator,tensor", [("rk4", "oseen"), ("heun", "oseen"), ("rk4", "rpy")])
+def test_fp64_streamed_stage_matches_oracle(oracle, integrator, tensor):
+    """The FP64 streamed stage (AD_FP64_TILED, fused = 3: rsqrt with one
+    Newton step and FMAs, tiled sums) on single systems from 1 dumbbell to
+    a size that is neither a multiple of the 1024-source padding nor of any
+    target block (4, 8 and 16 targets per work-group all occur), 200 steps:
+    within 1e-11 of the oracle relative to the displacement, per system and
+    per sphere."""
+    _torch()
+    for S, side in ((1, 10.0), (5, 20.0), (300, 120.0), (1100, 180.0), (2100, 240.0)):
+        sus = make_single(S, side, 61)
+        say(f"fp64 streamed {integrator} {tensor} S={S}")
+        s = P.Simulator(sus.params, [S], precision="fp64_tiled", integrator=integrator, tensor=tensor,
+                        launch=STREAM64, graph=True)
+        s.set_state(sus.X, sus.phi)
+        _, _, code = s.run(200, 0)
+        assert code == 0
+        X = s.get_state()[0].cpu().numpy()
+        Xo, _, _, _ = oracle.run(sus.params, sus.X, sus.phi, 200, integrator=1 if integrator == "heun" else 0,
+                                 tensor=1 if tensor == "rpy" else 0)
+        d, do = X - sus.X, Xo - sus.X
+        assert relerr(d, do) <= 1e-11, (S, relerr(d, do))
+        scale = np.linalg.norm(do, axis=1) + np.median(np.linalg.norm(do, axis=1))
+        assert (np.linalg.norm(d - do, axis=1) / scale).max() <= 1e-10, S
+
+
+def test_fp64_streamed_stage_ensemble_determinism_and_flag(oracle):
+    """FP64 streamed stage on an uneven ensemble: 100 steps per system within
+    1e-11 of the oracle; two runs give the same bits and split calls equal
+    one call; coincident spheres raise the flag."""
+    _torch()
+    sizes = np.array([1, 16, 120, 3, 57, 64, 33, 90, 200], dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    out = []
+    for calls in ((100,), (100,), (30, 70)):
+        s = P.Simulator(ens.params, sizes, precision="fp64_tiled", launch=STREAM64, graph=True)
+        s.set_state(ens.X, ens.phi)
+        for n in calls:
+            _, _, code = s.run(n, 0)
+            assert code == 0
+        out.append(s.get_state()[0].cpu().numpy())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    Xo, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 100, S_per_sys=sizes)
+    off = ens.sphere_offsets
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        assert relerr(out[0][sl] - ens.X[sl], Xo[sl] - ens.X[sl]) <= 1e-11, b
+    sus = make_single(8, 30.0, 3)
+    X = sus.X.copy()
+    X[5] = X[2]
+    s = P.Simulator(sus.params, [sus.S], precision="fp64_tiled", launch=STREAM64)
+    s.set_state(X, sus.phi)
+    _, _, code = s.run(2, 1)
+    assert code == P.binding.AD_ENONFINITE
+
+
 def test_streamed_fused_stage_ensemble_and_determinism(oracle):
     """An ensemble of uneven systems (16-target work list), 200 steps against
     the oracle; two runs give the same bits and split calls equal one call."""
