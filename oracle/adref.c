@@ -264,6 +264,22 @@ int adref_mobility(const adref_params* p, int64_t N, const double* X, const doub
     return bad ? ADREF_ENONFINITE : ADREF_OK;
 }
 
+/* The names of the library's calls: adref_mobility_apply is adref_mobility
+ * (u = M(X) F for caller forces), adref_step is adref_run without records
+ * (the oracle keeps no state: X is advanced in place). */
+int adref_mobility_apply(const adref_params* p, int64_t N, const double* X, const double* F, double* u) {
+    return adref_mobility(p, N, X, F, u);
+}
+
+int adref_run(const adref_params* p, int32_t nsys, const int64_t* off, double* X, const double* phi,
+              double t0, int64_t step0, int64_t nsteps, int64_t record_every,
+              double* centres_out, double* com_out);
+
+int adref_step(const adref_params* p, int32_t nsys, const int64_t* off, double* X, const double* phi,
+               double t0, int64_t step0, int64_t nsteps) {
+    return adref_run(p, nsys, off, X, phi, t0, step0, nsteps, 0, NULL, NULL);
+}
+
 /* The same sum for a subset of target spheres: u_rows[r] = u_{rows[r]}. */
 int adref_mobility_rows(const adref_params* p, int64_t N, const double* X, const double* F,
                         int64_t nrows, const int64_t* rows, double* u_rows) {

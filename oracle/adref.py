@@ -53,6 +53,8 @@ def lib():
         P = C.POINTER(_Params)
         L.adref_forces.argtypes = [P, C.c_int64, _dp, _dp, C.c_double, _dp]
         L.adref_mobility.argtypes = [P, C.c_int64, _dp, _dp, _dp]
+        L.adref_mobility_apply.argtypes = [P, C.c_int64, _dp, _dp, _dp]
+        L.adref_step.argtypes = [P, C.c_int32, _ip, _dp, _dp, C.c_double, C.c_int64, C.c_int64]
         L.adref_mobility_rows.argtypes = [P, C.c_int64, _dp, _dp, C.c_int64, _ip, _dp]
         L.adref_mobility_dense.argtypes = [P, C.c_int64, _dp, _dp, _dp]
         L.adref_run.argtypes = [P, C.c_int32, _ip, _dp, _dp, C.c_double, C.c_int64, C.c_int64,

@@ -464,3 +464,25 @@ def test_aligned_pair_in_phase_does_not_swim(oracle, golden_dir):
     g = json.loads((golden_dir / "fig1_aligned_pair.json").read_text())
     d, sa = _aligned_pair_displacement(oracle, g, g["a_over_ell"], 10.0, 0.0)
     assert abs(d[0, 0] + d[1, 0]) < 1e-6 * sa
+
+
+def test_library_call_names_are_the_same_functions(oracle):
+    """adref_mobility_apply and adref_step, the oracle's entries under the
+    library's call names, give the bits of adref_mobility and of adref_run
+    without records."""
+    import ctypes as C
+    L = oracle.lib()
+    sus = make_single(12, 40.0, 4)
+    p = C.byref(oracle._params(sus.params))
+    X = np.ascontiguousarray(sus.X, dtype=np.float64)
+    F = oracle.forces(sus.params, X, sus.phi, 0.7)
+    u = oracle.mobility(sus.params, X, F)
+    u2 = np.zeros_like(u)
+    assert L.adref_mobility_apply(p, X.shape[0], oracle._d(X), oracle._d(F), oracle._d(u2)) == 0
+    assert np.array_equal(u, u2)
+    Xr, _, _, _ = oracle.run(sus.params, X, sus.phi, 25, t0=0.3, step0=7)
+    Xs = X.copy()
+    off = np.array([0, X.shape[0]], dtype=np.int64)
+    assert L.adref_step(p, 1, off.ctypes.data_as(C.POINTER(C.c_int64)), oracle._d(Xs), oracle._d(sus.phi), 0.3,
+                        7, 25) == 0
+    assert np.array_equal(Xr, Xs)
