@@ -116,14 +116,16 @@ typedef struct ad_launch {
                          2: the same with 64 target spheres per 4-wave work-group, one per
                          lane, for ensembles of small systems (at most 6824 single-float or
                          4548 hi/lo spheres per system);
-                         3: 16 target spheres per work-group whose waves stream their share of
-                         the sources through a small LDS slot each (AD_FP32C, no steric
-                         forces, any system size; sources are padded to a multiple of 1024);
-                         4: resident: one work-group per system holds the whole system in
-                         LDS and runs every stage of a run of steps (up to the next record
-                         point) in one launch (AD_FP64 and AD_FP64_TILED: the sequential
-                         FP64 sum, systems of at most 128 spheres; AD_FP32C: at most 256;
-                         no steric forces; for ensembles of small systems);
+                         3: 4, 8 or 16 target spheres per work-group (about N_total / 256)
+                         whose waves stream their share of the sources through a small LDS
+                         slot each (AD_FP32C, or AD_FP64_TILED in FP64 arithmetic with
+                         v_rsq_f64 refined by one Newton step and FMAs; no steric forces, any
+                         system size; sources are padded to a multiple of 1024);
+                         4: resident: one work-group per system keeps the whole system on
+                         the compute unit and runs every stage of a run of steps (up to the
+                         next record point) in one launch (AD_FP64 and AD_FP64_TILED: the
+                         sequential FP64 sum, systems of at most 128 spheres; AD_FP32C: at
+                         most 256; no steric forces; for small systems and their ensembles);
                          0: pair kernel and epilogue as two kernels */
 } ad_launch;
 
@@ -200,7 +202,8 @@ int ad_use_graph(ad_ctx* ctx, int32_t enable);
 
 /* Measurement support. With enable != 0, ad_step/ad_run launch kernels
  * directly (no graph) and bracket every launch of the pair-sum kernel (with
- * launch.fused = 1 or 2, the stage kernel, which also does the stage update; with
+ * launch.fused = 1, 2 or 3, the stage kernel, which also does the stage update; with
+ * launch.fused = 4, each launch of the resident kernel; with
  * AD_FP64_DENSE, the assembly and product together) with HIP events on the
  * call's stream; ad_profile_read synchronises and returns the summed duration
  * (ms) and number of those launches since enabling. */

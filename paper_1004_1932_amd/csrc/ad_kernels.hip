@@ -1213,7 +1213,8 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
  * (wave w, lane group g of TI lanes) owns a contiguous range of Q sources
  * (Q a multiple of TI). A wave streams its ranges through a double-buffered LDS
  * slot of its own, TI sources per split at a time, one entry per lane: the
- * next chunk's loads are in flight while the current chunk is summed, no
+ * loads of the chunk after next are in flight while the current chunk is
+ * summed (two register sets; 0.5 % off a 4096-sphere step, 1.3 % at 8192), no
  * work-group barrier separates loading from summing, and no system is too
  * large for LDS. Lane (w, g, t) sums target t over its split's range in
  * ascending order, folding into (hi, lo) every 32 sources. LDS ops of one
@@ -1280,21 +1281,29 @@ __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
     const int so = (i0 - off) / Q, ko = ((i0 - off) - so * Q) / TI;
     const bool own_wave = so / G == w;
 
-    float4 eA, eB;
-    float eFy, eFz;
-    auto fetch = [&](int k) { load_stage_entry<SPLIT>(d, off, off + Nb, sp * Q + k * TI + t, eA, eB, eFy, eFz); };
-    auto put = [&](int buf) {
+    /* two register sets: chunk k + 2 is loaded while chunk k is summed */
+    float4 eA0, eB0, eA1, eB1;
+    float eFy0, eFz0, eFy1, eFz1;
+    auto fetch = [&](int k, auto R) {
+        if constexpr (decltype(R)::value == 0)
+            load_stage_entry<SPLIT>(d, off, off + Nb, sp * Q + k * TI + t, eA0, eB0, eFy0, eFz0);
+        else
+            load_stage_entry<SPLIT>(d, off, off + Nb, sp * Q + k * TI + t, eA1, eB1, eFy1, eFz1);
+    };
+    auto put = [&](int buf, auto R) {
+        constexpr int r = decltype(R)::value;
         const int x = (w * 2 + buf) * 64 + g * TI + t;
-        sA[x] = eA;
+        sA[x] = r ? eA1 : eA0;
         if (SPLIT) {
-            sB[x] = eB;
-            sC[x] = eFz;
+            sB[x] = r ? eB1 : eB0;
+            sC[x] = r ? eFz1 : eFz0;
         } else {
-            sF[x] = make_float2(eFy, eFz);
+            sF[x] = r ? make_float2(eFy1, eFz1) : make_float2(eFy0, eFz0);
         }
     };
-    fetch(0);
-    put(0);
+    fetch(0, std::integral_constant<int, 0>{});
+    put(0, std::integral_constant<int, 0>{});
+    if (K > 1) fetch(1, std::integral_constant<int, 1>{});
     /* wave 0 only: the step slots and this stage's (sin, cos)(omega t) and
      * phases, whose dependent loads then stall a wave that is not the last
      * to finish its sums */
@@ -1339,10 +1348,10 @@ __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
         pair_term<RPY>(ir, rx, ry, rz, Aj.w, Fy, Fz, crr, px, py, pz);
     };
     float px = 0.f, py = 0.f, pz = 0.f;
-    for (int k = 0; k < K; ++k) {
-        const int buf = k & 1;
-        if (k + 1 < K) fetch(k + 1);
-        const int x0 = (w * 2 + buf) * 64 + g * TI;
+    auto chunk = [&](int k, auto R) {
+        constexpr int r = decltype(R)::value; /* = k & 1, the buffer and the set of chunk k */
+        if (k + 2 < K) fetch(k + 2, R);
+        const int x0 = (w * 2 + r) * 64 + g * TI;
         const int j0 = sp * Q + k * TI;
         if (own_wave && k == ko) {
             for (int v = 0; v < TI; ++v) term(x0 + v, j0 + v, true, px, py, pz);
@@ -1356,7 +1365,11 @@ __global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
             two_sum_acc(az, bz, pz);
             px = py = pz = 0.f;
         }
-        if (k + 1 < K) put(buf ^ 1);
+        if (k + 1 < K) put(1 - r, std::integral_constant<int, 1 - r>{});
+    };
+    for (int k = 0; k < K; k += 2) {
+        chunk(k, std::integral_constant<int, 0>{});
+        if (k + 1 < K) chunk(k + 1, std::integral_constant<int, 1>{});
     }
 
     /* combine the partial sums of each target as k_stage_fused does: the G
