@@ -247,12 +247,16 @@ __host__ __device__ inline int stream_targets(int Ntot) {
     while (ti < FT_I && 2 * 256 * ti <= Ntot) ti *= 2;
     return ti;
 }
-/* LDS bytes of a streamed fused work-group: 16 waves x 2 slots x 64 source
- * entries, followed by the combination area (16 waves x at most 16 targets
- * x 6 floats, 16 x 3 stage positions) */
-__host__ __device__ inline int fused_stream_lds_bytes(int split) {
-    const int b = 16 * 2 * 64 * (split ? 36 : 24);
-    const int red = 16 * 16 * 6 * 4 + 16 * 3 * 8;
+/* waves per work-group of the streamed fused stage with ti targets: 8 with
+ * 4 targets (the small systems, whose few sources per lane make the
+ * combination of 16 waves' sums a large share), else 16 */
+__host__ __device__ inline int stream_waves(int ti) { return ti == 4 ? 8 : 16; }
+/* LDS bytes of a streamed fused work-group: nw waves x 2 slots x 64 source
+ * entries, followed by the combination area (nw waves x ti targets x 6
+ * floats, ti x 3 stage positions); at most 16 waves and 16 targets */
+__host__ __device__ inline int fused_stream_lds_bytes(int split, int nw = 16, int ti = FT_I) {
+    const int b = nw * 2 * 64 * (split ? 36 : 24);
+    const int red = nw * ti * 6 * 4 + ti * 3 * 8;
     return b + red;
 }
 /* LDS bytes of an FP64 streamed work-group: 16 waves x 2 slots x 64 source

@@ -1205,11 +1205,13 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
 }
 
 /* Streamed form of the fused stage (ad_launch.fused = 3). The work-group of
- * 16 waves owns TI target spheres, TI = 4, 8 or 16 chosen by stream_targets
- * so that a launch holds about one work-group per compute unit (at
- * N = 4096, TI = 8 puts two work-groups on a compute unit and measured 22 %
- * slower, since every work-group reads every source; at N = 2048, TI = 16
- * leaves half the compute units idle and measured 18 % slower). Each of its source splits
+ * NW waves owns TI target spheres. TI = 4, 8 or 16 (stream_targets) keeps
+ * about one work-group per compute unit: at N = 4096, TI = 8 puts two
+ * work-groups on a compute unit and measured 22 % slower, since every
+ * work-group reads every source; at N = 2048, TI = 16 leaves half the compute
+ * units idle and measured 18 % slower. NW = 16, or 8 with 4 targets
+ * (stream_waves): with 8 waves N = 512 ran 16 % faster and N = 1024 9 %, while
+ * N = 4096 with 16 targets ran 10 % slower. Each of its source splits
  * (wave w, lane group g of TI lanes) owns a contiguous range of Q sources
  * (Q a multiple of TI). A wave streams its ranges through a double-buffered LDS
  * slot of its own, TI sources per split at a time, one entry per lane: the
@@ -1225,9 +1227,8 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
  * area beside the slots, so one work-group barrier precedes the closing
  * update; wave 0 then does it alone (stage update, spring forces and pack,
  * in the rsqrt forms) with no further barrier. */
-template <int SPLIT, int RPY, int TI>
-__global__ __launch_bounds__(1024) void k_stage_stream(Dev d, Epi e) {
-    constexpr int NW = 16;
+template <int SPLIT, int RPY, int TI, int NW>
+__global__ __launch_bounds__(64 * NW) void k_stage_stream(Dev d, Epi e) {
     constexpr int G = 64 / TI;    /* lane groups (splits) per wave */
     constexpr int JS = NW * G;    /* source splits */
     constexpr int FOLD = 32 / TI; /* chunks per (hi, lo) fold */
@@ -2392,15 +2393,15 @@ static hipError_t go_wide(const Dev& d, const Epi& e, int maxNb, hipStream_t s, 
 
 template <int SPLIT, int RPY>
 static hipError_t go_stream(const Dev& d, const Epi& e, hipStream_t s, const Timing& tm) {
-    const int lds = fused_stream_lds_bytes(SPLIT);
-    const int ti = stream_targets(d.Ntot);
+    const int ti = stream_targets(d.Ntot), nw = stream_waves(ti);
+    const int lds = fused_stream_lds_bytes(SPLIT, nw, ti);
     const dim3 grid(d.nfitems ? d.nfitems : (d.Ntot + ti - 1) / ti);
-    auto kern = ti == 16 ? k_stage_stream<SPLIT, RPY, 16>
-                : ti == 8 ? k_stage_stream<SPLIT, RPY, 8> : k_stage_stream<SPLIT, RPY, 4>;
+    auto kern = ti == 16 ? k_stage_stream<SPLIT, RPY, 16, 16>
+                : ti == 8 ? k_stage_stream<SPLIT, RPY, 8, 16> : k_stage_stream<SPLIT, RPY, 4, 8>;
     if (tm.start)
-        hipExtLaunchKernelGGL(kern, grid, dim3(1024), lds, s, tm.start, tm.stop, 0, d, e);
+        hipExtLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, s, tm.start, tm.stop, 0, d, e);
     else
-        hipLaunchKernelGGL(kern, grid, dim3(1024), lds, s, d, e);
+        hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, s, d, e);
     return hipGetLastError();
 }
 
@@ -2445,18 +2446,18 @@ static ResidentKernel resident_c_kernel(int hilo, int rpy, int T, int integ) {
 }
 
 hipError_t prepare_fused() {
-    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_stream<0, 0, 16>),
-                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 16>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 16>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 16>),
-                             reinterpret_cast<const void*>(&k_stage_stream<0, 0, 8>),
-                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 8>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 8>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 8>),
-                             reinterpret_cast<const void*>(&k_stage_stream<0, 0, 4>),
-                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 4>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 4>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 4>),
+    const void* kernels[] = {reinterpret_cast<const void*>(&k_stage_stream<0, 0, 16, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 16, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 16, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 16, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 0, 8, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 8, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 8, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 8, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 0, 4, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 4, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 4, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 4, 8>),
                              reinterpret_cast<const void*>(&k_stage_stream64<0, 16>),
                              reinterpret_cast<const void*>(&k_stage_stream64<1, 16>),
                              reinterpret_cast<const void*>(&k_stage_stream64<0, 8>),
