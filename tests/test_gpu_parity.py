@@ -1085,6 +1085,29 @@ def test_resident_fp32c_matches_oracle(oracle, launch, integrator, tensor):
         check_fp32c(out["res"][sl] - ens.X[sl], out["two"][sl] - ens.X[sl], f"system {b} vs two-kernel path")
 
 
+@pytest.mark.parametrize("sizes", [[8], [16], [8, 1, 5, 2], [12, 16, 3]])
+def test_resident_fp32c_thread_counts_match_oracle(oracle, sizes):
+    """The FP32C resident form at each of its thread counts: one wave up to
+    16 spheres (4 lanes per sphere at 16 spheres, 32 at 2), 256 threads for
+    17 to 32 spheres (8 lanes per sphere), 512 above; the uneven ensembles
+    put systems of different sizes, and so different lane counts, in one
+    launch. 300 RK4 steps against the oracle per system, norm and per-sphere
+    bars."""
+    _torch()
+    sizes = np.array(sizes, dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    s = P.Simulator(ens.params, sizes, precision="fp32c", launch=RESIDENT_SINGLE, graph=True)
+    s.set_state(ens.X, ens.phi)
+    _, _, code = s.run(300, 0)
+    assert code == 0
+    X = s.get_state()[0].cpu().numpy()
+    Xo, _, _, _ = oracle.run(ens.params, ens.X, ens.phi, 300, S_per_sys=sizes)
+    off = ens.sphere_offsets
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        check_fp32c(X[sl] - ens.X[sl], Xo[sl] - ens.X[sl], f"system {b} (S={sizes[b]})")
+
+
 def test_resident_noise_determinism_and_split_calls(oracle):
     """Resident form: Heun with Brownian noise follows the oracle's
     trajectory (same Philox numbers); two runs give the same bits; split
