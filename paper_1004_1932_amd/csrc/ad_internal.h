@@ -95,10 +95,12 @@ struct Dev {
     float2* pC2;
     double2* pD2;
     double* part;       /* partial sums */
-    double* H;          /* dense mode: per system the 3Nb x 3Nb pair tensor, column-major */
-    const Item* fitems; /* fused stages of an ensemble: (system, 16-target block) items */
+    double* H;          /* dense mode: per system the 3Nb x 3Nb pair tensor, column-major;
+                           AD_FP64 two-pass sum: per system the pair terms [ncomp][Nb][Nb] */
+    const Item* fitems; /* fused stages of an ensemble: (system, target block) items; the
+                           resident form: one per system; AD_FP64 two-pass sum: term tiles */
     int nfitems;        /* 0: one system, blocks in order */
-    const long long* sys_hbase; /* [nsys] dense mode: first element of the system's tensor */
+    const long long* sys_hbase; /* [nsys] first element of the system's tensor or terms in H */
     const double* tab;  /* [ring][8] (sin, cos) of omega*t per epilogue stage */
     int ring;           /* entries in tab, a power of two (rows are step & (ring - 1)) */
     int Ntot, Stot, nsys, nitems;
@@ -235,6 +237,9 @@ __host__ __device__ inline int fused_wide_lds_bytes(int n, int split) {
     const int red = 4 * FW_I * 6 * 4 + FW_I * 3 * 8 + 16;
     return b > red ? b : red;
 }
+/* AD_FP64 term tiles of the two-pass pair sum: targets x sources */
+constexpr int TT_I = 16;
+constexpr int TT_J = 64;
 /* the most target spheres per work-group of the streamed fused stage */
 constexpr int FT_I = 16;
 /* target spheres per work-group of the streamed fused stage for Ntot
