@@ -387,7 +387,7 @@ def main():
     sim = P.Simulator(w.params, sizes, precision=args.precision, graph=not args.no_graph,
                       launch=launch, **model)
     sim.set_state(w.X, w.phi)
-    log(f"fp32c launch {sim.launch}")
+    log(f"{args.precision} launch {sim.launch}")
 
     # pair-kernel duration under HIP events on the launch stream (with fused
     # stages, the one kernel of a stage, which also does the stage update);
@@ -408,7 +408,7 @@ def main():
     assert sim.check() == 0
     ms_per_step = secs / args.steps * 1e3
     value = pairs_per_step * args.steps / secs
-    log(f"fp32c: {ms_per_step:.4f} ms/step, {value:.4e} pairs/s (wall {wall:.3f} s)")
+    log(f"{args.precision}: {ms_per_step:.4f} ms/step, {value:.4e} pairs/s (wall {wall:.3f} s)")
 
     # With one kernel per stage (the fused forms) or per run of steps (the
     # resident form) the timed region runs nothing but that kernel, back to

@@ -95,12 +95,11 @@ struct Dev {
     float2* pC2;
     double2* pD2;
     double* part;       /* partial sums */
-    double* H;          /* dense mode: per system the 3Nb x 3Nb pair tensor, column-major;
-                           AD_FP64 two-pass sum: per system the pair terms [ncomp][Nb][Nb] */
+    double* H;          /* dense mode: per system the 3Nb x 3Nb pair tensor, column-major */
     const Item* fitems; /* fused stages of an ensemble: (system, target block) items; the
-                           resident form: one per system; AD_FP64 two-pass sum: term tiles */
+                           resident form: one per system; AD_FP64 pair sum: target blocks */
     int nfitems;        /* 0: one system, blocks in order */
-    const long long* sys_hbase; /* [nsys] first element of the system's tensor or terms in H */
+    const long long* sys_hbase; /* [nsys] dense mode: first element of the system's tensor */
     const double* tab;  /* [ring][8] (sin, cos) of omega*t per epilogue stage */
     int ring;           /* entries in tab, a power of two (rows are step & (ring - 1)) */
     int Ntot, Stot, nsys, nitems;
@@ -237,9 +236,19 @@ __host__ __device__ inline int fused_wide_lds_bytes(int n, int split) {
     const int red = 4 * FW_I * 6 * 4 + FW_I * 3 * 8 + 16;
     return b > red ? b : red;
 }
-/* AD_FP64 term tiles of the two-pass pair sum: targets x sources */
-constexpr int TT_I = 16;
-constexpr int TT_J = 64;
+/* AD_FP64 pair sum with producer and consumer waves (k_pairs_f64w): LDS row
+ * stride in doubles (odd, so that the rows' reads of one column fall in
+ * different banks); producer waves per work-group (one, two and three
+ * measured at N = 512 to 8192: one was fastest everywhere, by 4 to 12 %);
+ * targets per work-group, about Ntot / 1024 from 1 to 4, so that the launch
+ * holds about two waves per SIMD */
+constexpr int F64W_RS = 65;
+constexpr int F64W_NP = 1;
+__host__ __device__ inline int f64w_targets(int Ntot) { return Ntot >= 4096 ? 4 : Ntot >= 2048 ? 2 : 1; }
+/* LDS of a work-group: two sets of F64W_NP chunk buffers of rows x F64W_RS */
+__host__ __device__ inline int f64w_lds_bytes(int tw, int rpy) {
+    return 2 * F64W_NP * (rpy ? 6 : 3) * tw * F64W_RS * 8;
+}
 /* the most target spheres per work-group of the streamed fused stage */
 constexpr int FT_I = 16;
 /* target spheres per work-group of the streamed fused stage for Ntot

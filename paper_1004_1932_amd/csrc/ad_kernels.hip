@@ -1738,93 +1738,127 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
     }
 }
 
-/* AD_FP64 in two passes, for systems whose pair terms fit a term buffer:
- * the terms of every ordered pair in parallel, then each (component,
- * target) row summed in ascending j. The terms are the plain sum's
- * expressions and the row sum is its sequence of additions, so the result
- * is bitwise k_pairs_f64's with one chunk per system. The self term and a
- * coincident pair (which raises the flag) are stored as +0.0 and added like
- * the others: a sum that starts at +0.0 is never -0.0 in round-to-nearest,
- * so adding +0.0 changes no bit of it. */
-/* pass 1: one tile of TT_I targets x TT_J sources per work-group of 256
- * threads (16 targets x 16 source lanes, 4 sources per lane); the terms go
- * to d.H as [component][source][target] per system (a target's row is then
- * read by the row sums with consecutive targets at consecutive addresses),
- * components 3-5 the RPY corrections */
-template <int RPY>
-__global__ __launch_bounds__(256) void k_terms_f64(Dev d, Epi e, int mode) {
-    const Item it = d.fitems[blockIdx.x];
-    if (mode) advance_slots(d, e);
-    const int t = threadIdx.x, ti = t >> 4, tj = t & 15;
-    const int Nb = it.Nb;
-    double* T = d.H + d.sys_hbase[it.sys];
-    const long long plane = (long long)Nb * Nb;
-    if (ti >= it.ni) return;
-    const int i = it.i0 + ti, li = i - it.ioff;
-    const double2 p0 = d.pD[3 * i], p1 = d.pD[3 * i + 1];
-    const double xi = p0.x, yi = p0.y, zi = p1.x;
-    int bad = 0;
-#pragma unroll
-    for (int u = 0; u < TT_J / 16; ++u) {
-        const int jj = tj + 16 * u;
-        if (jj >= it.nj) break;
-        const int j = it.j0 + jj, lj = j - it.ioff;
-        const double2 b0 = d.pD[3 * j], b1 = d.pD[3 * j + 1], b2 = d.pD[3 * j + 2];
-        const double Fx = b1.y, Fy = b2.x, Fz = b2.y;
-        const double rx = xi - b0.x;
-        const double ry = yi - b0.y;
-        const double rz = zi - b1.x;
-        const double r2 = (rx * rx + ry * ry) + rz * rz;
-        const bool self = j == i;
-        const bool skip = self || r2 == 0.0;
-        bad |= !self && r2 == 0.0;
-        const double r2s = skip ? 1.0 : r2;
-        const double ir = 1.0 / sqrt(r2s);
-        const double fr = (rx * Fx + ry * Fy) + rz * Fz;
-        const double tt = fr / r2s;
-        const long long o = (long long)lj * Nb + li;
-        T[o] = skip ? 0.0 : ir * (Fx + tt * rx);
-        T[plane + o] = skip ? 0.0 : ir * (Fy + tt * ry);
-        T[2 * plane + o] = skip ? 0.0 : ir * (Fz + tt * rz);
-        if (RPY) {
-            const double ir3 = ir / r2s;
-            const double t3 = 3.0 * tt;
-            T[3 * plane + o] = skip ? 0.0 : ir3 * (Fx - t3 * rx);
-            T[4 * plane + o] = skip ? 0.0 : ir3 * (Fy - t3 * ry);
-            T[5 * plane + o] = skip ? 0.0 : ir3 * (Fz - t3 * rz);
-        }
-    }
-    if (bad) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
+/* Work-group barrier that orders LDS only: vector-memory loads in flight
+ * (the step table's next row, the next chunk's sources) are not waited for. */
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-/* pass 2: one thread per (component, sphere): its row of terms added in
- * ascending j into the partial sum the epilogue reads (one chunk) */
-__global__ __launch_bounds__(256) void k_rowsum_f64(Dev d) {
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = d.Ntot;
-    if (q >= (long long)d.ncomp * N) return;
-    const int a = (int)(q / N), g = (int)(q - (long long)a * N);
-    const int b = d.dsys[g >> 1];
-    const int off = d.sys_off[b], Nb = d.sys_off[b + 1] - off, li = g - off;
-    const double* col = d.H + d.sys_hbase[b] + (long long)a * Nb * Nb + li; /* term j at col[j Nb] */
-    /* batches of 16 terms, the next batch's loads in flight while a batch is
-     * added; past the row's end a batch holds +0.0, which leaves the sum
-     * unchanged */
-    auto load = [&](double (&v)[16], int j0) {
+/* AD_FP64 in one kernel, with producer and consumer waves: a work-group owns
+ * TW targets of one system. Its NP producer waves form the pair terms of the
+ * system's sources in chunks of 64, one source per lane (the lane forms that
+ * source's terms for the TW targets), into LDS rows (component x TW +
+ * target) by columns (the chunk's sources); its consumer wave adds them,
+ * lane r row r, to a running sum in ascending j. Chunks go in rounds of NP,
+ * one per producer, through two sets of buffers: the producers form round
+ * m + 1 while the consumer adds round m, and one LDS barrier ends a round
+ * (one producer, F64W_NP, measured fastest).
+ * The terms are the plain sum's expressions and the additions its sequence,
+ * so the result is bitwise k_pairs_f64's with one chunk per system. The
+ * self term, a coincident pair (which raises the flag) and the padding past
+ * the system's last source are stored as +0.0 and added like the others: a
+ * sum that starts at +0.0 is never -0.0 in round-to-nearest, so adding +0.0
+ * changes no bit of it. The consumer's lanes past the last row repeat its
+ * reads and additions (the same LDS addresses, served once). */
+template <int TW, int NP, int RPY>
+__global__ __launch_bounds__(64 * (NP + 1)) void k_pairs_f64w(Dev d, Epi e, int mode) {
+    constexpr int NC = RPY ? 6 : 3;
+    constexpr int ROWS = NC * TW;
+    constexpr int BUF = ROWS * F64W_RS; /* doubles per chunk buffer */
+    extern __shared__ double w_lds[];   /* [2 sets][NP chunks][ROWS][F64W_RS] */
+    const Item it = d.fitems[blockIdx.x];
+    if (mode) advance_slots(d, e);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    const int Nb = it.Nb, off = it.ioff;
+    const int nch = (Nb + 63) / 64;
+    const int M = (nch + NP - 1) / NP; /* rounds */
+    if (w == 0) {
+        /* the consumer */
+        const int r = l < ROWS ? l : ROWS - 1;
+        double acc = 0.0;
+        lds_barrier();
+        for (int m = 0; m < M; ++m) {
+            const double* S = w_lds + (m & 1) * NP * BUF + r * F64W_RS;
+            for (int p = 0; p < NP && m * NP + p < nch; ++p) {
+                const double* Ta = S + p * BUF;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = j0 + u < Nb ? col[(long long)(j0 + u) * Nb] : 0.0;
-    };
-    double acc = 0.0, va[16], vb[16];
-    load(va, 0);
-    for (int j = 0; j < Nb; j += 32) {
-        load(vb, j + 16);
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc = acc + va[u];
-        load(va, j + 32);
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc = acc + vb[u];
+                for (int u = 0; u < 64; ++u) acc = acc + Ta[u];
+            }
+            lds_barrier();
+        }
+        if (l < ROWS) {
+            const int a = l / TW, q = l - a * TW;
+            if (q < it.ni) d.part[d.sys_pbase[it.sys] + (long long)a * Nb + (it.i0 + q - off)] = acc;
+        }
+        return;
     }
-    d.part[d.sys_pbase[b] + (long long)a * Nb + li] = acc;
+    /* producer p forms chunk m NP + p of every round m */
+    const int p = w - 1;
+    double xi[TW], yi[TW], zi[TW];
+    int iq[TW];
+    bool okq[TW];
+#pragma unroll
+    for (int q = 0; q < TW; ++q) {
+        okq[q] = q < it.ni;
+        iq[q] = it.i0 + (okq[q] ? q : 0);
+        const double2 p0 = d.pD[3 * iq[q]], p1 = d.pD[3 * iq[q] + 1];
+        xi[q] = p0.x; yi[q] = p0.y; zi[q] = p1.x;
+    }
+    int bad = 0;
+    double2 s0, s1, s2; /* the source of the next chunk to form */
+    auto load = [&](int k) {
+        const int lj = k * 64 + l;
+        const int j = off + (lj < Nb ? lj : Nb - 1);
+        s0 = d.pD[3 * j];
+        s1 = d.pD[3 * j + 1];
+        s2 = d.pD[3 * j + 2];
+    };
+    auto form = [&](int k, double* Tb) {
+        Tb += l;
+        const int lj = k * 64 + l;
+        const bool in = lj < Nb;
+        const int j = off + lj;
+        const double Fx = s1.y, Fy = s2.x, Fz = s2.y;
+#pragma unroll
+        for (int q = 0; q < TW; ++q) {
+            const double rx = xi[q] - s0.x;
+            const double ry = yi[q] - s0.y;
+            const double rz = zi[q] - s1.x;
+            const double r2 = (rx * rx + ry * ry) + rz * rz;
+            const bool self = j == iq[q];
+            const bool skip = !in || self || r2 == 0.0;
+            bad |= in && okq[q] && !self && r2 == 0.0;
+            const double r2s = skip ? 1.0 : r2;
+            const double ir = 1.0 / sqrt(r2s);
+            const double fr = (rx * Fx + ry * Fy) + rz * Fz;
+            const double tt = fr / r2s;
+            Tb[(0 * TW + q) * F64W_RS] = skip ? 0.0 : ir * (Fx + tt * rx);
+            Tb[(1 * TW + q) * F64W_RS] = skip ? 0.0 : ir * (Fy + tt * ry);
+            Tb[(2 * TW + q) * F64W_RS] = skip ? 0.0 : ir * (Fz + tt * rz);
+            if (RPY) {
+                const double ir3 = ir / r2s;
+                const double t3 = 3.0 * tt;
+                Tb[(3 * TW + q) * F64W_RS] = skip ? 0.0 : ir3 * (Fx - t3 * rx);
+                Tb[(4 * TW + q) * F64W_RS] = skip ? 0.0 : ir3 * (Fy - t3 * ry);
+                Tb[(5 * TW + q) * F64W_RS] = skip ? 0.0 : ir3 * (Fz - t3 * rz);
+            }
+        }
+    };
+    load(p);
+    form(p, w_lds + p * BUF);
+    load(NP + p);
+    lds_barrier();
+    for (int m = 0; m < M; ++m) {
+        if (m + 1 < M) {
+            form((m + 1) * NP + p, w_lds + (((m + 1) & 1) * NP + p) * BUF);
+            load((m + 2) * NP + p);
+        }
+        lds_barrier();
+    }
+    if (__any(bad) && l == 0) atomicOr(&d.ctl->flag, FLAG_NONFINITE);
 }
 
 /* Steric sum of sphere i over its candidate list (FP32C path). The list holds
@@ -2009,14 +2043,6 @@ __device__ __forceinline__ void combine_level_shfl(float v[6], int sh) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) o[q] = __shfl_xor(v[q], sh);
     combine_hilo(v, o);
-}
-
-/* Work-group barrier that orders LDS only: vector-memory loads in flight
- * (the step table's next row) are not waited for. */
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 /* FP64 (the plain sum, bitwise that of the sequential oracle): X, R, Y, F
@@ -2454,6 +2480,19 @@ static hipError_t f64_ten(const Dev& d, const Epi& e, const Shape& sh, int mode,
     return sh.rpy ? go(k_pairs_f64<WG, IPL, 1>, WG, d, e, mode, s, tm) : go(k_pairs_f64<WG, IPL, 0>, WG, d, e, mode, s, tm);
 }
 
+template <int TW>
+static hipError_t go_f64w(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, const Timing& tm) {
+    constexpr int NP = F64W_NP;
+    auto kern = sh.rpy ? k_pairs_f64w<TW, NP, 1> : k_pairs_f64w<TW, NP, 0>;
+    const size_t lds = f64w_lds_bytes(TW, sh.rpy);
+    const dim3 block(64 * (NP + 1));
+    if (tm.start)
+        hipExtLaunchKernelGGL(kern, dim3(d.nfitems), block, lds, s, tm.start, tm.stop, 0, d, e, mode);
+    else
+        hipLaunchKernelGGL(kern, dim3(d.nfitems), block, lds, s, d, e, mode);
+    return hipGetLastError();
+}
+
 hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
     if (d.nitems <= 0) return hipSuccess;
@@ -2465,22 +2504,12 @@ hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, h
         if (sh.wg == 256 && sh.wj == 4) return f32c_ten<256, 4>(d, e, sh, mode, s, tm);
         return hipErrorInvalidValue;
     }
-    /* AD_FP64 with a term buffer: the two passes */
-    if (e.prec == PREC_FP64 && d.H && d.nfitems > 0) {
-        auto kt = sh.rpy ? k_terms_f64<1> : k_terms_f64<0>;
-        if (tm.start)
-            hipExtLaunchKernelGGL(kt, dim3(d.nfitems), dim3(256), 0, s, tm.start, nullptr, 0, d, e, mode);
-        else
-            hipLaunchKernelGGL(kt, dim3(d.nfitems), dim3(256), 0, s, d, e, mode);
-        const hipError_t err = hipGetLastError();
-        if (err != hipSuccess) return err;
-        const long long rows = (long long)d.ncomp * d.Ntot;
-        const dim3 grid((unsigned)((rows + 255) / 256));
-        if (tm.start)
-            hipExtLaunchKernelGGL(k_rowsum_f64, grid, dim3(256), 0, s, nullptr, tm.stop, 0, d);
-        else
-            hipLaunchKernelGGL(k_rowsum_f64, grid, dim3(256), 0, s, d);
-        return hipGetLastError();
+    /* AD_FP64: the terms spread over waves (work list of target blocks) */
+    if (e.prec == PREC_FP64 && d.nfitems > 0) {
+        const int tw = f64w_targets(d.Ntot);
+        if (tw == 4) return go_f64w<4>(d, e, sh, mode, s, tm);
+        if (tw == 2) return go_f64w<2>(d, e, sh, mode, s, tm);
+        return go_f64w<1>(d, e, sh, mode, s, tm);
     }
     /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group; the
      * work list was built for this shape, so anything else is refused */

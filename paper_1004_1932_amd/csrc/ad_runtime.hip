@@ -32,8 +32,6 @@ constexpr int kTabSteps = 4096;          /* steps per table chunk */
 constexpr int kGraphSteps[] = {16, 4, 1};
 constexpr int kGraphs = 3;
 constexpr int kRing = 2 * kTabSteps;     /* table entries (two chunks) */
-/* AD_FP64: the largest term buffer of the two-pass pair sum */
-constexpr long long kTermBytes = 1LL << 30;
 static_assert((kRing & (kRing - 1)) == 0, "the kernels take table rows as step & (ring - 1)");
 
 /* message of the last failure of a context-free call on this thread
@@ -59,10 +57,10 @@ struct ad_ctx {
     std::vector<int32_t> sysP;
     std::vector<long long> pbase;
     long long npart = 0;
-    std::vector<long long> hbase; /* dense mode or AD_FP64 two-pass sum: first element per system in H */
+    std::vector<long long> hbase; /* dense mode: first tensor element per system */
     std::vector<Item> fitems;     /* fused stages of an ensemble: (system, target block) */
     bool fused_ready = false;     /* the fused kernels may use all of LDS */
-    long long nH = 0;             /* elements of H (dense tensors or AD_FP64 pair terms) */
+    long long nH = 0;             /* dense mode: tensor elements over all systems */
     int maxNb = 0;
 
     /* workspace */
@@ -345,34 +343,27 @@ static void build_items(ad_ctx* c) {
         }
     }
     c->npart = pb;
-    /* AD_FP64 with two kernels per stage: the pair terms of every system in
-     * a term buffer, when they fit kTermBytes, computed in tiles of
-     * TT_I x TT_J and summed row by row (ad_kernels.hip, k_terms_f64) */
+    /* AD_FP64 with two kernels per stage: the pair sum's work list, blocks of
+     * TW targets (one work-group each), longest system first (ad_kernels.hip,
+     * k_pairs_f64w) */
     c->fitems.clear();
     if (c->p.precision == AD_FP64 && L.fused == 0) {
-        long long terms = 0;
-        for (int b = 0; b < c->nsys; ++b) terms += (long long)NC * (2LL * c->S[b]) * (2LL * c->S[b]);
-        if (terms * 8 <= kTermBytes) {
-            long long hb = 0;
-            for (int b = 0; b < c->nsys; ++b) {
-                const int Nb = 2 * c->S[b];
-                c->hbase[b] = hb;
-                hb += (long long)NC * Nb * Nb;
-                for (int i = 0; i < Nb; i += ad::TT_I)
-                    for (int j = 0; j < Nb; j += ad::TT_J) {
-                        Item it{};
-                        it.sys = b;
-                        it.i0 = c->off[b] + i;
-                        it.ni = std::min(ad::TT_I, Nb - i);
-                        it.j0 = c->off[b] + j;
-                        it.nj = std::min(ad::TT_J, Nb - j);
-                        it.ioff = c->off[b];
-                        it.Nb = Nb;
-                        c->fitems.push_back(it);
-                    }
+        const int tb = ad::f64w_targets(c->Ntot);
+        for (int b = 0; b < c->nsys; ++b) {
+            const int Nb = 2 * c->S[b];
+            for (int i = 0; i < Nb; i += tb) {
+                Item it{};
+                it.sys = b;
+                it.i0 = c->off[b] + i;
+                it.ni = std::min(tb, Nb - i);
+                it.j0 = c->off[b];
+                it.nj = Nb;
+                it.ioff = c->off[b];
+                it.Nb = Nb;
+                c->fitems.push_back(it);
             }
-            c->nH = hb;
         }
+        std::stable_sort(c->fitems.begin(), c->fitems.end(), [](const Item& x, const Item& y) { return x.Nb > y.Nb; });
     }
     /* fused stages: one item per target block of a system (16 targets for an
      * ensemble in the first and the streamed form, 64 in the wide form, for

@@ -519,6 +519,42 @@ def test_rpy_trajectory_fp64_bitwise(oracle):
     assert np.array_equal(com.cpu().numpy(), mo)
 
 
+# The plain FP64 pair sum runs 1, 2 or 4 targets per work-group (one system
+# of 4100 spheres: 4; ensembles of 2048 to 4095 spheres: 2, of 4096 and more:
+# 4, with odd dumbbell counts leaving part-filled blocks); 64-source chunks,
+# the last one part-filled.
+@pytest.mark.parametrize("tensor", [0, 1])
+@pytest.mark.parametrize("sizes", [[2050], [1, 3, 1025, 999, 33], [7, 1000, 61]])
+def test_fp64_pair_sum_block_shapes_bitwise(oracle, sizes, tensor):
+    _torch()
+    say(f"fp64 pair sum sizes={sizes} tensor={tensor}")
+    sizes = np.array(sizes, dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    F = np.random.default_rng(21).standard_normal(ens.X.shape)
+    s = P.Simulator(ens.params, sizes, precision="fp64", tensor="rpy" if tensor else "oseen")
+    u = s.mobility(ens.X, F).cpu().numpy()
+    off = ens.sphere_offsets
+    for b in range(len(sizes)):
+        sl = slice(off[b], off[b + 1])
+        assert np.array_equal(u[sl], oracle.mobility(ens.params, ens.X[sl], F[sl], tensor=tensor)), f"system {b}"
+
+
+def test_fp64_pair_sum_four_target_blocks_trajectory(oracle):
+    """Stepping through the 4-target blocks (part-filled ones included):
+    3 RK4 steps bitwise, and the records."""
+    _torch()
+    sizes = np.array([1, 3, 1025, 999, 33], dtype=np.int32)
+    ens = make_ensemble(nsys=len(sizes), sizes=sizes)
+    say("fp64 pair sum, 4-target blocks, 3 steps")
+    s = P.Simulator(ens.params, sizes, precision="fp64", graph=True)
+    s.set_state(ens.X, ens.phi)
+    cen, com, code = s.run(3, 1)
+    assert code == 0
+    Xo, co, mo, _ = oracle.run(ens.params, ens.X, ens.phi, 3, record_every=1, S_per_sys=sizes)
+    assert np.array_equal(s.get_state()[0].cpu().numpy(), Xo)
+    assert np.array_equal(com.cpu().numpy(), mo)
+
+
 @pytest.mark.parametrize("precision,launch", [("fp64_tiled", None), ("fp32c", None),
                                               ("fp32c", dict(wg=256, wj=4, ipl=2, jchunk=512, posmode=2)),
                                               ("fp32c", dict(wg=64, wj=1, ipl=4, jchunk=128))])
