@@ -100,7 +100,11 @@ typedef struct ad_params {
 
 /* Launch shape of the pair kernel. Zero fields mean "library default for
  * this size". A work-group of wg threads holds wg/64/wj waves on distinct
- * target spheres (ipl per lane) and wj waves that split every j-tile. */
+ * target spheres (ipl per lane) and wj waves that split every j-tile.
+ * AD_FP64 with fused = 0 validates ipl, jchunk, wg and wj but its pair
+ * kernel does not use them: a work-group of a producer and a consumer wave
+ * per 1, 2 or 4 target spheres (about N_total / 1024), every source of the
+ * system in ascending order. */
 typedef struct ad_launch {
     int32_t ipl;      /* target spheres per lane: 1, 2 or 4 (FP64 modes: 1 or 2; dense: 1) */
     int32_t jchunk;   /* source spheres per work-group, >= 64 (AD_FP64: whole system;
