@@ -1637,8 +1637,10 @@ __global__ __launch_bounds__(1024) void k_stage_stream64(Dev d, Epi e) {
  *   t = fr/r2; acc = acc + ir*(F + t*r)
  * over every j != i of the chunk (partner included). A coincident pair is
  * skipped and raises the flag. With one chunk per system this is the
- * sequential FP64 sum exactly. With RPY the correction
- * (F - 3 t r) ir/r2 is summed in a second accumulator. */
+ * sequential FP64 sum exactly (the form AD_FP64 takes in the allocation-free
+ * mobility call; a context's AD_FP64 runs k_pairs_f64w); AD_FP64_TILED runs
+ * several chunks. With RPY the correction (F - 3 t r) ir/r2 is summed in a
+ * second accumulator. */
 template <int WG, int IPL, int RPY>
 __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
     __shared__ double2 sD[3][WG];
@@ -1738,6 +1740,41 @@ __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
     }
 }
 
+/* Correctly rounded FP64 square root and division in their short forms.
+ * The compiler's forms of sqrt(x) and a / b scale the operands' exponents
+ * where an intermediate could leave the normal range and fix up special
+ * operands (zero, infinity, NaN) afterwards; between those steps they are
+ * exactly these instruction sequences (the square root: v_rsq_f64 refined
+ * by Newton steps on g = sqrt(x) and h = 1 / (2 sqrt(x)); the division:
+ * v_rcp_f64 refined twice, then the quotient corrected once by its
+ * residual). For operands where no scaling or fixup applies they give the
+ * same bits, which f64_plain_range guarantees with a wide margin: every
+ * operand in [2^-400, 2^400], so that no intermediate gets near the ends of
+ * the exponent range. */
+__device__ __forceinline__ bool f64_plain_range(double x) { return x >= 0x1p-400 && x <= 0x1p400; }
+__device__ __forceinline__ double sqrt_plain(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double h = y * 0.5;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, x);
+    return __builtin_fma(d, h, g);
+}
+__device__ __forceinline__ double div_plain(double a, double b) {
+    double y = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    const double q = a * y;
+    const double r = __builtin_fma(-b, q, a);
+    return __builtin_fma(r, y, q);
+}
+
 /* Work-group barrier that orders LDS only: vector-memory loads in flight
  * (the step table's next row, the next chunk's sources) are not waited for. */
 __device__ __forceinline__ void lds_barrier() {
@@ -1822,28 +1859,43 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_pairs_f64w(Dev d, Epi e, int 
         const bool in = lj < Nb;
         const int j = off + lj;
         const double Fx = s1.y, Fy = s2.x, Fz = s2.y;
+        double rx[TW], ry[TW], rz[TW], r2s[TW], ir[TW];
+        bool skip[TW];
+        int safe = 1;
 #pragma unroll
         for (int q = 0; q < TW; ++q) {
-            const double rx = xi[q] - s0.x;
-            const double ry = yi[q] - s0.y;
-            const double rz = zi[q] - s1.x;
-            const double r2 = (rx * rx + ry * ry) + rz * rz;
+            rx[q] = xi[q] - s0.x;
+            ry[q] = yi[q] - s0.y;
+            rz[q] = zi[q] - s1.x;
+            const double r2 = (rx[q] * rx[q] + ry[q] * ry[q]) + rz[q] * rz[q];
             const bool self = j == iq[q];
-            const bool skip = !in || self || r2 == 0.0;
+            skip[q] = !in || self || r2 == 0.0;
             bad |= in && okq[q] && !self && r2 == 0.0;
-            const double r2s = skip ? 1.0 : r2;
-            const double ir = 1.0 / sqrt(r2s);
-            const double fr = (rx * Fx + ry * Fy) + rz * Fz;
-            const double tt = fr / r2s;
-            Tb[(0 * TW + q) * F64W_RS] = skip ? 0.0 : ir * (Fx + tt * rx);
-            Tb[(1 * TW + q) * F64W_RS] = skip ? 0.0 : ir * (Fy + tt * ry);
-            Tb[(2 * TW + q) * F64W_RS] = skip ? 0.0 : ir * (Fz + tt * rz);
+            r2s[q] = skip[q] ? 1.0 : r2;
+            safe &= f64_plain_range(r2s[q]);
+        }
+        /* 1/sqrt(r2): the short forms when every lane's r2 allows them (any
+         * physical configuration), else the library's */
+        if (__all(safe)) {
+#pragma unroll
+            for (int q = 0; q < TW; ++q) ir[q] = div_plain(1.0, sqrt_plain(r2s[q]));
+        } else {
+#pragma unroll
+            for (int q = 0; q < TW; ++q) ir[q] = 1.0 / sqrt(r2s[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < TW; ++q) {
+            const double fr = (rx[q] * Fx + ry[q] * Fy) + rz[q] * Fz;
+            const double tt = fr / r2s[q];
+            Tb[(0 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir[q] * (Fx + tt * rx[q]);
+            Tb[(1 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir[q] * (Fy + tt * ry[q]);
+            Tb[(2 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir[q] * (Fz + tt * rz[q]);
             if (RPY) {
-                const double ir3 = ir / r2s;
+                const double ir3 = ir[q] / r2s[q];
                 const double t3 = 3.0 * tt;
-                Tb[(3 * TW + q) * F64W_RS] = skip ? 0.0 : ir3 * (Fx - t3 * rx);
-                Tb[(4 * TW + q) * F64W_RS] = skip ? 0.0 : ir3 * (Fy - t3 * ry);
-                Tb[(5 * TW + q) * F64W_RS] = skip ? 0.0 : ir3 * (Fz - t3 * rz);
+                Tb[(3 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir3 * (Fx - t3 * rx[q]);
+                Tb[(4 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir3 * (Fy - t3 * ry[q]);
+                Tb[(5 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir3 * (Fz - t3 * rz[q]);
             }
         }
     };
