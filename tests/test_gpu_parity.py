@@ -539,6 +539,34 @@ def test_fp64_pair_sum_block_shapes_bitwise(oracle, sizes, tensor):
         assert np.array_equal(u[sl], oracle.mobility(ens.params, ens.X[sl], F[sl], tensor=tensor)), f"system {b}"
 
 
+# The producer takes short forms of 1/sqrt(r2) only when every r2 of its chunk
+# lies in [2^-400, 2^400]; a chunk with any pair outside takes the library's.
+# Both must give the oracle's bits: systems scaled far below and above that
+# range, and a near-coincident pair (1e-61 apart) in an otherwise plain one.
+@pytest.mark.parametrize("tensor", [0, 1])
+@pytest.mark.parametrize("case", ["tiny", "huge", "near_pair"])
+def test_fp64_pair_sum_outside_short_form_range_bitwise(oracle, case, tensor):
+    _torch()
+    say(f"fp64 pair sum outside the short-form range: {case} tensor={tensor}")
+    S = 2050 if case == "near_pair" else 300
+    sus = make_single(S, 240.0 if case == "near_pair" else 90.0, 31)
+    X = sus.X.copy()
+    F = np.random.default_rng(32).standard_normal(X.shape)
+    if case == "tiny":
+        X *= 1e-62
+    elif case == "huge":
+        X *= 1e62
+    else:
+        # near the origin, where 1e-61 is representable beside the coordinates
+        X[3001] = np.array([1e-59, 2e-59, -1e-59])
+        X[1000] = X[3001] + np.array([1e-61, -2e-61, 0.5e-61])
+    s = P.Simulator(sus.params, [S], precision="fp64", tensor="rpy" if tensor else "oseen")
+    u = s.mobility(X, F).cpu().numpy()
+    uo = oracle.mobility(sus.params, X, F, tensor=tensor)
+    assert np.isfinite(uo).all()
+    assert np.array_equal(u, uo)
+
+
 def test_fp64_pair_sum_four_target_blocks_trajectory(oracle):
     """Stepping through the 4-target blocks (part-filled ones included):
     3 RK4 steps bitwise, and the records."""
