@@ -367,6 +367,22 @@ def main():
         sims.close()
         del sims
 
+    # FP64 with the oracle's sum order (bitwise equal to it), the library's
+    # tuned form for this size
+    bitwise64 = None
+    if args.precision == "fp32c":
+        simb = P.Simulator(w.params, sizes, precision="fp64", graph=not args.no_graph, launch="tuned", **model)
+        simb.set_state(w.X, w.phi)
+        secsb, _ = time_steps(simb, fp64_steps, max(1, fp64_steps // 10))
+        assert simb.check() == 0
+        vb = pairs_per_step * fp64_steps / secsb
+        log(f"fp64 bitwise: {secsb / fp64_steps * 1e3:.4f} ms/step, {vb:.4e} pairs/s")
+        bitwise64 = {"value": vb, "unit": "pair interactions/s", "ms_per_step": secsb / fp64_steps * 1e3,
+                     "steps": fp64_steps, "launch": simb.launch,
+                     "form": "FP64 summed in ascending source order, bitwise equal to the oracle"}
+        simb.close()
+        del simb
+
     # the paper's own design: assembled full tensor, then the product (Sec. V);
     # per step 4 stages, each tensor written once and read once
     dense_bytes = 4 * 2 * 72.0 * float((Nb * Nb).sum())
@@ -448,6 +464,8 @@ def main():
         "speedup_vs_fp64": value / v64,
         "fp64_streamed": stream64,
         "speedup_vs_fp64_streamed": value / stream64["value"] if stream64 else None,
+        "fp64_bitwise": bitwise64,
+        "speedup_vs_fp64_bitwise": value / bitwise64["value"] if bitwise64 else None,
         "fp64_dense": dense,
         "speedup_vs_dense": value / dense["value"] if dense else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
