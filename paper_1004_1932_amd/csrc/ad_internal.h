@@ -236,18 +236,20 @@ __host__ __device__ inline int fused_wide_lds_bytes(int n, int split) {
     const int red = 4 * FW_I * 6 * 4 + FW_I * 3 * 8 + 16;
     return b > red ? b : red;
 }
-/* AD_FP64 pair sum with producer and consumer waves (k_pairs_f64w): LDS row
- * stride in doubles (odd, so that the rows' reads of one column fall in
- * different banks); producer waves per work-group (one, two and three
- * measured at N = 512 to 8192: one was fastest everywhere, by 4 to 12 %);
- * targets per work-group, about Ntot / 1024 from 1 to 4, so that the launch
- * holds about two waves per SIMD */
-constexpr int F64W_RS = 65;
+/* AD_FP64 pair sum with producer and consumer waves (k_pairs_f64w):
+ * producer waves per work-group (one, two and three measured at N = 512 to
+ * 8192: one was fastest everywhere, by 4 to 12 %); targets per work-group,
+ * about Ntot / 1024 from 1 to 4, so that the launch holds about two waves per
+ * SIMD; sources per chunk: 128 where a launch of 4-target work-groups holds
+ * at most one producer wave per SIMD (Ntot below 8192: 7 % faster at 4096,
+ * more independent terms per lane), else 64 (at 8192 the larger chunk's
+ * registers cost a wave per SIMD, 48 % slower) */
 constexpr int F64W_NP = 1;
 __host__ __device__ inline int f64w_targets(int Ntot) { return Ntot >= 4096 ? 4 : Ntot >= 2048 ? 2 : 1; }
-/* LDS of a work-group: two sets of F64W_NP chunk buffers of rows x F64W_RS */
-__host__ __device__ inline int f64w_lds_bytes(int tw, int rpy) {
-    return 2 * F64W_NP * (rpy ? 6 : 3) * tw * F64W_RS * 8;
+__host__ __device__ inline int f64w_chunk(int Ntot) { return f64w_targets(Ntot) == 4 && Ntot < 8192 ? 128 : 64; }
+/* LDS of a work-group: two sets of F64W_NP chunk buffers of rows x (cw + 1) */
+__host__ __device__ inline int f64w_lds_bytes(int tw, int rpy, int cw) {
+    return 2 * F64W_NP * (rpy ? 6 : 3) * tw * (cw + 1) * 8;
 }
 /* the most target spheres per work-group of the streamed fused stage */
 constexpr int FT_I = 16;

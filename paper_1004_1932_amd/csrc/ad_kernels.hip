@@ -1785,8 +1785,8 @@ __device__ __forceinline__ void lds_barrier() {
 
 /* AD_FP64 in one kernel, with producer and consumer waves: a work-group owns
  * TW targets of one system. Its NP producer waves form the pair terms of the
- * system's sources in chunks of 64, one source per lane (the lane forms that
- * source's terms for the TW targets), into LDS rows (component x TW +
+ * system's sources in chunks of CW (64 or 128; a lane forms the terms of
+ * sources l, l + 64, ... for the TW targets), into LDS rows (component x TW +
  * target) by columns (the chunk's sources); its consumer wave adds them,
  * lane r row r, to a running sum in ascending j. Chunks go in rounds of NP,
  * one per producer, through two sets of buffers: the producers form round
@@ -1799,18 +1799,20 @@ __device__ __forceinline__ void lds_barrier() {
  * sum that starts at +0.0 is never -0.0 in round-to-nearest, so adding +0.0
  * changes no bit of it. The consumer's lanes past the last row repeat its
  * reads and additions (the same LDS addresses, served once). */
-template <int TW, int NP, int RPY>
+template <int TW, int NP, int CW, int RPY>
 __global__ __launch_bounds__(64 * (NP + 1)) void k_pairs_f64w(Dev d, Epi e, int mode) {
     constexpr int NC = RPY ? 6 : 3;
     constexpr int ROWS = NC * TW;
-    constexpr int BUF = ROWS * F64W_RS; /* doubles per chunk buffer */
-    extern __shared__ double w_lds[];   /* [2 sets][NP chunks][ROWS][F64W_RS] */
+    constexpr int RS = CW + 1;          /* LDS row stride in doubles: odd, so the rows' reads of one
+                                           column fall in different banks */
+    constexpr int BUF = ROWS * RS; /* doubles per chunk buffer */
+    extern __shared__ double w_lds[];   /* [2 sets][NP chunks][ROWS][RS] */
     const Item it = d.fitems[blockIdx.x];
     if (mode) advance_slots(d, e);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
     const int Nb = it.Nb, off = it.ioff;
-    const int nch = (Nb + 63) / 64;
+    const int nch = (Nb + CW - 1) / CW;
     const int M = (nch + NP - 1) / NP; /* rounds */
     if (w == 0) {
         /* the consumer */
@@ -1818,11 +1820,11 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_pairs_f64w(Dev d, Epi e, int 
         double acc = 0.0;
         lds_barrier();
         for (int m = 0; m < M; ++m) {
-            const double* S = w_lds + (m & 1) * NP * BUF + r * F64W_RS;
+            const double* S = w_lds + (m & 1) * NP * BUF + r * RS;
             for (int p = 0; p < NP && m * NP + p < nch; ++p) {
                 const double* Ta = S + p * BUF;
 #pragma unroll
-                for (int u = 0; u < 64; ++u) acc = acc + Ta[u];
+                for (int u = 0; u < CW; ++u) acc = acc + Ta[u];
             }
             lds_barrier();
         }
@@ -1845,57 +1847,69 @@ __global__ __launch_bounds__(64 * (NP + 1)) void k_pairs_f64w(Dev d, Epi e, int 
         xi[q] = p0.x; yi[q] = p0.y; zi[q] = p1.x;
     }
     int bad = 0;
-    double2 s0, s1, s2; /* the source of the next chunk to form */
+    constexpr int U = CW / 64; /* sources per lane and chunk */
+    double2 s0[U], s1[U], s2[U]; /* the sources of the next chunk to form */
     auto load = [&](int k) {
-        const int lj = k * 64 + l;
-        const int j = off + (lj < Nb ? lj : Nb - 1);
-        s0 = d.pD[3 * j];
-        s1 = d.pD[3 * j + 1];
-        s2 = d.pD[3 * j + 2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int lj = k * CW + u * 64 + l;
+            const int j = off + (lj < Nb ? lj : Nb - 1);
+            s0[u] = d.pD[3 * j];
+            s1[u] = d.pD[3 * j + 1];
+            s2[u] = d.pD[3 * j + 2];
+        }
     };
-    auto form = [&](int k, double* Tb) {
-        Tb += l;
-        const int lj = k * 64 + l;
-        const bool in = lj < Nb;
-        const int j = off + lj;
-        const double Fx = s1.y, Fy = s2.x, Fz = s2.y;
-        double rx[TW], ry[TW], rz[TW], r2s[TW], ir[TW];
-        bool skip[TW];
+    auto form = [&](int k, double* Tb0) {
+        double rx[U][TW], ry[U][TW], rz[U][TW], r2s[U][TW], ir[U][TW];
+        bool skip[U][TW];
         int safe = 1;
 #pragma unroll
-        for (int q = 0; q < TW; ++q) {
-            rx[q] = xi[q] - s0.x;
-            ry[q] = yi[q] - s0.y;
-            rz[q] = zi[q] - s1.x;
-            const double r2 = (rx[q] * rx[q] + ry[q] * ry[q]) + rz[q] * rz[q];
-            const bool self = j == iq[q];
-            skip[q] = !in || self || r2 == 0.0;
-            bad |= in && okq[q] && !self && r2 == 0.0;
-            r2s[q] = skip[q] ? 1.0 : r2;
-            safe &= f64_plain_range(r2s[q]);
+        for (int u = 0; u < U; ++u) {
+            const int lj = k * CW + u * 64 + l;
+            const bool in = lj < Nb;
+            const int j = off + lj;
+#pragma unroll
+            for (int q = 0; q < TW; ++q) {
+                rx[u][q] = xi[q] - s0[u].x;
+                ry[u][q] = yi[q] - s0[u].y;
+                rz[u][q] = zi[q] - s1[u].x;
+                const double r2 = (rx[u][q] * rx[u][q] + ry[u][q] * ry[u][q]) + rz[u][q] * rz[u][q];
+                const bool self = j == iq[q];
+                skip[u][q] = !in || self || r2 == 0.0;
+                bad |= in && okq[q] && !self && r2 == 0.0;
+                r2s[u][q] = skip[u][q] ? 1.0 : r2;
+                safe &= f64_plain_range(r2s[u][q]);
+            }
         }
-        /* 1/sqrt(r2): the short forms when every lane's r2 allows them (any
-         * physical configuration), else the library's */
         if (__all(safe)) {
 #pragma unroll
-            for (int q = 0; q < TW; ++q) ir[q] = div_plain(1.0, sqrt_plain(r2s[q]));
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < TW; ++q) ir[u][q] = div_plain(1.0, sqrt_plain(r2s[u][q]));
         } else {
 #pragma unroll
-            for (int q = 0; q < TW; ++q) ir[q] = 1.0 / sqrt(r2s[q]);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < TW; ++q) ir[u][q] = 1.0 / sqrt(r2s[u][q]);
         }
 #pragma unroll
-        for (int q = 0; q < TW; ++q) {
-            const double fr = (rx[q] * Fx + ry[q] * Fy) + rz[q] * Fz;
-            const double tt = fr / r2s[q];
-            Tb[(0 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir[q] * (Fx + tt * rx[q]);
-            Tb[(1 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir[q] * (Fy + tt * ry[q]);
-            Tb[(2 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir[q] * (Fz + tt * rz[q]);
-            if (RPY) {
-                const double ir3 = ir[q] / r2s[q];
-                const double t3 = 3.0 * tt;
-                Tb[(3 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir3 * (Fx - t3 * rx[q]);
-                Tb[(4 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir3 * (Fy - t3 * ry[q]);
-                Tb[(5 * TW + q) * F64W_RS] = skip[q] ? 0.0 : ir3 * (Fz - t3 * rz[q]);
+        for (int u = 0; u < U; ++u) {
+            double* Tb = Tb0 + u * 64 + l;
+            const double Fx = s1[u].y, Fy = s2[u].x, Fz = s2[u].y;
+#pragma unroll
+            for (int q = 0; q < TW; ++q) {
+                const double fr = (rx[u][q] * Fx + ry[u][q] * Fy) + rz[u][q] * Fz;
+                const double tt = fr / r2s[u][q];
+                Tb[(0 * TW + q) * RS] = skip[u][q] ? 0.0 : ir[u][q] * (Fx + tt * rx[u][q]);
+                Tb[(1 * TW + q) * RS] = skip[u][q] ? 0.0 : ir[u][q] * (Fy + tt * ry[u][q]);
+                Tb[(2 * TW + q) * RS] = skip[u][q] ? 0.0 : ir[u][q] * (Fz + tt * rz[u][q]);
+                if (RPY) {
+                    const double ir3 = ir[u][q] / r2s[u][q];
+                    const double t3 = 3.0 * tt;
+                    Tb[(3 * TW + q) * RS] = skip[u][q] ? 0.0 : ir3 * (Fx - t3 * rx[u][q]);
+                    Tb[(4 * TW + q) * RS] = skip[u][q] ? 0.0 : ir3 * (Fy - t3 * ry[u][q]);
+                    Tb[(5 * TW + q) * RS] = skip[u][q] ? 0.0 : ir3 * (Fz - t3 * rz[u][q]);
+                }
             }
         }
     };
@@ -2532,11 +2546,11 @@ static hipError_t f64_ten(const Dev& d, const Epi& e, const Shape& sh, int mode,
     return sh.rpy ? go(k_pairs_f64<WG, IPL, 1>, WG, d, e, mode, s, tm) : go(k_pairs_f64<WG, IPL, 0>, WG, d, e, mode, s, tm);
 }
 
-template <int TW>
+template <int TW, int CW>
 static hipError_t go_f64w(const Dev& d, const Epi& e, const Shape& sh, int mode, hipStream_t s, const Timing& tm) {
     constexpr int NP = F64W_NP;
-    auto kern = sh.rpy ? k_pairs_f64w<TW, NP, 1> : k_pairs_f64w<TW, NP, 0>;
-    const size_t lds = f64w_lds_bytes(TW, sh.rpy);
+    auto kern = sh.rpy ? k_pairs_f64w<TW, NP, CW, 1> : k_pairs_f64w<TW, NP, CW, 0>;
+    const size_t lds = f64w_lds_bytes(TW, sh.rpy, CW);
     const dim3 block(64 * (NP + 1));
     if (tm.start)
         hipExtLaunchKernelGGL(kern, dim3(d.nfitems), block, lds, s, tm.start, tm.stop, 0, d, e, mode);
@@ -2559,9 +2573,11 @@ hipError_t launch_pairs(const Dev& d, const Epi& e, const Shape& sh, int mode, h
     /* AD_FP64: the terms spread over waves (work list of target blocks) */
     if (e.prec == PREC_FP64 && d.nfitems > 0) {
         const int tw = f64w_targets(d.Ntot);
-        if (tw == 4) return go_f64w<4>(d, e, sh, mode, s, tm);
-        if (tw == 2) return go_f64w<2>(d, e, sh, mode, s, tm);
-        return go_f64w<1>(d, e, sh, mode, s, tm);
+        if (tw == 4)
+            return f64w_chunk(d.Ntot) == 128 ? go_f64w<4, 128>(d, e, sh, mode, s, tm)
+                                             : go_f64w<4, 64>(d, e, sh, mode, s, tm);
+        if (tw == 2) return go_f64w<2, 64>(d, e, sh, mode, s, tm);
+        return go_f64w<1, 64>(d, e, sh, mode, s, tm);
     }
     /* FP64 kernels: 1 or 2 targets per lane, no j split inside a group; the
      * work list was built for this shape, so anything else is refused */

@@ -521,10 +521,10 @@ def test_rpy_trajectory_fp64_bitwise(oracle):
 
 # The plain FP64 pair sum runs 1, 2 or 4 targets per work-group (one system
 # of 4100 spheres: 4; ensembles of 2048 to 4095 spheres: 2, of 4096 and more:
-# 4, with odd dumbbell counts leaving part-filled blocks); 64-source chunks,
-# the last one part-filled.
+# 4, with odd dumbbell counts leaving part-filled blocks), in chunks of 128
+# sources (4 targets, fewer than 8192 spheres) or 64, the last one part-filled.
 @pytest.mark.parametrize("tensor", [0, 1])
-@pytest.mark.parametrize("sizes", [[2050], [1, 3, 1025, 999, 33], [7, 1000, 61]])
+@pytest.mark.parametrize("sizes", [[2050], [1, 3, 1025, 999, 33], [7, 1000, 61], [4100, 7]])
 def test_fp64_pair_sum_block_shapes_bitwise(oracle, sizes, tensor):
     _torch()
     say(f"fp64 pair sum sizes={sizes} tensor={tensor}")
@@ -565,6 +565,21 @@ def test_fp64_pair_sum_outside_short_form_range_bitwise(oracle, case, tensor):
     uo = oracle.mobility(sus.params, X, F, tensor=tensor)
     assert np.isfinite(uo).all()
     assert np.array_equal(u, uo)
+
+
+def test_fp64_bitwise_full_n4096_tuned(oracle):
+    """The 4096-sphere workload in the bench's bitwise-FP64 configuration
+    (launch "tuned"): 2 RK4 steps bitwise, and the records."""
+    _torch()
+    sus = make_preset("n4096")
+    say("fp64 bitwise n4096 tuned, 2 steps")
+    s = P.Simulator(sus.params, [sus.S], precision="fp64", launch="tuned", graph=True)
+    s.set_state(sus.X, sus.phi)
+    cen, com, code = s.run(2, 1)
+    assert code == 0
+    Xo, co, mo, _ = oracle.run(sus.params, sus.X, sus.phi, 2, record_every=1)
+    assert np.array_equal(s.get_state()[0].cpu().numpy(), Xo)
+    assert np.array_equal(com.cpu().numpy(), mo)
 
 
 def test_fp64_pair_sum_four_target_blocks_trajectory(oracle):
