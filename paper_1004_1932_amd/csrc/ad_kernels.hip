@@ -1637,10 +1637,9 @@ __global__ __launch_bounds__(1024) void k_stage_stream64(Dev d, Epi e) {
  *   t = fr/r2; acc = acc + ir*(F + t*r)
  * over every j != i of the chunk (partner included). A coincident pair is
  * skipped and raises the flag. With one chunk per system this is the
- * sequential FP64 sum exactly (the form AD_FP64 takes in the allocation-free
- * mobility call; a context's AD_FP64 runs k_pairs_f64w); AD_FP64_TILED runs
- * several chunks. With RPY the correction (F - 3 t r) ir/r2 is summed in a
- * second accumulator. */
+ * sequential FP64 sum exactly (AD_FP64 runs k_pairs_f64w, which gives the
+ * same bits); AD_FP64_TILED runs several chunks. With RPY the correction
+ * (F - 3 t r) ir/r2 is summed in a second accumulator. */
 template <int WG, int IPL, int RPY>
 __global__ __launch_bounds__(WG) void k_pairs_f64(Dev d, Epi e, int mode) {
     __shared__ double2 sD[3][WG];

@@ -21,6 +21,7 @@
 #include <math.h>
 #include <stddef.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "../../include/ad.h"
@@ -47,11 +48,12 @@ size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 /* Offsets of the regions inside the scratch array for one system of N
  * spheres in the given launch shape. */
 struct StaticLayout {
-    size_t ctl, U0, dsys, sys_off, sys_P, sys_pbase, items, pA, pB, pC, pD, part, total;
+    size_t ctl, U0, dsys, sys_off, sys_P, sys_pbase, items, fitems, pA, pB, pC, pD, part, total;
     int nIB, P, nitems, ncomp;
+    int tw, nfitems; /* AD_FP64: targets per work-group of the pair sum and its work list */
 };
 
-StaticLayout static_layout(int prec, int rpy, int N, const ad::PairShape& sh) {
+StaticLayout static_layout(int prec, int rpy, int N, const ad::PairShape& sh, bool fp64_blocks) {
     StaticLayout L{};
     const int IB = sh.ipl * sh.wg / sh.wj;
     const int jc = sh.jchunk < N ? sh.jchunk : N;
@@ -74,6 +76,9 @@ StaticLayout static_layout(int prec, int rpy, int N, const ad::PairShape& sh) {
     L.sys_P = take(4);
     L.sys_pbase = take(8);
     L.items = take((size_t)L.nitems * sizeof(Item));
+    L.tw = ad::f64w_targets(N);
+    L.nfitems = prec == ad::PREC_FP64 && fp64_blocks ? (N + L.tw - 1) / L.tw : 0;
+    L.fitems = take((size_t)L.nfitems * sizeof(Item));
     L.pA = take(f32 ? n * 16 : 0);
     L.pB = take(f32 ? n * 16 : 0);
     L.pC = take(f32 ? n * 8 : 0);
@@ -83,10 +88,12 @@ StaticLayout static_layout(int prec, int rpy, int N, const ad::PairShape& sh) {
     return L;
 }
 
-/* The control block's flag, the one-system tables and the work list:
- * item q covers target block q % nIB against source chunk q / nIB. */
+/* The control block's flag, the one-system tables and the work lists:
+ * item q covers target block q % nIB against source chunk q / nIB; AD_FP64's
+ * pair sum item q covers targets [q tw, q tw + tw) against every source. */
 __global__ void k_static_tables(ad::Ctl* ctl, int* dsys, int* sys_off, int* sys_P, long long* sys_pbase,
-                                Item* items, int N, int IB, int jc, int nIB, int nitems) {
+                                Item* items, int N, int IB, int jc, int nIB, int nitems, Item* fitems, int tw,
+                                int nfitems) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g == 0) {
         ctl->flag = 0;
@@ -108,6 +115,18 @@ __global__ void k_static_tables(ad::Ctl* ctl, int* dsys, int* sys_off, int* sys_
         it.Nb = N;
         it.ioff = 0;
         items[g] = it;
+    }
+    if (g < nfitems) {
+        Item it;
+        it.sys = 0;
+        it.i0 = g * tw;
+        it.ni = min(tw, N - it.i0);
+        it.j0 = 0;
+        it.nj = N;
+        it.c = 0;
+        it.Nb = N;
+        it.ioff = 0;
+        fitems[g] = it;
     }
 }
 
@@ -151,7 +170,11 @@ extern "C" int ad_mobility_apply_static(const ad_params* p, int32_t N, const dou
                                                      : ad::PREC_FP64;
     const int rpy = p->tensor == AD_RPY ? 1 : 0;
     const ad::PairShape ps = ad::default_pair_shape(prec, 1, N);
-    const StaticLayout L = static_layout(prec, rpy, N, ps);
+    /* AD_FP64 sums in k_pairs_f64w over a list of target blocks; where that
+     * list does not fit beside the rest, in k_pairs_f64 with one source
+     * chunk (the same bits, slower) */
+    StaticLayout L = static_layout(prec, rpy, N, ps, true);
+    if (L.total > kScratchBytes && L.nfitems > 0) L = static_layout(prec, rpy, N, ps, false);
     if (L.total > kScratchBytes)
         return ad::thread_fail(AD_ENOMEM,
                                "N = %d needs %zu bytes of scratch, more than the %zu bytes the library holds per "
@@ -170,6 +193,8 @@ extern "C" int ad_mobility_apply_static(const ad_params* p, int32_t N, const dou
     d.sys_P = reinterpret_cast<const int*>(b + L.sys_P);
     d.sys_pbase = reinterpret_cast<const long long*>(b + L.sys_pbase);
     d.items = reinterpret_cast<const Item*>(b + L.items);
+    d.fitems = reinterpret_cast<const Item*>(b + L.fitems);
+    d.nfitems = L.nfitems;
     if (prec == ad::PREC_FP32C) {
         d.pA = reinterpret_cast<float4*>(b + L.pA);
         d.pB = reinterpret_cast<float4*>(b + L.pB);
@@ -206,11 +231,11 @@ extern "C" int ad_mobility_apply_static(const ad_params* p, int32_t N, const dou
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int IB = ps.ipl * ps.wg / ps.wj;
     const int jc = ps.jchunk < N ? ps.jchunk : N;
-    const int nthr = N > L.nitems ? N : L.nitems;
+    const int nthr = std::max(N, std::max(L.nitems, L.nfitems));
     hipLaunchKernelGGL(k_static_tables, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st, d.ctl,
                        const_cast<int*>(d.dsys), const_cast<int*>(d.sys_off), const_cast<int*>(d.sys_P),
                        const_cast<long long*>(d.sys_pbase), const_cast<Item*>(d.items), N, IB, jc, L.nIB,
-                       L.nitems);
+                       L.nitems, const_cast<Item*>(d.fitems), L.tw, L.nfitems);
     hipError_t err = hipGetLastError();
     if (err == hipSuccess) err = ad::launch_pack_apply(d, e.c, prec, X, F, st);
     if (err == hipSuccess) err = ad::launch_pairs(d, e, sh, 0, st);

@@ -24,9 +24,10 @@ def _with_context(sus, precision, tensor, X, F):
 def test_static_equals_context_apply(oracle, precision, tensor):
     import torch
     assert torch.cuda.is_available()
-    # ragged sizes: 3000 spans several 64- and 256-target blocks and source
-    # chunks with a partial last one; 150 is below the large-system shape
-    for S, side, seed in ((1500, 200.0, 31), (75, 40.0, 32)):
+    # ragged sizes: 4100 and 3000 span several 64- and 256-target blocks and
+    # source chunks with a partial last one (and, in AD_FP64, 4- and 2-target
+    # blocks); 150 is below the large-system shape
+    for S, side, seed in ((2050, 240.0, 33), (1500, 200.0, 31), (75, 40.0, 32)):
         sus = make_single(S, side, seed)
         rng = np.random.default_rng(seed)
         X = sus.X + rng.normal(scale=0.1, size=sus.X.shape)
@@ -48,6 +49,27 @@ def test_static_equals_context_apply(oracle, precision, tensor):
             assert np.array_equal(u, uo)
         else:
             assert relerr(u, uo) <= 1e-13
+
+
+def test_static_fp64_rpy_beyond_the_block_list():
+    """AD_FP64 with RPY at 129,000 spheres: the target-block list no longer
+    fits the scratch array beside the rest, so the call sums in the
+    one-chunk pair kernel instead; the same bits as the context's call."""
+    import torch
+    assert torch.cuda.is_available()
+    S = 64500
+    sus = make_single(S, 1600.0, 34, exclusion=False)
+    F = np.random.default_rng(35).standard_normal(sus.X.shape)
+    p = B.make_params(sus.params, "fp64", tensor="rpy")
+    Xd = torch.as_tensor(sus.X, device="cuda")
+    Fd = torch.as_tensor(F, device="cuda")
+    ud = torch.full_like(Xd, float("nan"))
+    B.ad_mobility_apply_static(p, Xd, Fd, ud)
+    torch.cuda.synchronize()
+    u = ud.cpu().numpy()
+    uc = _with_context(sus, "fp64", "rpy", sus.X, F)
+    assert np.isfinite(u).all()
+    assert np.array_equal(u, uc)
 
 
 def test_static_refuses_sizes_and_arguments():
