@@ -1226,8 +1226,17 @@ __global__ __launch_bounds__(256) void k_stage_wide(Dev d, Epi e) {
  * The partial sums are combined in k_stage_fused's order, through an LDS
  * area beside the slots, so one work-group barrier precedes the closing
  * update; wave 0 then does it alone (stage update, spring forces and pack,
- * in the rsqrt forms) with no further barrier. */
-template <int SPLIT, int RPY, int TI, int NW>
+ * in the rsqrt forms) with no further barrier.
+ * BAL: with one work-group per compute unit, the waves of a SIMD keep pace:
+ * a wave lowers its issue priority one step per quarter of its chunks, so
+ * the SIMD issues from the waves that are behind. Under the default oldest-
+ * first choice the first waves finish early and the last run with fewer
+ * waves to hide their latencies; kept in step, all four waves issue until
+ * the end (N = 4096: 7 % off the step). With two work-groups per compute
+ * unit the early finishers' closing update overlaps the other work-group's
+ * sums instead, and keeping pace was 6 % slower (N = 8192), as it was with
+ * fewer chunks per lane (1-3 % at N = 512 and 2048). */
+template <int SPLIT, int RPY, int TI, int NW, int BAL>
 __device__ __forceinline__ void stage_stream(const Dev& d, const Epi& e) {
     constexpr int G = 64 / TI;    /* lane groups (splits) per wave */
     constexpr int JS = NW * G;    /* source splits */
@@ -1351,6 +1360,13 @@ __device__ __forceinline__ void stage_stream(const Dev& d, const Epi& e) {
     float px = 0.f, py = 0.f, pz = 0.f;
     auto chunk = [&](int k, auto R) {
         constexpr int r = decltype(R)::value; /* = k & 1, the buffer and the set of chunk k */
+        if (BAL) {
+            const int lvl = (4 * k) / K;
+            if (lvl == 0) __builtin_amdgcn_s_setprio(3);
+            else if (lvl == 1) __builtin_amdgcn_s_setprio(2);
+            else if (lvl == 2) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
+        }
         if (k + 2 < K) fetch(k + 2, R);
         const int x0 = (w * 2 + r) * 64 + g * TI;
         const int j0 = sp * Q + k * TI;
@@ -1402,6 +1418,7 @@ __device__ __forceinline__ void stage_stream(const Dev& d, const Epi& e) {
     __syncthreads();
     /* wave 0 closes the stage alone */
     if (w != 0) return;
+    if (BAL) __builtin_amdgcn_s_setprio(3);
     int bad = 0;
     if (tid < 3 * ni) {
         const int tt = tid / 3, a = tid - 3 * tt;
@@ -1437,7 +1454,7 @@ __device__ __forceinline__ void stage_stream(const Dev& d, const Epi& e) {
 
 template <int SPLIT, int RPY, int TI, int NW>
 __global__ __launch_bounds__(64 * NW) void k_stage_stream(Dev d, Epi e) {
-    stage_stream<SPLIT, RPY, TI, NW>(d, e);
+    stage_stream<SPLIT, RPY, TI, NW, TI == 16 && NW == 16>(d, e);
 }
 
 /* The same with registers capped for 8 waves per SIMD (63 VGPRs), so that two
@@ -1446,7 +1463,7 @@ __global__ __launch_bounds__(64 * NW) void k_stage_stream(Dev d, Epi e) {
  * unit, N = 4096, the cap cost 5 %). */
 template <int SPLIT, int RPY, int TI, int NW>
 __global__ __launch_bounds__(64 * NW, 8) void k_stage_stream_x2(Dev d, Epi e) {
-    stage_stream<SPLIT, RPY, TI, NW>(d, e);
+    stage_stream<SPLIT, RPY, TI, NW, 0>(d, e);
 }
 
 /* FP64 streamed form of the fused stage (AD_FP64_TILED with
