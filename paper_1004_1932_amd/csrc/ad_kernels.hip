@@ -1590,6 +1590,16 @@ __global__ __launch_bounds__(1024) void k_stage_stream64(Dev d, Epi e) {
     };
     for (int k = 0; k < K; ++k) {
         const int buf = k & 1;
+        if (TI == 16) {
+            /* the waves of a SIMD keep pace, as in k_stage_stream's
+             * one-work-group-per-unit instance (one 16-wave work-group per
+             * compute unit fits at this kernel's register count) */
+            const int lvl = (4 * k) / K;
+            if (lvl == 0) __builtin_amdgcn_s_setprio(3);
+            else if (lvl == 1) __builtin_amdgcn_s_setprio(2);
+            else if (lvl == 2) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
+        }
         if (k + 1 < K) fetch(k + 1);
         const int x0 = (w * 2 + buf) * 64 + g * TI;
         const int j0 = sp * Q + k * TI;
@@ -1617,6 +1627,7 @@ __global__ __launch_bounds__(1024) void k_stage_stream64(Dev d, Epi e) {
     }
     __syncthreads();
     if (w != 0) return;
+    if (TI == 16) __builtin_amdgcn_s_setprio(3);
     int bad = 0;
     if (tid < 3 * ni) {
         const int tt = tid / 3, a = tid - 3 * tt;
