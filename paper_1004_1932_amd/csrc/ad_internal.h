@@ -263,10 +263,13 @@ __host__ __device__ inline int stream_targets(int Ntot) {
     while (ti < FT_I && 2 * 256 * ti <= Ntot) ti *= 2;
     return ti;
 }
-/* waves per work-group of the streamed fused stage with ti targets: 8 with
- * 4 targets (the small systems, whose few sources per lane make the
- * combination of 16 waves' sums a large share), else 16 */
-__host__ __device__ inline int stream_waves(int ti) { return ti == 4 ? 8 : 16; }
+/* waves per work-group of the streamed fused stage with ti targets: 16 with
+ * 16 targets, else 8. With 4 targets (the small systems) the few sources per
+ * lane make the combination of 16 waves' sums a large share; with 8 targets
+ * (2048 to 4095 spheres) an 8-wave work-group lets two share a compute unit
+ * when the launch has more than 256 (N = 3072: 42.1 against 49.0 us per
+ * step; N = 2048 equal) */
+__host__ __device__ inline int stream_waves(int ti) { return ti == 16 ? 16 : 8; }
 /* LDS bytes of a streamed fused work-group: nw waves x 2 slots x 64 source
  * entries, followed by the combination area (nw waves x ti targets x 6
  * floats, ti x 3 stage positions); at most 16 waves and 16 targets */

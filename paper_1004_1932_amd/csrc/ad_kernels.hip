@@ -2645,7 +2645,7 @@ static hipError_t go_stream(const Dev& d, const Epi& e, hipStream_t s, const Tim
     const int lds = fused_stream_lds_bytes(SPLIT, nw, ti);
     const dim3 grid(d.nfitems ? d.nfitems : (d.Ntot + ti - 1) / ti);
     auto kern = ti == 16 ? (grid.x > 256 ? k_stage_stream_x2<SPLIT, RPY, 16, 16> : k_stage_stream<SPLIT, RPY, 16, 16>)
-                : ti == 8 ? k_stage_stream<SPLIT, RPY, 8, 16> : k_stage_stream<SPLIT, RPY, 4, 8>;
+                : ti == 8 ? k_stage_stream<SPLIT, RPY, 8, 8> : k_stage_stream<SPLIT, RPY, 4, 8>;
     if (tm.start)
         hipExtLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, s, tm.start, tm.stop, 0, d, e);
     else
@@ -2702,10 +2702,10 @@ hipError_t prepare_fused() {
                              reinterpret_cast<const void*>(&k_stage_stream_x2<0, 1, 16, 16>),
                              reinterpret_cast<const void*>(&k_stage_stream_x2<1, 0, 16, 16>),
                              reinterpret_cast<const void*>(&k_stage_stream_x2<1, 1, 16, 16>),
-                             reinterpret_cast<const void*>(&k_stage_stream<0, 0, 8, 16>),
-                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 8, 16>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 8, 16>),
-                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 8, 16>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 0, 8, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<0, 1, 8, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 0, 8, 8>),
+                             reinterpret_cast<const void*>(&k_stage_stream<1, 1, 8, 8>),
                              reinterpret_cast<const void*>(&k_stage_stream<0, 0, 4, 8>),
                              reinterpret_cast<const void*>(&k_stage_stream<0, 1, 4, 8>),
                              reinterpret_cast<const void*>(&k_stage_stream<1, 0, 4, 8>),

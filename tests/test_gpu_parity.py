@@ -907,10 +907,12 @@ def test_streamed_fused_stage_matches_oracle(oracle, launch, integrator, tensor)
         check_fp32c(out["stream"] - sus.X, out["two"] - sus.X, "displacement vs two-kernel path")
 
 
-@pytest.mark.parametrize("S,posmode", [(2048, 2), (4100, 2), (4100, 1)])
+@pytest.mark.parametrize("S,posmode", [(1500, 2), (1500, 1), (2048, 2), (4100, 2), (4100, 1)])
 def test_streamed_fused_stage_large_systems(oracle, S, posmode):
     """Systems at and beyond the size where every source fits one
-    work-group's LDS (8200 spheres): two steps against the oracle."""
+    work-group's LDS (8200 spheres), and of 3000 spheres (8-target, 8-wave
+    work-groups, more than one per compute unit): two steps against the
+    oracle."""
     _torch()
     sus = make_single(S, 240.0 * (2 * S / 4096.0) ** (1.0 / 3.0), 53)
     say(f"streamed N = {2 * S}, posmode {posmode}")
